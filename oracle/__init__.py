@@ -1,0 +1,183 @@
+"""ctypes front-end of the plain FP64 CPU oracle (test infrastructure only).
+
+Only tests/, the smoke check and the CPU-baseline leg of bench.py may import
+this package.  The HIP product path never does.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+RK3, SSPRK43, SSPRK54 = 0, 1, 2
+STAGES = {RK3: 3, SSPRK43: 4, SSPRK54: 5}
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liborc.so")
+        if not os.path.exists(path):
+            from . import build as _b  # noqa: F401
+            _b.build()
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        dpp = ctypes.POINTER(dp)
+        L.orc_mp5.restype = ctypes.c_double
+        L.orc_mp5.argtypes = [dp, ctypes.c_double]
+        L.orc_mp5_grad.restype = ctypes.c_double
+        L.orc_mp5_grad.argtypes = [dp, ctypes.c_double, dp]
+        L.orc_prim.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
+        L.orc_flux.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp]
+        L.orc_fast_speed.restype = ctypes.c_double
+        L.orc_fast_speed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp]
+        L.orc_scheme_table.argtypes = [ctypes.c_int, dp, dp]
+        L.orc_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_int, ip, dp, ip, dpp, dpp, dp]
+        L.orc_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_int, ip, dp, ip, ctypes.c_int, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_int, dpp, dp]
+        L.orc_run_jvp.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int, ip, dp, ip, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_int, dpp, dpp]
+        L.orc_branch_hash_end.restype = ctypes.c_uint64
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        _LIB = L
+    return _LIB
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _ptrs(arrs: Sequence[np.ndarray]):
+    dp = ctypes.POINTER(ctypes.c_double)
+    P = (dp * len(arrs))()
+    for i, a in enumerate(arrs):
+        P[i] = _dp(a)
+    return P
+
+
+def _geom(bs):
+    n = np.ascontiguousarray(bs.n, np.int32)
+    dx = np.ascontiguousarray(bs.dx, np.float64)
+    nbr = np.ascontiguousarray(bs.nbr, np.int32)
+    return n, dx, nbr
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        raise OracleError(f"oracle {what} failed with status {st}")
+
+
+def mp5(f: Sequence[float], eps: float = 0.0) -> float:
+    a = np.ascontiguousarray(f, np.float64)
+    return lib().orc_mp5(_dp(a), eps)
+
+
+def mp5_grad(f: Sequence[float], eps: float = 0.0) -> Tuple[float, np.ndarray]:
+    a = np.ascontiguousarray(f, np.float64)
+    g = np.zeros(5)
+    v = lib().orc_mp5_grad(_dp(a), eps, _dp(g))
+    return v, g
+
+
+def prim(ndim: int, mhd: bool, gamma: float, u: Sequence[float]) -> Tuple[int, np.ndarray]:
+    a = np.zeros(8); a[:len(u)] = u
+    w = np.zeros(8)
+    st = lib().orc_prim(ndim, int(mhd), gamma, _dp(a), _dp(w))
+    return st, w
+
+
+def flux(ndim: int, mhd: bool, gamma: float, d: int, u: Sequence[float]) -> np.ndarray:
+    a = np.zeros(8); a[:len(u)] = u
+    f = np.zeros(8)
+    lib().orc_flux(ndim, int(mhd), gamma, d, _dp(a), _dp(f))
+    return f[:len(u)]
+
+
+def fast_speed(ndim: int, mhd: bool, gamma: float, d: int, u: Sequence[float]) -> float:
+    a = np.zeros(8); a[:len(u)] = u
+    return lib().orc_fast_speed(ndim, int(mhd), gamma, d, _dp(a))
+
+
+def scheme_table(scheme: int):
+    al = np.zeros(36); be = np.zeros(36)
+    s = lib().orc_scheme_table(scheme, _dp(al), _dp(be))
+    return s, al.reshape(6, 6)[:s + 1, :s], be.reshape(6, 6)[:s + 1, :s]
+
+
+def rhs(bs, eps: float = 0.0) -> Tuple[List[np.ndarray], np.ndarray]:
+    """L(U) for every block (padded arrays, ghost entries 0) and c_max[3]."""
+    n, dx, nbr = _geom(bs)
+    u = [np.ascontiguousarray(x, np.float64) for x in bs.u]
+    out = [np.zeros_like(x) for x in u]
+    cm = np.zeros(3)
+    st = lib().orc_rhs(bs.ndim, int(bs.mhd), bs.gamma, eps, bs.nb, _ip(n), _dp(dx), _ip(nbr),
+                       _ptrs(u), _ptrs(out), _dp(cm))
+    _check(st, "rhs")
+    return out, cm
+
+
+def run(bs, scheme: int, nsteps: int, cfl: float = 0.4, dt: Optional[float] = None,
+        eps: float = 0.0):
+    """nsteps steps; returns (new BlockSet, per-step dt array)."""
+    n, dx, nbr = _geom(bs)
+    out = bs.copy()
+    out.u = [np.ascontiguousarray(x, np.float64).copy() for x in bs.u]
+    dts = np.zeros(max(nsteps, 1))
+    st = lib().orc_run(bs.ndim, int(bs.mhd), bs.gamma, eps, bs.nb, _ip(n), _dp(dx), _ip(nbr),
+                       scheme, cfl, -1.0 if dt is None else float(dt), nsteps, _ptrs(out.u),
+                       _dp(dts))
+    _check(st, "run")
+    return out, dts[:nsteps]
+
+
+def run_jvp(bs, tangent: Sequence[np.ndarray], scheme: int, nsteps: int, dt: float,
+            eps: float = 0.0):
+    """Forward-mode JVP of U0 -> U_N at fixed dt; returns (U_N BlockSet, dU_N list)."""
+    n, dx, nbr = _geom(bs)
+    out = bs.copy()
+    out.u = [np.ascontiguousarray(x, np.float64).copy() for x in bs.u]
+    du = [np.ascontiguousarray(t, np.float64).copy() for t in tangent]
+    st = lib().orc_run_jvp(bs.ndim, int(bs.mhd), bs.gamma, eps, bs.nb, _ip(n), _dp(dx), _ip(nbr),
+                           scheme, float(dt), nsteps, _ptrs(out.u), _ptrs(du))
+    _check(st, "jvp")
+    return out, du
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
+
+
+def run_branch_hash(bs, scheme: int, nsteps: int, dt: float, eps: float = 0.0) -> int:
+    """Fingerprint of every branch decision of a forward run (single thread);
+    equal fingerprints at U0 +/- h dU certify a non-kinked difference quotient."""
+    nthreads = num_threads()
+    lib().orc_branch_hash_begin()
+    try:
+        run(bs, scheme, nsteps, dt=dt, eps=eps)
+    finally:
+        h = int(lib().orc_branch_hash_end())
+        set_threads(nthreads)
+    return h

@@ -1,0 +1,720 @@
+// Plain FP64 CPU oracle for the conservative finite-difference MP5 / global
+// Lax-Friedrichs / SSPRK scheme of Porth et al. (2014), "MPI-AMRVAC for Solar
+// and Astrophysics", Sect. 2.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+// CPU-baseline leg of the benchmark may load this library.  It shares no
+// source with the HIP path and the HIP path never calls it.
+//
+// It is written to be checked by eye against the paper, not to be fast:
+//   * scalar loops, no blocking, no fusion;
+//   * every stage evaluates the Shu-Osher sum literally from stored stages;
+//   * built with -O2 -ffp-contract=off (no FMA contraction, no fast-math).
+//
+// Templated on the scalar type: `double` for the forward map and `Dual`
+// (value + one tangent) for Jacobian-vector products of the whole time
+// integration.  Branches (MP5 limiter, minmod, median, global max) are taken
+// on the value part, so a JVP differentiates the branch taken at the forward
+// point.
+//
+// Readings of the paper where it is silent (each also listed in the design
+// notes of the repository):
+//   R1  c_max is the domain-global maximum over all interior cells of all
+//       blocks, per direction d, of |v_d| + c_{f,d}, evaluated on the state
+//       that L is applied to (Sect. 2.2 calls it the grid-global maximal
+//       characteristic velocity).
+//   R2  c_f is the textbook fast-magnetosonic speed along d (Sect. 4.4 names
+//       it without a formula); the hydro limit is the sound speed.
+//   R3  MP5 uses alpha = 4 and eps = 0 (Suresh & Huynh 1997, cited in
+//       Sect. 2.2).
+//   R4  dt = CFL / max_blocks sum_d c_max,d / dx_d  (Sect. 4.4 gives the 1D
+//       form dt < dx / c_w).
+//   R5  SSPRK(5,4) uses the printed table except alpha_50 := 1 - (alpha_52 +
+//       alpha_53 + alpha_54) so that each row sums to one.  RK3 is the
+//       Gottlieb-Shu scheme (cited, not printed, in Sect. 2.3).
+//   R6  d|v|/dv := 0 at v = 0 (the derivative a central difference sees).
+//       Ties: minmod / min / max take the first argument, the median takes
+//       f^L when it equals a bound, the global max keeps the lowest
+//       (block, cell) index.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace orc {
+
+// Fingerprint of every branch decision taken (MP5 branch, median choice,
+// c_max argmax), used by tests to certify that two nearby forward runs took
+// the same branches ("non-kinked") before comparing them with a difference
+// quotient.  Collected only when enabled (single-threaded runs).
+static bool g_hash_on = false;
+static uint64_t g_hash = 1469598103934665603ull;
+static inline void hash_mix(uint64_t x) {
+  if (!g_hash_on) return;
+  g_hash ^= x + 0x9e3779b97f4a7c15ull + (g_hash << 6) + (g_hash >> 2);
+}
+
+// ---------------------------------------------------------------------------
+// Forward-mode dual number: value v and one tangent d.
+// ---------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+  Dual() : v(0.0), d(0.0) {}
+  Dual(double x) : v(x), d(0.0) {}
+  Dual(double x, double dx) : v(x), d(dx) {}
+};
+static inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+static inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+static inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+static inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+static inline Dual operator/(Dual a, Dual b) {
+  double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+static inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+static inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+static inline Dual sqrt_(Dual a) {
+  double s = std::sqrt(a.v);
+  return Dual(s, s > 0.0 ? a.d / (2.0 * s) : 0.0);
+}
+static inline double sqrt_(double a) { return std::sqrt(a); }
+static inline double val(double a) { return a; }
+static inline double val(Dual a) { return a.v; }
+static inline bool finite_(double a) { return std::isfinite(a); }
+static inline bool finite_(Dual a) { return std::isfinite(a.v) && std::isfinite(a.d); }
+
+// |x| with derivative sign(x), and 0 at x == 0 (reading R6).
+static inline double absv(double x) { return std::fabs(x); }
+static inline Dual absv(Dual x) {
+  if (x.v > 0.0) return x;
+  if (x.v < 0.0) return -x;
+  return Dual(0.0, 0.0);
+}
+
+// min / max returning the first argument on ties.
+template <class T> static inline T min2(T a, T b) { return (val(b) < val(a)) ? b : a; }
+template <class T> static inline T max2(T a, T b) { return (val(b) > val(a)) ? b : a; }
+template <class T> static inline T min3(T a, T b, T c) { return min2(min2(a, b), c); }
+template <class T> static inline T max3(T a, T b, T c) { return max2(max2(a, b), c); }
+
+// ---------------------------------------------------------------------------
+// MP5 reconstruction (Suresh & Huynh 1997; selected in Sect. 2.2).
+// ---------------------------------------------------------------------------
+static const double MP5_ALPHA = 4.0;
+
+// minmod(x, y): 0 unless x and y share a strict sign, else the argument of
+// smaller magnitude (first argument on equal magnitudes).
+template <class T> static inline T minmod2(T x, T y) {
+  if (val(x) * val(y) <= 0.0) return T(0.0);
+  return (std::fabs(val(y)) < std::fabs(val(x))) ? y : x;
+}
+
+// minmod of four: sign * min |.| when all four share a strict sign, else 0.
+template <class T> static inline T minmod4(T w, T x, T y, T z) {
+  bool pos = val(w) > 0.0 && val(x) > 0.0 && val(y) > 0.0 && val(z) > 0.0;
+  bool neg = val(w) < 0.0 && val(x) < 0.0 && val(y) < 0.0 && val(z) < 0.0;
+  if (pos) return min2(min2(min2(w, x), y), z);
+  if (neg) return max2(max2(max2(w, x), y), z);
+  return T(0.0);
+}
+
+// Median of three; x is returned when it equals one of the bounds.
+template <class T> static inline T median3(T x, T lo, T hi) {
+  // lo <= hi holds for the MP5 bounds (both bracket the centre value).
+  if (val(x) < val(lo)) return lo;
+  if (val(x) > val(hi)) return hi;
+  return x;
+}
+
+// Interface value at j+1/2 from the five values f_{j-2}..f_{j+2}, biased to
+// the left (upwind for a positive-speed flux F^+).
+template <class T> static T mp5(T a, T b, T c, T d, T e, double eps) {
+  // fifth-order linear interface value
+  T fL = (T(2.0) * a - T(13.0) * b + T(47.0) * c + T(27.0) * d - T(3.0) * e) / T(60.0);
+  // monotonicity-preserving bound
+  T fMP = c + minmod2(d - c, T(MP5_ALPHA) * (c - b));
+  if (val((fL - c) * (fL - fMP)) <= eps) {   // linear piece 1: fL
+    bool flat = val(a) == val(c) && val(b) == val(c) && val(d) == val(c) && val(e) == val(c);
+    hash_mix(flat ? 0 : 1);
+    return fL;
+  }
+  // curvatures at j-1, j, j+1
+  T dm = a - T(2.0) * b + c;
+  T d0 = b - T(2.0) * c + d;
+  T dp = c - T(2.0) * d + e;
+  T dM4p = minmod4(T(4.0) * d0 - dp, T(4.0) * dp - d0, d0, dp);   // at j+1/2
+  T dM4m = minmod4(T(4.0) * d0 - dm, T(4.0) * dm - d0, d0, dm);   // at j-1/2
+  T fUL = c + T(MP5_ALPHA) * (c - b);
+  T fAV = T(0.5) * (c + d);
+  T fMD = fAV - T(0.5) * dM4p;
+  T fLC = c + T(0.5) * (c - b) + T(4.0 / 3.0) * dM4m;
+  T fmin = max2(min3(c, d, fMD), min3(c, fUL, fLC));
+  T fmax = min2(max3(c, d, fMD), max3(c, fUL, fLC));
+  T r = median3(fL, fmin, fmax);
+  if (g_hash_on) {
+    // identify the linear piece returned: fL, or the candidate that set the
+    // active bound (with the minmod4 choice behind fMD / fLC).  An exactly
+    // flat stencil gets a code of its own: every piece returns the same
+    // value there and the same derivative along directions that keep it
+    // flat, while rounding of fL decides which piece is reported.
+    uint64_t code = 1;
+    bool flat = val(a) == val(c) && val(b) == val(c) && val(d) == val(c) && val(e) == val(c);
+    if (flat) {
+      code = 0;
+    } else if (val(r) != val(fL)) {
+      auto which = [&](T x) -> uint64_t {
+        if (val(x) == val(c)) return 2;
+        if (val(x) == val(d)) return 3;
+        if (val(x) == val(fUL)) return 4;
+        auto m4 = [](T m, T w, T x1, T y, T z) -> uint64_t {
+          return val(m) == 0.0 ? 0 : val(m) == val(w) ? 1 : val(m) == val(x1) ? 2 : val(m) == val(y) ? 3 : 4;
+        };
+        if (val(x) == val(fMD)) return 8 + m4(dM4p, T(4.0) * d0 - dp, T(4.0) * dp - d0, d0, dp);
+        return 16 + m4(dM4m, T(4.0) * d0 - dm, T(4.0) * dm - d0, d0, dm);
+      };
+      code = (val(r) == val(fmin) ? 32 : 64) + which(r);
+    }
+    hash_mix(code);
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Physics (Sect. 3 hydro with an ideal-gas energy equation; Sect. 4.1 and 4.3
+// ideal MHD with B0 = 0, eta = eta_h = 0, no psi).  Units with magnetic
+// pressure B^2/2.
+// Variable order: hydro (rho, m_1..m_ndim, E); MHD (rho, m_x, m_y, m_z, E,
+// B_x, B_y, B_z).
+// ---------------------------------------------------------------------------
+struct Phys {
+  int ndim;
+  int mhd;
+  double gamma;
+  int nvar() const { return mhd ? 8 : 2 + ndim; }
+  int ncomp() const { return mhd ? 3 : ndim; }   // momentum components
+  int iE() const { return 1 + ncomp(); }
+};
+
+// Primitive state: rho, v[0..2], p, B[0..2]; returns false if non-physical.
+template <class T> struct Prim {
+  T rho, v[3], p, B[3];
+};
+
+template <class T>
+static bool cons_to_prim(const Phys& ph, const T* u, Prim<T>& w) {
+  const int nc = ph.ncomp();
+  w.rho = u[0];
+  for (int k = 0; k < 3; ++k) { w.v[k] = T(0.0); w.B[k] = T(0.0); }
+  for (int k = 0; k < nc; ++k) w.v[k] = u[1 + k] / w.rho;
+  T kin(0.0);                                   // m.v
+  for (int k = 0; k < nc; ++k) kin += u[1 + k] * w.v[k];
+  T E = u[ph.iE()];
+  T eint = E - T(0.5) * kin;
+  if (ph.mhd) {
+    T b2(0.0);
+    for (int k = 0; k < 3; ++k) { w.B[k] = u[5 + k]; b2 += w.B[k] * w.B[k]; }
+    eint = eint - T(0.5) * b2;
+  }
+  w.p = T(ph.gamma - 1.0) * eint;
+  bool ok = finite_(w.rho) && finite_(w.p) && val(w.rho) > 0.0 && val(w.p) > 0.0;
+  for (int k = 0; k < nc; ++k) ok = ok && finite_(u[1 + k]);
+  return ok;
+}
+
+// Physical flux along direction d.
+template <class T>
+static void phys_flux(const Phys& ph, int d, const T* u, const Prim<T>& w, T* f) {
+  const int nc = ph.ncomp();
+  const T vd = w.v[d];
+  f[0] = u[1 + d];                                           // m_d
+  if (!ph.mhd) {
+    for (int k = 0; k < nc; ++k) f[1 + k] = u[1 + k] * vd;   // m_k v_d
+    f[1 + d] = f[1 + d] + w.p;                               // + p delta_kd
+    f[ph.iE()] = vd * (u[ph.iE()] + w.p);                    // v_d (E + p)
+    return;
+  }
+  T b2 = w.B[0] * w.B[0] + w.B[1] * w.B[1] + w.B[2] * w.B[2];
+  T ptot = w.p + T(0.5) * b2;
+  T Bd = w.B[d];
+  T bv = w.B[0] * w.v[0] + w.B[1] * w.v[1] + w.B[2] * w.v[2];
+  for (int k = 0; k < 3; ++k) f[1 + k] = u[1 + k] * vd - Bd * w.B[k];
+  f[1 + d] = f[1 + d] + ptot;
+  f[4] = vd * (u[4] + ptot) - Bd * bv;
+  for (int k = 0; k < 3; ++k) f[5 + k] = vd * w.B[k] - Bd * w.v[k];
+}
+
+// Fast speed along d (sound speed for hydro).
+template <class T>
+static T fast_speed(const Phys& ph, int d, const Prim<T>& w) {
+  T a2 = T(ph.gamma) * w.p / w.rho;
+  if (!ph.mhd) return sqrt_(a2);
+  T b2 = (w.B[0] * w.B[0] + w.B[1] * w.B[1] + w.B[2] * w.B[2]) / w.rho;
+  T bd2 = w.B[d] * w.B[d] / w.rho;
+  T s = a2 + b2;
+  T disc = s * s - T(4.0) * a2 * bd2;
+  if (val(disc) < 0.0) disc = T(0.0);   // rounding guard; >= 0 analytically
+  T cf2 = T(0.5) * (s + sqrt_(disc));
+  return sqrt_(cf2);
+}
+
+// ---------------------------------------------------------------------------
+// SSPRK tables in Shu-Osher form (Sect. 2.3).
+// ---------------------------------------------------------------------------
+struct Scheme {
+  int s;
+  double alpha[6][6];
+  double beta[6][6];
+};
+
+static Scheme make_scheme(int id) {
+  Scheme S;
+  std::memset(&S, 0, sizeof(S));
+  if (id == 0) {            // RK3, Gottlieb & Shu (1998)
+    S.s = 3;
+    S.alpha[1][0] = 1.0;       S.beta[1][0] = 1.0;
+    S.alpha[2][0] = 0.75;      S.alpha[2][1] = 0.25; S.beta[2][1] = 0.25;
+    S.alpha[3][0] = 1.0 / 3.0; S.alpha[3][2] = 2.0 / 3.0; S.beta[3][2] = 2.0 / 3.0;
+  } else if (id == 1) {     // SSPRK(4,3), Sect. 2.3.1
+    S.s = 4;
+    S.alpha[1][0] = 1.0;       S.beta[1][0] = 0.5;
+    S.alpha[2][1] = 1.0;       S.beta[2][1] = 0.5;
+    S.alpha[3][0] = 2.0 / 3.0; S.alpha[3][2] = 1.0 / 3.0; S.beta[3][2] = 1.0 / 6.0;
+    S.alpha[4][3] = 1.0;       S.beta[4][3] = 0.5;
+  } else {                  // SSPRK(5,4), Sect. 2.3.2 (printed digits)
+    S.s = 5;
+    S.alpha[1][0] = 1.0;
+    S.alpha[2][0] = 0.44437049406734; S.alpha[2][1] = 0.55562950593266;
+    S.alpha[3][0] = 0.62010185138540; S.alpha[3][2] = 0.37989814861460;
+    S.alpha[4][0] = 0.17807995410773; S.alpha[4][3] = 0.82192004589227;
+    S.alpha[5][2] = 0.51723167208978; S.alpha[5][3] = 0.12759831133288;
+    S.alpha[5][4] = 0.34833675773694;
+    // reading R5: the row sum is restored to one through alpha_50
+    S.alpha[5][0] = 1.0 - (S.alpha[5][2] + S.alpha[5][3] + S.alpha[5][4]);
+    S.beta[1][0] = 0.39175222700392;
+    S.beta[2][1] = 0.36841059262959;
+    S.beta[3][2] = 0.25189177424738;
+    S.beta[4][3] = 0.54497475021237;
+    S.beta[5][3] = 0.08460416338212;
+    S.beta[5][4] = 0.22600748319395;
+  }
+  return S;
+}
+
+// ---------------------------------------------------------------------------
+// Blocks: cell-centred point values with 3 ghost layers in every active
+// direction; storage var-major, x fastest (the layout of the public API).
+// ---------------------------------------------------------------------------
+static const int NG = 3;
+
+struct Geom {
+  int n[3];        // interior cells (1 for inactive directions)
+  int P[3];        // padded extent
+  int G[3];        // ghost depth (3 or 0)
+  double dx[3];
+  int nbr[6];
+  size_t ncell;    // padded cells per variable
+  size_t idx(int i, int j, int k) const {
+    return ((size_t)(k + G[2]) * P[1] + (size_t)(j + G[1])) * P[0] + (size_t)(i + G[0]);
+  }
+};
+
+struct Grid {
+  Phys ph;
+  std::vector<Geom> g;
+};
+
+template <class T> using State = std::vector<std::vector<T>>;   // [block][var*ncell + idx]
+
+enum { ORC_OK = 0, ORC_ERR_INVALID = 1, ORC_ERR_NONPHYSICAL = 4 };
+
+static int build_grid(Grid& G, int ndim, int mhd, double gamma, int nb, const int* n,
+                      const double* dx, const int* nbr) {
+  if (ndim < 1 || ndim > 3 || nb <= 0) return ORC_ERR_INVALID;
+  G.ph.ndim = ndim; G.ph.mhd = mhd; G.ph.gamma = gamma;
+  G.g.resize(nb);
+  for (int b = 0; b < nb; ++b) {
+    Geom& q = G.g[b];
+    for (int d = 0; d < 3; ++d) {
+      bool act = d < ndim;
+      q.n[d] = act ? n[3 * b + d] : 1;
+      if (act && q.n[d] < NG) return ORC_ERR_INVALID;
+      q.G[d] = act ? NG : 0;
+      q.P[d] = q.n[d] + 2 * q.G[d];
+      q.dx[d] = dx[3 * b + d];
+    }
+    for (int f = 0; f < 6; ++f) q.nbr[f] = (f < 2 * ndim) ? nbr[6 * b + f] : -1;
+    q.ncell = (size_t)q.P[0] * q.P[1] * q.P[2];
+  }
+  return ORC_OK;
+}
+
+// Copy the 3 face layers of every periodic (nbr >= 0) face from the
+// neighbour's interior; fixed faces (nbr < 0) keep their values.  Edges and
+// corners are never read by the dimension-by-dimension operator.
+template <class T>
+static void fill_ghosts(const Grid& G, State<T>& U) {
+  const int nv = G.ph.nvar();
+  for (size_t b = 0; b < G.g.size(); ++b) {
+    const Geom& q = G.g[b];
+    for (int d = 0; d < G.ph.ndim; ++d) {
+      for (int side = 0; side < 2; ++side) {
+        int nb = q.nbr[2 * d + side];
+        if (nb < 0) continue;
+        const Geom& r = G.g[nb];
+        for (int layer = 1; layer <= NG; ++layer) {
+          int dst = side == 0 ? -layer : q.n[d] - 1 + layer;       // ghost index along d
+          int src = side == 0 ? r.n[d] - layer : layer - 1;        // neighbour interior
+          int lo[3] = {0, 0, 0}, hi[3] = {q.n[0], q.n[1], q.n[2]};
+          lo[d] = 0; hi[d] = 1;
+          for (int k = lo[2]; k < hi[2]; ++k)
+            for (int j = lo[1]; j < hi[1]; ++j)
+              for (int i = lo[0]; i < hi[0]; ++i) {
+                int cd[3] = {i, j, k}, cs[3] = {i, j, k};
+                cd[d] = dst; cs[d] = src;
+                for (int v = 0; v < nv; ++v)
+                  U[b][v * q.ncell + q.idx(cd[0], cd[1], cd[2])] =
+                      U[nb][v * r.ncell + r.idx(cs[0], cs[1], cs[2])];
+              }
+        }
+      }
+    }
+  }
+}
+
+// Domain-global per-direction maximum of |v_d| + c_{f,d} over interior
+// cells (reading R1).  Ties keep the first (lowest block, lowest cell).
+template <class T>
+static int global_cmax(const Grid& G, const State<T>& U, T cmax[3]) {
+  const int nv = G.ph.nvar();
+  for (int d = 0; d < 3; ++d) cmax[d] = T(0.0);
+  uint64_t arg[3] = {0, 0, 0};
+  bool first = true;
+  for (size_t b = 0; b < G.g.size(); ++b) {
+    const Geom& q = G.g[b];
+    for (int k = 0; k < q.n[2]; ++k)
+      for (int j = 0; j < q.n[1]; ++j)
+        for (int i = 0; i < q.n[0]; ++i) {
+          T u[8];
+          size_t c = q.idx(i, j, k);
+          for (int v = 0; v < nv; ++v) u[v] = U[b][v * q.ncell + c];
+          Prim<T> w;
+          if (!cons_to_prim(G.ph, u, w)) return ORC_ERR_NONPHYSICAL;
+          for (int d = 0; d < G.ph.ndim; ++d) {
+            T s = absv(w.v[d]) + fast_speed(G.ph, d, w);
+            if (first || val(s) > val(cmax[d])) { cmax[d] = s; arg[d] = ((uint64_t)b << 32) | c; }
+          }
+          first = false;
+        }
+  }
+  for (int d = 0; d < G.ph.ndim; ++d) hash_mix(arg[d] * 3 + d);
+  return ORC_OK;
+}
+
+// Right-hand side L(U) = - sum_d (Fhat_{i+1/2} - Fhat_{i-1/2}) / dx_d on the
+// interior of every block (Sect. 2.1, eqs. fdcons and timeoperator, S = 0),
+// with Fhat from the global Lax-Friedrichs split and MP5 (Sect. 2.2).
+// Ghost layers of U must be filled.  L has the padded layout; its ghost
+// entries are left at zero.
+template <class T>
+static int rhs(const Grid& G, const State<T>& U, const T cmax[3], State<T>& L, double eps) {
+  const int nv = G.ph.nvar();
+  const int nb = (int)G.g.size();
+  int status = ORC_OK;
+#pragma omp parallel for schedule(dynamic)
+  for (int b = 0; b < nb; ++b) {
+    const Geom& q = G.g[b];
+    std::fill(L[b].begin(), L[b].end(), T(0.0));
+    for (int d = 0; d < G.ph.ndim; ++d) {
+      const int nd = q.n[d];
+      const int len = nd + 2 * NG;
+      std::vector<T> Fp(nv * len), Fm(nv * len), Fh(nv * (nd + 1));
+      int lo[3] = {0, 0, 0}, hi[3] = {q.n[0], q.n[1], q.n[2]};
+      hi[d] = 1;
+      for (int k = lo[2]; k < hi[2]; ++k)
+        for (int j = lo[1]; j < hi[1]; ++j)
+          for (int i = lo[0]; i < hi[0]; ++i) {
+            // split fluxes along the pencil, cells -3 .. nd+2
+            for (int m = -NG; m < nd + NG; ++m) {
+              int c3[3] = {i, j, k};
+              c3[d] = m;
+              size_t c = q.idx(c3[0], c3[1], c3[2]);
+              T u[8], f[8];
+              for (int v = 0; v < nv; ++v) u[v] = U[b][v * q.ncell + c];
+              Prim<T> w;
+              if (!cons_to_prim(G.ph, u, w)) {
+#pragma omp atomic write
+                status = ORC_ERR_NONPHYSICAL;
+              }
+              phys_flux(G.ph, d, u, w, f);
+              for (int v = 0; v < nv; ++v) {
+                Fp[v * len + (m + NG)] = T(0.5) * (f[v] + cmax[d] * u[v]);
+                Fm[v * len + (m + NG)] = T(0.5) * (f[v] - cmax[d] * u[v]);
+              }
+            }
+            // interface fluxes at i+1/2 for i = -1 .. nd-1
+            for (int v = 0; v < nv; ++v) {
+              const T* p = &Fp[v * len + NG];
+              const T* mneg = &Fm[v * len + NG];
+              for (int s = -1; s < nd; ++s) {
+                T plus = mp5(p[s - 2], p[s - 1], p[s], p[s + 1], p[s + 2], eps);
+                T minus = mp5(mneg[s + 3], mneg[s + 2], mneg[s + 1], mneg[s], mneg[s - 1], eps);
+                Fh[v * (nd + 1) + (s + 1)] = plus + minus;
+              }
+            }
+            // conservative difference
+            for (int s = 0; s < nd; ++s) {
+              int c3[3] = {i, j, k};
+              c3[d] = s;
+              size_t c = q.idx(c3[0], c3[1], c3[2]);
+              for (int v = 0; v < nv; ++v) {
+                T diff = Fh[v * (nd + 1) + (s + 1)] - Fh[v * (nd + 1) + s];
+                L[b][v * q.ncell + c] -= diff / T(q.dx[d]);
+              }
+            }
+          }
+    }
+  }
+  return status;
+}
+
+template <class T>
+static void alloc_state(const Grid& G, State<T>& S) {
+  S.resize(G.g.size());
+  for (size_t b = 0; b < G.g.size(); ++b) S[b].assign(G.ph.nvar() * G.g[b].ncell, T(0.0));
+}
+
+static double dt_rule(const Grid& G, const double cmax[3], double cfl) {
+  double worst = 0.0;
+  for (const Geom& q : G.g) {
+    double s = 0.0;
+    for (int d = 0; d < G.ph.ndim; ++d) s += cmax[d] / q.dx[d];
+    worst = std::max(worst, s);
+  }
+  return cfl / worst;
+}
+
+// One SSPRK step in literal Shu-Osher form:
+//   U(0) = U^n,  U(i) = sum_{k<i} alpha_ik U(k) + dt beta_ik L(U(k)),
+//   U^{n+1} = U(s)      (Sect. 2.3).
+// dt < 0 selects the CFL rule R4 evaluated on U^n; the dt used is returned.
+template <class T>
+static int ssprk_step(const Grid& G, const Scheme& S, State<T>& U, double cfl, double dt_in,
+                      double eps, double* dt_used) {
+  const int nv = G.ph.nvar();
+  std::vector<State<T>> Us(S.s + 1), Ls(S.s);
+  Us[0] = U;
+  double dt = dt_in;
+  for (int i = 1; i <= S.s; ++i) {
+    // L(U(i-1)) is the only new right-hand side this stage needs.
+    int k = i - 1;
+    fill_ghosts(G, Us[k]);
+    T cm[3];
+    int st = global_cmax(G, Us[k], cm);
+    if (st) return st;
+    if (k == 0 && dt_in < 0.0) {
+      double cv[3] = {val(cm[0]), val(cm[1]), val(cm[2])};
+      dt = dt_rule(G, cv, cfl);
+    }
+    alloc_state(G, Ls[k]);
+    st = rhs(G, Us[k], cm, Ls[k], eps);
+    if (st) return st;
+    Us[i] = Us[0];   // ghost layers: fixed faces keep U^n's values
+    for (size_t b = 0; b < G.g.size(); ++b) {
+      const Geom& q = G.g[b];
+      for (int kk = 0; kk < q.n[2]; ++kk)
+        for (int j = 0; j < q.n[1]; ++j)
+          for (int ii = 0; ii < q.n[0]; ++ii) {
+            size_t c = q.idx(ii, j, kk);
+            for (int v = 0; v < nv; ++v) {
+              size_t o = v * q.ncell + c;
+              T acc(0.0);
+              for (int m = 0; m < i; ++m) {
+                if (S.alpha[i][m] != 0.0) acc += T(S.alpha[i][m]) * Us[m][b][o];
+                if (S.beta[i][m] != 0.0) acc += T(dt * S.beta[i][m]) * Ls[m][b][o];
+              }
+              Us[i][b][o] = acc;
+            }
+          }
+    }
+  }
+  U = Us[S.s];
+  if (dt_used) *dt_used = dt;
+  return ORC_OK;
+}
+
+template <class T>
+static void load_state(const Grid& G, State<T>& U, const double* const* u) {
+  alloc_state(G, U);
+  for (size_t b = 0; b < G.g.size(); ++b)
+    for (size_t o = 0; o < U[b].size(); ++o) U[b][o] = T(u[b][o]);
+}
+
+}  // namespace orc
+
+using namespace orc;
+
+extern "C" {
+
+int orc_nvar(int ndim, int mhd) {
+  Phys p; p.ndim = ndim; p.mhd = mhd; p.gamma = 1.4;
+  return p.nvar();
+}
+
+// MP5 left-biased interface value from f[0..4] = f_{j-2}..f_{j+2}.
+double orc_mp5(const double* f, double eps) { return mp5<double>(f[0], f[1], f[2], f[3], f[4], eps); }
+
+// MP5 and its five partial derivatives (dual numbers, one per input).
+double orc_mp5_grad(const double* f, double eps, double* grad) {
+  double out = 0.0;
+  for (int s = 0; s < 5; ++s) {
+    Dual x[5];
+    for (int t = 0; t < 5; ++t) x[t] = Dual(f[t], t == s ? 1.0 : 0.0);
+    Dual r = mp5<Dual>(x[0], x[1], x[2], x[3], x[4], eps);
+    grad[s] = r.d;
+    out = r.v;
+  }
+  return out;
+}
+
+// Primitive variables (rho, vx, vy, vz, p, Bx, By, Bz) of one cell.
+int orc_prim(int ndim, int mhd, double gamma, const double* u, double* w8) {
+  Phys ph; ph.ndim = ndim; ph.mhd = mhd; ph.gamma = gamma;
+  Prim<double> w;
+  bool ok = cons_to_prim(ph, u, w);
+  w8[0] = w.rho; w8[1] = w.v[0]; w8[2] = w.v[1]; w8[3] = w.v[2]; w8[4] = w.p;
+  w8[5] = w.B[0]; w8[6] = w.B[1]; w8[7] = w.B[2];
+  return ok ? ORC_OK : ORC_ERR_NONPHYSICAL;
+}
+
+int orc_flux(int ndim, int mhd, double gamma, int d, const double* u, double* f) {
+  Phys ph; ph.ndim = ndim; ph.mhd = mhd; ph.gamma = gamma;
+  Prim<double> w;
+  bool ok = cons_to_prim(ph, u, w);
+  phys_flux(ph, d, u, w, f);
+  return ok ? ORC_OK : ORC_ERR_NONPHYSICAL;
+}
+
+double orc_fast_speed(int ndim, int mhd, double gamma, int d, const double* u) {
+  Phys ph; ph.ndim = ndim; ph.mhd = mhd; ph.gamma = gamma;
+  Prim<double> w;
+  cons_to_prim(ph, u, w);
+  return fast_speed(ph, d, w);
+}
+
+// Shu-Osher table: alpha, beta are 6x6 row-major (row i = stage i).
+int orc_scheme_table(int scheme, double* alpha, double* beta) {
+  Scheme S = make_scheme(scheme);
+  for (int i = 0; i < 6; ++i)
+    for (int k = 0; k < 6; ++k) { alpha[6 * i + k] = S.alpha[i][k]; beta[6 * i + k] = S.beta[i][k]; }
+  return S.s;
+}
+
+// L(U) on every block.  u: padded input blocks (periodic ghosts are filled
+// from neighbours internally; fixed ghosts are read as given).  rhs:
+// padded output blocks (ghost entries set to 0).  cmax: out, per direction.
+int orc_rhs(int ndim, int mhd, double gamma, double eps, int nb, const int* n, const double* dx,
+            const int* nbr, const double* const* u, double* const* rhs_out, double* cmax) {
+  Grid G;
+  int st = build_grid(G, ndim, mhd, gamma, nb, n, dx, nbr);
+  if (st) return st;
+  State<double> U, L;
+  load_state(G, U, u);
+  alloc_state(G, L);
+  fill_ghosts(G, U);
+  double cm[3];
+  st = global_cmax(G, U, cm);
+  if (st) return st;
+  st = rhs(G, U, cm, L, eps);
+  if (st) return st;
+  for (int b = 0; b < nb; ++b) std::memcpy(rhs_out[b], L[b].data(), L[b].size() * sizeof(double));
+  for (int d = 0; d < 3; ++d) cmax[d] = cm[d];
+  return ORC_OK;
+}
+
+// nsteps SSPRK steps.  dt_fixed <= 0 selects the CFL rule.  u: in/out
+// padded blocks (interiors updated; ghosts on output are those of the last
+// stage: periodic ones refreshed, fixed ones unchanged).  dts: optional
+// array of nsteps used time steps.
+int orc_run(int ndim, int mhd, double gamma, double eps, int nb, const int* n, const double* dx,
+            const int* nbr, int scheme, double cfl, double dt_fixed, int nsteps,
+            double* const* u, double* dts) {
+  Grid G;
+  int st = build_grid(G, ndim, mhd, gamma, nb, n, dx, nbr);
+  if (st) return st;
+  if (scheme < 0 || scheme > 2) return ORC_ERR_INVALID;
+  Scheme S = make_scheme(scheme);
+  State<double> U;
+  load_state(G, U, u);
+  for (int it = 0; it < nsteps; ++it) {
+    double dtu = 0.0;
+    st = ssprk_step(G, S, U, cfl, dt_fixed > 0.0 ? dt_fixed : -1.0, eps, &dtu);
+    if (st) return st;
+    if (dts) dts[it] = dtu;
+  }
+  fill_ghosts(G, U);
+  for (int b = 0; b < nb; ++b) std::memcpy(u[b], U[b].data(), U[b].size() * sizeof(double));
+  return ORC_OK;
+}
+
+// Jacobian-vector product of the map U_0 -> U_N (N = nsteps, fixed dt):
+// u in/out (value), du in/out (tangent).  Forward-mode dual numbers through
+// every stage, including the global c_max (derivative of the maximising
+// cell).
+int orc_run_jvp(int ndim, int mhd, double gamma, double eps, int nb, const int* n,
+                const double* dx, const int* nbr, int scheme, double dt, int nsteps,
+                double* const* u, double* const* du) {
+  Grid G;
+  int st = build_grid(G, ndim, mhd, gamma, nb, n, dx, nbr);
+  if (st) return st;
+  if (scheme < 0 || scheme > 2 || !(dt > 0.0)) return ORC_ERR_INVALID;
+  Scheme S = make_scheme(scheme);
+  State<Dual> U;
+  alloc_state(G, U);
+  for (int b = 0; b < nb; ++b)
+    for (size_t o = 0; o < U[b].size(); ++o) U[b][o] = Dual(u[b][o], du[b][o]);
+  for (int it = 0; it < nsteps; ++it) {
+    st = ssprk_step(G, S, U, 0.0, dt, eps, nullptr);
+    if (st) return st;
+  }
+  fill_ghosts(G, U);
+  for (int b = 0; b < nb; ++b)
+    for (size_t o = 0; o < U[b].size(); ++o) { u[b][o] = U[b][o].v; du[b][o] = U[b][o].d; }
+  return ORC_OK;
+}
+
+// Branch fingerprint: orc_branch_hash_begin() enables collection (and
+// forces one thread), orc_branch_hash_end() returns the fingerprint.
+void orc_branch_hash_begin(void) {
+  g_hash_on = true;
+  g_hash = 1469598103934665603ull;
+#ifdef _OPENMP
+  omp_set_num_threads(1);
+#endif
+}
+
+uint64_t orc_branch_hash_end(void) {
+  g_hash_on = false;
+  return g_hash;
+}
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+}  // extern "C"
