@@ -1,0 +1,187 @@
+/*
+ * amrvac.h -- C ABI of the MI355X (gfx950) FP64 hot path of the conservative
+ * high-order finite-difference scheme of Porth et al. (2014), "MPI-AMRVAC for
+ * Solar and Astrophysics", Sect. 2:
+ *
+ *   dU/dt = L(U) = - sum_d (Fhat_{d,i+1/2} - Fhat_{d,i-1/2}) / dx_d
+ *     (Sect. 2.1, eqs. fdcons, reconstruct, timeoperator; no source terms),
+ *   Fhat = R_[L](F^+) + R_[R](F^-),  F^+- = (F +- c_max U) / 2
+ *     (Sect. 2.2, global Lax-Friedrichs flux-vector splitting),
+ *   R = MP5 (Suresh & Huynh 1997, selected in Sect. 2.2),
+ *   U^(i) = sum_k alpha_ik U^(k) + dt beta_ik L(U^(k))
+ *     (Sect. 2.3, Shu-Osher form; RK3, SSPRK(4,3), SSPRK(5,4)),
+ *
+ * for ideal hydrodynamics (Sect. 3, ideal-gas energy equation) and ideal MHD
+ * (Sects. 4.1 and 4.3 with B0 = 0, eta = eta_h = 0).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * All floating point is IEEE binary64.
+ *  * A "block" is a Cartesian box of n[0] x n[1] x n[2] interior cells
+ *    (n[d] = 1 for d >= ndim) stored with AMRVAC_NGHOST = 3 ghost layers on
+ *    both sides of every active direction: nvar arrays of
+ *    P0 * P1 * P2 doubles (P_d = n[d] + 6 if d < ndim, else 1), variable
+ *    major, x fastest.  Variables: hydro (rho, m_1..m_ndim, E), nvar =
+ *    2 + ndim; MHD (rho, m_x, m_y, m_z, E, B_x, B_y, B_z), nvar = 8.  Values
+ *    are point values at cell centres (Sect. 2.1).
+ *  * Faces: nbr[2d] (low side) and nbr[2d+1] (high side) of direction d are
+ *    either the index of the neighbouring block in the list (its interior
+ *    supplies the 3 ghost layers; periodic wrap is expressed by the caller
+ *    through these indices) or -1, meaning the ghost layers of this block
+ *    hold caller-filled boundary values that stay constant in time.  Only
+ *    face ghosts are read (the operator is a sum of 1D stencils); edge and
+ *    corner ghosts are never read.  Periodic ghost layers are neither read
+ *    nor written.
+ *  * c_max (Sect. 2.2) is the maximum over all interior cells of all blocks
+ *    of |v_d| + c_f,d, per direction d, of the state L is applied to (c_f:
+ *    fast magnetosonic speed along d; the sound speed for hydro).
+ *  * Device pointers are HIP device addresses; the caller owns them.  Every
+ *    call is stream-ordered on the stream given to amrvac_create and does
+ *    not synchronise the host unless stated.
+ *  * Errors: a call returns a status.  Host-detectable errors (null
+ *    pointers, bad sizes, inconsistent neighbours, unsupported options) are
+ *    reported before anything is enqueued, leaving all state unchanged.
+ *    Device-detected errors (rho <= 0, p <= 0 or a non-finite value met by
+ *    the primitive recovery) set a sticky flag that the next synchronising
+ *    call (amrvac_sync, or a call documented to synchronise) returns as
+ *    AMRVAC_ERR_NONPHYSICAL; the state is then unspecified.  No call aborts
+ *    or throws across the ABI.
+ *  * A context is used from one host thread at a time.
+ */
+#ifndef AMRVAC_H
+#define AMRVAC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AMRVAC_ABI_VERSION 1
+#define AMRVAC_NGHOST 3
+
+typedef enum {
+  AMRVAC_OK = 0,
+  AMRVAC_ERR_INVALID = 1,      /* bad argument, layout or neighbour table      */
+  AMRVAC_ERR_NOMEM = 2,        /* device allocation failed                     */
+  AMRVAC_ERR_DEVICE = 3,       /* HIP runtime error                            */
+  AMRVAC_ERR_NONPHYSICAL = 4,  /* rho <= 0, p <= 0 or non-finite state met     */
+  AMRVAC_ERR_UNSUPPORTED = 5   /* valid request this build does not implement  */
+} amrvac_status;
+
+typedef enum { AMRVAC_HD = 0, AMRVAC_MHD = 1 } amrvac_physics;
+
+/* Sect. 2.3: RK3 (Gottlieb & Shu 1998), SSPRK(4,3) and SSPRK(5,4) tables. */
+typedef enum { AMRVAC_RK3 = 0, AMRVAC_SSPRK43 = 1, AMRVAC_SSPRK54 = 2 } amrvac_scheme;
+
+/* Execution form of a stage: one launch per block, or one persistent fused
+ * launch over the whole block list replayed from a HIP graph. */
+typedef enum { AMRVAC_EXEC_PER_BLOCK = 0, AMRVAC_EXEC_BATCHED = 1 } amrvac_exec;
+
+typedef struct {
+  int ndim;        /* 1, 2 or 3                                     */
+  int physics;     /* amrvac_physics                                */
+  double gamma;    /* ratio of specific heats, finite and > 1       */
+  int exec;        /* amrvac_exec                                   */
+} amrvac_config;
+
+typedef struct {
+  double *u;       /* device; padded conserved state (layout above)     */
+  int n[3];        /* interior cells per direction (1 for d >= ndim)    */
+  double dx[3];    /* cell widths, > 0 for active directions            */
+  double xlo[3];   /* lower face of the first interior cell             */
+  int nbr[6];      /* face neighbours (-x,+x,-y,+y,-z,+z) or -1 (fixed) */
+} amrvac_block;
+
+typedef struct amrvac_ctx amrvac_ctx;
+
+/* Returns AMRVAC_ABI_VERSION. */
+int amrvac_abi_version(void);
+
+/* Creates a context on the current HIP device.  hip_stream: a hipStream_t
+ * (NULL = the default stream) on which all later work is enqueued; it is
+ * borrowed, not owned.  *out receives the context (NULL on failure).
+ * Errors: INVALID (null cfg/out, ndim not in 1..3, physics or exec unknown,
+ * gamma not finite or <= 1), DEVICE, NOMEM. */
+amrvac_status amrvac_create(const amrvac_config *cfg, void *hip_stream, amrvac_ctx **out);
+
+/* Sets the block list (Sect. 2.1 grid of point values; block/ghost layout
+ * above).  The descriptors are copied; the u pointers are borrowed until the
+ * next set_blocks or destroy and must stay valid and unaliased.  Builds the
+ * neighbour and work tables and the context-owned scratch (stage buffers,
+ * checkpoints are allocated on demand), and drops cached graphs.  Enqueues
+ * table uploads on the context stream.
+ * Errors: INVALID (null pointers, nblocks < 1, n[d] < 3 for an active
+ * direction, n[d] != 1 or nbr != -1 for an inactive one, dx <= 0 or not
+ * finite, a neighbour index out of range, a neighbour relation that is not
+ * mutual (b's +d neighbour must name b as its -d neighbour), or neighbouring
+ * faces of different size); NOMEM; DEVICE. */
+amrvac_status amrvac_set_blocks(amrvac_ctx *ctx, const amrvac_block *blocks, int nblocks);
+
+/* Host-only check of a block list against cfg, with the same rules as
+ * amrvac_set_blocks (Sect. 2.1 grid of ghost-padded blocks).  Makes no HIP
+ * call and needs no device.  msg (may be NULL) receives a description of
+ * the first violation, truncated to msglen bytes including the NUL.
+ * Returns OK or INVALID. */
+amrvac_status amrvac_validate_blocks(const amrvac_config *cfg, const amrvac_block *blocks,
+                                     int nblocks, char *msg, int msglen);
+
+/* Chooses the execution form used by later calls (amrvac_exec). */
+amrvac_status amrvac_set_exec(amrvac_ctx *ctx, int exec);
+
+/* Evaluates L(U) (Sect. 2.1 eq. timeoperator with S = 0, fluxes from
+ * Sect. 2.2) of the current block states.  rhs: host array of nblocks
+ * device pointers, each to nvar x n[0]*n[1]*n[2] doubles (interior only,
+ * variable major, x fastest), written by the call.  cmax_out: host array of
+ * 3 doubles receiving c_max per direction (0 for inactive ones), or NULL;
+ * when non-NULL the call synchronises the context stream and reports
+ * device errors.  Errors: INVALID (no blocks, null rhs or null entry),
+ * NONPHYSICAL (only when synchronising), DEVICE. */
+amrvac_status amrvac_fd_rhs(amrvac_ctx *ctx, double *const *rhs, double *cmax_out);
+
+/* Advances every block by nsteps steps of `scheme` (Sect. 2.3).  The
+ * interiors of the u buffers are overwritten with U^{n+nsteps}; ghost layers
+ * are not written.  dt_fixed: host pointer to a fixed step > 0, or NULL to
+ * use dt = cfl / max_blocks sum_d (c_max,d / dx_d) evaluated on U^n at the
+ * start of every step (the multi-D form of the Sect. 4.4 bound dt < dx /
+ * c_w).  t_inout: host pointer; in: start time, out: end time.  Non-NULL
+ * t_inout synchronises the stream and reports device errors; NULL does
+ * neither.  Errors: INVALID (no blocks, nsteps < 0, scheme unknown, cfl not
+ * > 0 and finite when dt_fixed is NULL, *dt_fixed not > 0 and finite),
+ * NONPHYSICAL (only when synchronising), DEVICE, NOMEM. */
+amrvac_status amrvac_ssprk_step(amrvac_ctx *ctx, int scheme, double cfl, const double *dt_fixed,
+                                int nsteps, double *t_inout);
+
+/* Reverse mode of amrvac_ssprk_step at a fixed dt: with U_0 the current
+ * block states (read only, not modified) and U_N the state after nsteps
+ * steps, lam[b] (host array of nblocks device pointers, each in the padded
+ * block layout) holds on entry dJ/dU_N (ghost entries ignored) and on
+ * return dJ/dU_0 (ghost entries set to 0).  The map differentiated is the
+ * discrete scheme of Sects. 2.1-2.3 with c_max a function of every stage
+ * state (its derivative is delivered to the maximising cell, lowest block
+ * then lowest cell index on ties); MP5, minmod and median are
+ * differentiated along the branch taken by the forward pass.  Checkpoints
+ * of U are kept every ckpt_every steps and the steps in between are
+ * recomputed.  Requires every face to be periodic (nbr >= 0) and n[d] >= 5.
+ * Synchronises the stream and reports device errors.
+ * Errors: INVALID (no blocks, null lam or entry, nsteps < 0, ckpt_every < 1,
+ * dt not > 0 and finite, scheme unknown), UNSUPPORTED (a fixed face or
+ * n[d] < 5), NONPHYSICAL, NOMEM, DEVICE. */
+amrvac_status amrvac_ssprk_adjoint(amrvac_ctx *ctx, int scheme, double dt, int nsteps,
+                                   int ckpt_every, double *const *lam);
+
+/* Waits for the context stream and returns (and clears) the sticky device
+ * error: OK, NONPHYSICAL or DEVICE. */
+amrvac_status amrvac_sync(amrvac_ctx *ctx);
+
+/* Message describing the last error of ctx ("" if none); NULL ctx gives a
+ * static description of context-less failures.  Owned by the library. */
+const char *amrvac_last_error(const amrvac_ctx *ctx);
+
+/* Releases the context and everything it owns (never the caller's
+ * buffers).  NULL is ignored. */
+void amrvac_destroy(amrvac_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMRVAC_H */

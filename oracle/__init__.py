@@ -43,7 +43,9 @@ def lib():
         L.orc_fast_speed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp]
         L.orc_scheme_table.argtypes = [ctypes.c_int, dp, dp]
         L.orc_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                              ctypes.c_int, ip, dp, ip, dpp, dpp, dp]
+                              ctypes.c_int, ip, dp, ip, dpp, dpp, dp, dp]
+        L.orc_cmax.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ip, dp, ip,
+                               dpp, dp]
         L.orc_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                               ctypes.c_int, ip, dp, ip, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, ctypes.c_int, dpp, dp]
@@ -123,16 +125,31 @@ def scheme_table(scheme: int):
     return s, al.reshape(6, 6)[:s + 1, :s], be.reshape(6, 6)[:s + 1, :s]
 
 
-def rhs(bs, eps: float = 0.0) -> Tuple[List[np.ndarray], np.ndarray]:
-    """L(U) for every block (padded arrays, ghost entries 0) and c_max[3]."""
+def rhs(bs, eps: float = 0.0, cmax: Optional[Sequence[float]] = None
+        ) -> Tuple[List[np.ndarray], np.ndarray]:
+    """L(U) for every block (padded arrays, ghost entries 0) and c_max[3].
+    `cmax` overrides the maximum over these blocks (for samples of a larger
+    block list)."""
     n, dx, nbr = _geom(bs)
     u = [np.ascontiguousarray(x, np.float64) for x in bs.u]
     out = [np.zeros_like(x) for x in u]
     cm = np.zeros(3)
+    cin = None if cmax is None else np.ascontiguousarray(cmax, np.float64)
     st = lib().orc_rhs(bs.ndim, int(bs.mhd), bs.gamma, eps, bs.nb, _ip(n), _dp(dx), _ip(nbr),
-                       _ptrs(u), _ptrs(out), _dp(cm))
+                       _ptrs(u), _ptrs(out), _dp(cm), None if cin is None else _dp(cin))
     _check(st, "rhs")
-    return out, cm
+    return out, (cm if cin is None else cin.copy())
+
+
+def cmax(bs) -> np.ndarray:
+    """Global c_max over the interior cells of every block."""
+    n, dx, nbr = _geom(bs)
+    u = [np.ascontiguousarray(x, np.float64) for x in bs.u]
+    cm = np.zeros(3)
+    st = lib().orc_cmax(bs.ndim, int(bs.mhd), bs.gamma, bs.nb, _ip(n), _dp(dx), _ip(nbr), _ptrs(u),
+                        _dp(cm))
+    _check(st, "cmax")
+    return cm
 
 
 def run(bs, scheme: int, nsteps: int, cfl: float = 0.4, dt: Optional[float] = None,

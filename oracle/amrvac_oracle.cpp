@@ -616,8 +616,11 @@ int orc_scheme_table(int scheme, double* alpha, double* beta) {
 // L(U) on every block.  u: padded input blocks (periodic ghosts are filled
 // from neighbours internally; fixed ghosts are read as given).  rhs:
 // padded output blocks (ghost entries set to 0).  cmax: out, per direction.
+// cmax_in: if non-NULL, c_max to use instead of the maximum over these
+// blocks (lets a test evaluate L on a sample of a larger block list).
 int orc_rhs(int ndim, int mhd, double gamma, double eps, int nb, const int* n, const double* dx,
-            const int* nbr, const double* const* u, double* const* rhs_out, double* cmax) {
+            const int* nbr, const double* const* u, double* const* rhs_out, double* cmax,
+            const double* cmax_in) {
   Grid G;
   int st = build_grid(G, ndim, mhd, gamma, nb, n, dx, nbr);
   if (st) return st;
@@ -628,11 +631,27 @@ int orc_rhs(int ndim, int mhd, double gamma, double eps, int nb, const int* n, c
   double cm[3];
   st = global_cmax(G, U, cm);
   if (st) return st;
+  if (cmax_in)
+    for (int d = 0; d < 3; ++d) cm[d] = cmax_in[d];
   st = rhs(G, U, cm, L, eps);
   if (st) return st;
   for (int b = 0; b < nb; ++b) std::memcpy(rhs_out[b], L[b].data(), L[b].size() * sizeof(double));
   for (int d = 0; d < 3; ++d) cmax[d] = cm[d];
   return ORC_OK;
+}
+
+// c_max (reading R1) of the interior cells of the given blocks.
+int orc_cmax(int ndim, int mhd, double gamma, int nb, const int* n, const double* dx, const int* nbr,
+             const double* const* u, double* cmax) {
+  Grid G;
+  int st = build_grid(G, ndim, mhd, gamma, nb, n, dx, nbr);
+  if (st) return st;
+  State<double> U;
+  load_state(G, U, u);
+  double cm[3];
+  st = global_cmax(G, U, cm);
+  for (int d = 0; d < 3; ++d) cmax[d] = cm[d];
+  return st;
 }
 
 // nsteps SSPRK steps.  dt_fixed <= 0 selects the CFL rule.  u: in/out

@@ -1,0 +1,95 @@
+// Internal data structures shared by the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace amrvac {
+
+constexpr int NG = 3;          // ghost layers (MP5 stencils reach i-2..i+3)
+constexpr int MAX_SLOTS = 8;   // c_max slots per step (stages + 1)
+
+// One block as the kernels see it.
+struct BlockDev {
+  double* u;            // caller's padded state (buffer id 0)
+  long long off;        // offset (doubles) of this block inside one scratch slot
+  long long cells;      // interior cells n0*n1*n2
+  int n[3];             // interior extents (1 for inactive directions)
+  int P[3];             // padded extents
+  int g[3];             // ghost depth per direction (3 or 0)
+  int nbr[6];           // face neighbours, -1 = fixed ghosts in u
+  double dx[3];
+  double inv_dx[3];
+};
+
+// One unit of work: a box of interior cells of one block.
+struct Tile {
+  int block;
+  int o[3];             // origin (interior coordinates)
+};
+
+// Device-resident step control: c_max slots (uint64 bit patterns of
+// non-negative doubles, so integer max == floating max), dt, t, error flag.
+struct Control {
+  unsigned long long cm[MAX_SLOTS][3];
+  double dt;
+  double t;
+  double dt_fixed;      // > 0: fixed step
+  double cfl;
+  int err;              // sticky: 1 = non-physical state met
+  int ndx;              // number of distinct dx tuples in dxtab
+  int pad[2];
+};
+
+// Buffers: id 0 = caller's padded u; id k >= 1 = scratch slot k-1 with the
+// interior-only layout, at scr + (k-1)*slot_stride + block.off.
+struct StateTable {
+  const BlockDev* blocks;
+  double* scr;
+  long long slot_stride;
+};
+
+constexpr int MAX_SRC = 3;
+
+// Parameters of one fused stage launch:
+//   L     = L(buffer `in`)   (c_max from slot cm_in)
+//   dst   = sum_j a[j] * buffer src[j] + (dt * b) * L          (mode 0)
+//   sdst  = sum_j sa[j] * buffer ssrc[j] + (dt * sb) * L       (optional)
+//   rhs_out[block] = L  (interior layout)                     (mode 1)
+// Every WG keeps a running maximum of |v_d| + c_f,d of the new state and
+// folds it into slot cm_out at exit (cm_out < 0: none).  cm_reset >= 0:
+// one thread clears that slot.
+struct StageParams {
+  StateTable st;
+  const Tile* tiles;
+  int tile_begin;
+  int ntiles;
+  Control* ctl;
+  double gamma;
+  int in;
+  int mode;
+  int cm_in, cm_out, cm_reset;
+  int nsrc;
+  int src[MAX_SRC];
+  double a[MAX_SRC];
+  double b;
+  int dst;
+  int snsrc;
+  int ssrc[MAX_SRC];
+  double sa[MAX_SRC];
+  double sb;
+  int sdst;
+  double* const* rhs_out;
+};
+
+struct CmaxParams {
+  StateTable st;
+  const Tile* tiles;
+  int ntiles;
+  int tx, ty, tz;       // tile extents used for the tile list
+  Control* ctl;
+  double gamma;
+  int in;
+  int slot;
+};
+
+}  // namespace amrvac

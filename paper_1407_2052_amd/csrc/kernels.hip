@@ -1,0 +1,643 @@
+// gfx950 (MI355X) FP64 kernels of the conservative finite-difference scheme
+// of Porth et al. (2014), Sect. 2:
+//   * k_stage: one fused Shu-Osher stage (Sect. 2.3) on tiles of blocks:
+//     halo load -> primitive recovery -> physical flux -> global
+//     Lax-Friedrichs split (Sect. 2.2) -> MP5 of F+ (left-biased) and F-
+//     (right-biased) -> interface flux -> conservative difference (Sect.
+//     2.1, eq. fdcons) -> stage combination -> |v_d| + c_f,d of the new
+//     state for the next stage's c_max;
+//   * k_cmax: c_max of a state (Sect. 2.2);
+//   * k_step_begin: dt from c_max (multi-D form of the Sect. 4.4 bound),
+//     t accumulation and c_max slot resets, so a whole step runs without
+//     a host round trip.
+//
+// Work decomposition.  A tile is a TX x TY x TZ box of one block's interior;
+// one work-group owns one tile at a time and loops over tiles (persistent
+// grid).  Per direction d and per group of variables the work-group
+//   A) computes F+ and F- for the tile extended by 3 cells along d (halo
+//      cells come from the neighbour's interior or the fixed ghost layers)
+//      into LDS,
+//   B) evaluates MP5(F+) + MP5(F-) for every (interface, variable) of the
+//      tile (T_d + 1 interfaces per pencil) into registers, then LDS,
+//   C) accumulates -(Fhat_{i+1/2} - Fhat_{i-1/2}) / dx_d into per-thread
+//      register accumulators of the cells it owns.
+// The stage update reads its sources once per cell and writes the result;
+// the only HBM traffic beyond the algorithmic state passes is the 3-cell
+// halo of tiles (served mostly by L2).
+//
+// Accumulation order of L matches the definition: L = 0; for d: L -= diff_d
+// / dx_d (as a product with 1/dx_d).  MP5 is evaluated in its median form
+// median(fL, fmin, fmax); with eps = 0 the early exit of the published
+// algorithm returns the same value (fL lies inside both bounds whenever the
+// early-exit test holds).
+#include "amrvac_internal.h"
+
+#include <type_traits>
+#include <utility>
+
+namespace amrvac {
+
+template <int NDIM, bool MHD>
+struct Eq {
+  static constexpr int NV = MHD ? 8 : 2 + NDIM;
+  static constexpr int NC = MHD ? 3 : NDIM;
+  static constexpr int IE = 1 + NC;
+};
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Addressing of state buffers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ const double* cell_addr(const StateTable& st, const BlockDev& B, int buf,
+                                                   int i, int j, int k, long long& vstride) {
+  if (buf == 0) {
+    vstride = (long long)B.P[0] * B.P[1] * B.P[2];
+    return B.u + (((long long)(k + B.g[2]) * B.P[1] + (j + B.g[1])) * B.P[0] + (i + B.g[0]));
+  }
+  vstride = B.cells;
+  return st.scr + (long long)(buf - 1) * st.slot_stride + B.off +
+         (((long long)k * B.n[1] + j) * B.n[0] + i);
+}
+
+__device__ __forceinline__ double* cell_addr_w(const StateTable& st, const BlockDev& B, int buf,
+                                               int i, int j, int k, long long& vstride) {
+  return const_cast<double*>(cell_addr(st, B, buf, i, j, k, vstride));
+}
+
+// Load all NV variables of cell (i,j,k) of block blk, where only coordinate
+// D may lie outside [0, n_D): then the value comes from the face neighbour's
+// interior (same buffer), or from this block's fixed ghost layer (buffer 0).
+template <int NV, int D>
+__device__ __forceinline__ void load_cell(const StateTable& st, int blk, int buf, int i, int j, int k,
+                                          double* u) {
+  const BlockDev* B = &st.blocks[blk];
+  int c[3] = {i, j, k};
+  int bf = buf;
+  if (c[D] < 0) {
+    int nb = B->nbr[2 * D];
+    if (nb >= 0) {
+      B = &st.blocks[nb];
+      c[D] += B->n[D];
+    } else {
+      bf = 0;
+    }
+  } else if (c[D] >= B->n[D]) {
+    int nb = B->nbr[2 * D + 1];
+    if (nb >= 0) {
+      c[D] -= B->n[D];
+      B = &st.blocks[nb];
+    } else {
+      bf = 0;
+    }
+  }
+  long long vs;
+  const double* p = cell_addr(st, *B, bf, c[0], c[1], c[2], vs);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = p[v * vs];
+}
+
+// ---------------------------------------------------------------------------
+// Physics: primitive recovery, flux along D, fast speed.
+// ---------------------------------------------------------------------------
+struct PrimD {
+  double rho, ri, v[3], p, B[3], b2;
+};
+
+template <int NDIM, bool MHD>
+__device__ __forceinline__ bool prim(const double* u, double gamma, PrimD& w) {
+  using E = Eq<NDIM, MHD>;
+  w.rho = u[0];
+  w.ri = 1.0 / w.rho;
+  double mv = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    w.v[k] = (k < E::NC) ? u[1 + k] * w.ri : 0.0;
+    w.B[k] = 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < E::NC; ++k) mv += u[1 + k] * w.v[k];
+  double eint = u[E::IE] - 0.5 * mv;
+  w.b2 = 0.0;
+  if constexpr (MHD) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w.B[k] = u[5 + k];
+    w.b2 = w.B[0] * w.B[0] + w.B[1] * w.B[1] + w.B[2] * w.B[2];
+    eint -= 0.5 * w.b2;
+  }
+  w.p = (gamma - 1.0) * eint;
+  return (w.rho > 0.0) && (w.p > 0.0) && (w.p < __builtin_huge_val()) &&
+         (w.rho < __builtin_huge_val());
+}
+
+// Physical flux along D (Sect. 3 eqs. masscons, momentum, total; Sect. 4.1
+// eq. b1eq and Sect. 4.3 eqs. momentummhd, fractional with B0 = 0).
+template <int NDIM, bool MHD, int D>
+__device__ __forceinline__ void phys_flux(const double* u, const PrimD& w, double* F) {
+  using E = Eq<NDIM, MHD>;
+  const double vd = w.v[D];
+  F[0] = u[1 + D];
+  if constexpr (!MHD) {
+#pragma unroll
+    for (int k = 0; k < E::NC; ++k) F[1 + k] = u[1 + k] * vd;
+    F[1 + D] += w.p;
+    F[E::IE] = vd * (u[E::IE] + w.p);
+  } else {
+    const double ptot = w.p + 0.5 * w.b2;
+    const double Bd = w.B[D];
+    const double bv = w.B[0] * w.v[0] + w.B[1] * w.v[1] + w.B[2] * w.v[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) F[1 + k] = u[1 + k] * vd - Bd * w.B[k];
+    F[1 + D] += ptot;
+    F[4] = vd * (u[4] + ptot) - Bd * bv;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) F[5 + k] = (k == D) ? 0.0 : vd * w.B[k] - Bd * w.v[k];
+  }
+}
+
+// Fast magnetosonic speed along d (sound speed for hydro).
+template <bool MHD>
+__device__ __forceinline__ double fast_speed(const PrimD& w, int d, double gamma) {
+  const double a2 = gamma * w.p * w.ri;
+  if constexpr (!MHD) {
+    return sqrt(a2);
+  } else {
+    const double b2 = w.b2 * w.ri;
+    const double bd2 = w.B[d] * w.B[d] * w.ri;
+    const double s = a2 + b2;
+    double disc = s * s - 4.0 * a2 * bd2;
+    disc = disc < 0.0 ? 0.0 : disc;
+    return sqrt(0.5 * (s + sqrt(disc)));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MP5 (Suresh & Huynh 1997), alpha = 4, eps = 0, median form.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double minmod4(double w, double x, double y, double z) {
+  const double lo = fmin(fmin(w, x), fmin(y, z));
+  const double hi = fmax(fmax(w, x), fmax(y, z));
+  return fmax(lo, 0.0) + fmin(hi, 0.0);
+}
+
+__device__ __forceinline__ double mp5(double a, double b, double c, double d, double e) {
+  const double fL = (2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e) * (1.0 / 60.0);
+  const double cb = c - b;
+  const double dm = a - 2.0 * b + c;
+  const double d0 = b - 2.0 * c + d;
+  const double dp = c - 2.0 * d + e;
+  const double m4p = minmod4(4.0 * d0 - dp, 4.0 * dp - d0, d0, dp);
+  const double m4m = minmod4(4.0 * d0 - dm, 4.0 * dm - d0, d0, dm);
+  const double fUL = c + 4.0 * cb;
+  const double fMD = 0.5 * (c + d) - 0.5 * m4p;
+  const double fLC = c + 0.5 * cb + (4.0 / 3.0) * m4m;
+  const double fmn = fmax(fmin(fmin(c, d), fMD), fmin(fmin(c, fUL), fLC));
+  const double fmx = fmin(fmax(fmax(c, d), fMD), fmax(fmax(c, fUL), fLC));
+  return fmin(fmax(fL, fmn), fmx);
+}
+
+// ---------------------------------------------------------------------------
+// Tile geometry helpers (compile time).
+// ---------------------------------------------------------------------------
+template <int TX, int TY, int TZ>
+struct TileShape {
+  static constexpr int T(int d) { return d == 0 ? TX : d == 1 ? TY : TZ; }
+  static constexpr int TC = TX * TY * TZ;
+  // extended box along D (halo of 3 on both sides)
+  static constexpr int E(int D, int d) { return T(d) + (d == D ? 2 * NG : 0); }
+  static constexpr int NEXT(int D) { return E(D, 0) * E(D, 1) * E(D, 2); }
+  static constexpr int SD(int D) { return D == 0 ? 1 : D == 1 ? E(D, 0) : E(D, 0) * E(D, 1); }
+  // interface box along D
+  static constexpr int I(int D, int d) { return T(d) + (d == D ? 1 : 0); }
+  static constexpr int NIFC(int D) { return I(D, 0) * I(D, 1) * I(D, 2); }
+  static constexpr int SI(int D) { return D == 0 ? 1 : D == 1 ? I(D, 0) : I(D, 0) * I(D, 1); }
+};
+
+template <int A, int B>
+struct cmax_i { static constexpr int v = A > B ? A : B; };
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x = fmax(x, __shfl_xor(x, m, 64));
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Fused stage kernel.
+// ---------------------------------------------------------------------------
+template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP>
+__global__ void __launch_bounds__(NT) k_stage(StageParams P) {
+  using E = Eq<NDIM, MHD>;
+  using S = TileShape<TX, TY, TZ>;
+  constexpr int NV = E::NV;
+  constexpr int VPG = (NV + NGRP - 1) / NGRP;
+  constexpr int TC = S::TC;
+  constexpr int CPT = (TC + NT - 1) / NT;
+  constexpr int EXT = cmax_i<cmax_i<S::NEXT(0), NDIM >= 2 ? S::NEXT(1) : 0>::v,
+                             NDIM >= 3 ? S::NEXT(2) : 0>::v;
+  constexpr int IFC = cmax_i<cmax_i<S::NIFC(0), NDIM >= 2 ? S::NIFC(1) : 0>::v,
+                             NDIM >= 3 ? S::NIFC(2) : 0>::v;
+  constexpr int LDS_N = cmax_i<2 * VPG * EXT, VPG * IFC>::v;
+  __shared__ double lds[LDS_N];
+  __shared__ double red[NT / 64][3];
+
+  const int tid = threadIdx.x;
+  const StateTable& st = P.st;
+  Control* ctl = P.ctl;
+  const double gamma = P.gamma;
+
+  double cin[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) cin[d] = __longlong_as_double((long long)ctl->cm[P.cm_in][d]);
+  const double dt = (P.mode == 0) ? ctl->dt : 0.0;
+  const double dtb = dt * P.b;
+  const double dtsb = dt * P.sb;
+  if (P.cm_reset >= 0 && blockIdx.x == 0 && tid == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ctl->cm[P.cm_reset][d] = 0ull;
+  }
+
+  double run[3] = {0.0, 0.0, 0.0};
+  bool ok_all = true;
+
+  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) {
+    const Tile tl = P.tiles[P.tile_begin + t];
+    const BlockDev& B = st.blocks[tl.block];
+    int tend[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int rem = B.n[d] - tl.o[d];
+      tend[d] = rem < S::T(d) ? rem : S::T(d);
+    }
+
+    double L[CPT][NV];
+#pragma unroll
+    for (int r = 0; r < CPT; ++r)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) L[r][v] = 0.0;
+
+    static_for<0, NDIM>([&](auto Dc) {
+      constexpr int D = decltype(Dc)::value;
+      constexpr int NEXT_D = S::NEXT(D);
+      constexpr int NIFC_D = S::NIFC(D);
+      constexpr int NITEM = VPG * NIFC_D;
+      constexpr int IPT = (NITEM + NT - 1) / NT;
+      constexpr int E0 = S::E(D, 0), E1 = S::E(D, 1);
+      constexpr int I0 = S::I(D, 0), I1 = S::I(D, 1);
+      constexpr int SD = S::SD(D);
+      const double c = cin[D];
+      const double idx_d = B.inv_dx[D];
+
+      static_for<0, NGRP>([&](auto Gc) {
+        constexpr int G = decltype(Gc)::value;
+        // A) split fluxes of the extended tile -> LDS
+        for (int e = tid; e < NEXT_D; e += NT) {
+          int a[3];
+          a[0] = e % E0;
+          a[1] = (e / E0) % E1;
+          a[2] = e / (E0 * E1);
+          bool valid = true;
+          int cc[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            if (d == D) {
+              valid = valid && (a[d] < tend[d] + 2 * NG);
+              cc[d] = tl.o[d] + a[d] - NG;
+            } else {
+              valid = valid && (a[d] < tend[d]);
+              cc[d] = tl.o[d] + a[d];
+            }
+          }
+          if (valid) {
+            double u[NV];
+            load_cell<NV, D>(st, tl.block, P.in, cc[0], cc[1], cc[2], u);
+            PrimD w;
+            ok_all = prim<NDIM, MHD>(u, gamma, w) && ok_all;
+            double F[NV];
+            phys_flux<NDIM, MHD, D>(u, w, F);
+#pragma unroll
+            for (int vg = 0; vg < VPG; ++vg) {
+              constexpr int dummy = 0;
+              (void)dummy;
+              const int v = G * VPG + vg;
+              if (v < NV) {
+                lds[vg * NEXT_D + e] = 0.5 * (F[v] + c * u[v]);
+                lds[(VPG + vg) * NEXT_D + e] = 0.5 * (F[v] - c * u[v]);
+              }
+            }
+          }
+        }
+        __syncthreads();
+        // B) interface fluxes for every (variable, interface)
+        double res[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+          const int w = tid + r * NT;
+          res[r] = 0.0;
+          if (w < NITEM) {
+            const int vg = w / NIFC_D;
+            const int q = w - vg * NIFC_D;
+            int a[3];
+            a[0] = q % I0;
+            a[1] = (q / I0) % I1;
+            a[2] = q / (I0 * I1);
+            bool valid = (G * VPG + vg) < NV;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) valid = valid && (a[d] < tend[d] + (d == D ? 1 : 0));
+            if (valid) {
+              // interface between cells a_D - 1 and a_D (tile coordinates);
+              // stencil cells a_D - 3 .. a_D + 2 are ext indices a_D .. a_D + 5
+              int eb = 0;
+              {
+                int ea[3] = {a[0], a[1], a[2]};
+                eb = ea[0] + E0 * (ea[1] + E1 * ea[2]);
+              }
+              const double* fp = &lds[vg * NEXT_D + eb];
+              const double* fm = &lds[(VPG + vg) * NEXT_D + eb];
+              res[r] = mp5(fp[0], fp[SD], fp[2 * SD], fp[3 * SD], fp[4 * SD]) +
+                       mp5(fm[5 * SD], fm[4 * SD], fm[3 * SD], fm[2 * SD], fm[SD]);
+            }
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+          const int w = tid + r * NT;
+          if (w < NITEM) lds[w] = res[r];
+        }
+        __syncthreads();
+        // C) conservative difference into the owned cells
+#pragma unroll
+        for (int r = 0; r < CPT; ++r) {
+          const int cidx = tid + r * NT;
+          if (cidx < TC) {
+            int a[3];
+            a[0] = cidx % TX;
+            a[1] = (cidx / TX) % TY;
+            a[2] = cidx / (TX * TY);
+            if (a[0] < tend[0] && a[1] < tend[1] && a[2] < tend[2]) {
+              const int il = a[0] + I0 * (a[1] + I1 * a[2]);
+              constexpr int SI = S::SI(D);
+#pragma unroll
+              for (int vg = 0; vg < VPG; ++vg) {
+                const int v = G * VPG + vg;
+                if (v < NV) {
+                  const double diff = lds[vg * NIFC_D + il + SI] - lds[vg * NIFC_D + il];
+                  L[r][v] -= diff * idx_d;
+                }
+              }
+            }
+          }
+        }
+        __syncthreads();
+      });
+    });
+
+    // Stage update (or right-hand side output) and next-stage speeds.
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+      const int cidx = tid + r * NT;
+      if (cidx >= TC) continue;
+      int a[3];
+      a[0] = cidx % TX;
+      a[1] = (cidx / TX) % TY;
+      a[2] = cidx / (TX * TY);
+      if (!(a[0] < tend[0] && a[1] < tend[1] && a[2] < tend[2])) continue;
+      const int i = tl.o[0] + a[0], j = tl.o[1] + a[1], k = tl.o[2] + a[2];
+      if (P.mode == 1) {
+        double* out = P.rhs_out[tl.block] + (((long long)k * B.n[1] + j) * B.n[0] + i);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v * B.cells] = L[r][v];
+        continue;
+      }
+      double un[NV];
+      {
+        long long vs[MAX_SRC];
+        const double* sp[MAX_SRC];
+#pragma unroll
+        for (int q = 0; q < MAX_SRC; ++q)
+          if (q < P.nsrc) sp[q] = cell_addr(st, B, P.src[q], i, j, k, vs[q]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double acc = P.a[0] * sp[0][v * vs[0]];
+#pragma unroll
+          for (int q = 1; q < MAX_SRC; ++q)
+            if (q < P.nsrc) acc += P.a[q] * sp[q][v * vs[q]];
+          acc += dtb * L[r][v];
+          un[v] = acc;
+        }
+      }
+      if (P.sdst >= 0) {
+        long long vs[MAX_SRC];
+        const double* sp[MAX_SRC];
+#pragma unroll
+        for (int q = 0; q < MAX_SRC; ++q)
+          if (q < P.snsrc) sp[q] = cell_addr(st, B, P.ssrc[q], i, j, k, vs[q]);
+        long long ws;
+        double* sd = cell_addr_w(st, B, P.sdst, i, j, k, ws);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double acc = P.sa[0] * sp[0][v * vs[0]];
+#pragma unroll
+          for (int q = 1; q < MAX_SRC; ++q)
+            if (q < P.snsrc) acc += P.sa[q] * sp[q][v * vs[q]];
+          acc += dtsb * L[r][v];
+          sd[v * ws] = acc;
+        }
+      }
+      {
+        long long ws;
+        double* dp = cell_addr_w(st, B, P.dst, i, j, k, ws);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dp[v * ws] = un[v];
+      }
+      if (P.cm_out >= 0) {
+        PrimD w;
+        ok_all = prim<NDIM, MHD>(un, gamma, w) && ok_all;
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) run[d] = fmax(run[d], fabs(w.v[d]) + fast_speed<MHD>(w, d, gamma));
+      }
+    }
+  }
+
+  // Fold the work-group maxima into the next stage's c_max slot.
+  if (P.cm_out >= 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) run[d] = wave_max(run[d]);
+    const int wv = tid >> 6, ln = tid & 63;
+    if (ln == 0) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) red[wv][d] = run[d];
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+      for (int d = 0; d < NDIM; ++d) {
+        double m = red[0][d];
+        for (int q = 1; q < NT / 64; ++q) m = fmax(m, red[q][d]);
+        atomicMax(&ctl->cm[P.cm_out][d], (unsigned long long)__double_as_longlong(m));
+      }
+    }
+  }
+  if (!ok_all) atomicOr(&ctl->err, 1);
+}
+
+// ---------------------------------------------------------------------------
+// c_max of a state (interior cells of every block).
+// ---------------------------------------------------------------------------
+template <int NDIM, bool MHD>
+__global__ void __launch_bounds__(256) k_cmax(CmaxParams P) {
+  using E = Eq<NDIM, MHD>;
+  constexpr int NV = E::NV;
+  __shared__ double red[4][3];
+  const int tid = threadIdx.x;
+  double run[3] = {0.0, 0.0, 0.0};
+  bool ok_all = true;
+  const int tcells = P.tx * P.ty * P.tz;
+  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) {
+    const Tile tl = P.tiles[t];
+    const BlockDev& B = P.st.blocks[tl.block];
+    for (int c = tid; c < tcells; c += 256) {
+      const int i = tl.o[0] + c % P.tx;
+      const int j = tl.o[1] + (c / P.tx) % P.ty;
+      const int k = tl.o[2] + c / (P.tx * P.ty);
+      if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
+      long long vs;
+      const double* p = cell_addr(P.st, B, P.in, i, j, k, vs);
+      double u[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v] = p[v * vs];
+      PrimD w;
+      ok_all = prim<NDIM, MHD>(u, P.gamma, w) && ok_all;
+#pragma unroll
+      for (int d = 0; d < NDIM; ++d) run[d] = fmax(run[d], fabs(w.v[d]) + fast_speed<MHD>(w, d, P.gamma));
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) run[d] = wave_max(run[d]);
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) red[tid >> 6][d] = run[d];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int d = 0; d < NDIM; ++d) {
+      double m = fmax(fmax(red[0][d], red[1][d]), fmax(red[2][d], red[3][d]));
+      atomicMax(&P.ctl->cm[P.slot][d], (unsigned long long)__double_as_longlong(m));
+    }
+  }
+  if (!ok_all) atomicOr(&P.ctl->err, 1);
+}
+
+// dt from c_max (or the fixed step), t += dt, and clearing of the c_max
+// slots the coming stages accumulate into.  One thread.
+__global__ void k_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo, int clear_hi) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double dt;
+  if (ctl->dt_fixed > 0.0) {
+    dt = ctl->dt_fixed;
+  } else {
+    double cm[3];
+    for (int d = 0; d < 3; ++d) cm[d] = __longlong_as_double((long long)ctl->cm[0][d]);
+    double worst = 0.0;
+    for (int q = 0; q < ctl->ndx; ++q) {
+      double s = 0.0;
+      for (int d = 0; d < ndim; ++d) s += cm[d] / dxtab[3 * q + d];
+      worst = fmax(worst, s);
+    }
+    dt = ctl->cfl / worst;
+  }
+  ctl->dt = dt;
+  ctl->t += dt;
+  for (int s = clear_lo; s <= clear_hi; ++s)
+    for (int d = 0; d < 3; ++d) ctl->cm[s][d] = 0ull;
+}
+
+// Host-provided step controls, set on the stream (no host buffer lifetime).
+__global__ void k_set_control(Control* ctl, double dt_fixed, double cfl, double t) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->dt_fixed = dt_fixed;
+    ctl->cfl = cfl;
+    ctl->t = t;
+  }
+}
+
+// Clears one c_max slot (used before a standalone c_max reduction).
+__global__ void k_clear_slot(Control* ctl, int slot) {
+  if (threadIdx.x < 3 && blockIdx.x == 0) ctl->cm[slot][threadIdx.x] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Variant table.
+// ---------------------------------------------------------------------------
+struct StageVariant {
+  int ndim, mhd, tx, ty, tz, nt, ngrp;
+  const void* fn;
+  void (*launch)(const StageParams&, int grid, hipStream_t);
+};
+
+template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP>
+static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP>), dim3(grid), dim3(NT), 0, s, p);
+}
+
+#define AMRVAC_VARIANT(ND, M, TX, TY, TZ, NT, NGRP)                                 \
+  {ND, M, TX, TY, TZ, NT, NGRP, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP>}
+
+static const StageVariant g_variants[] = {
+    // 1D
+    AMRVAC_VARIANT(1, false, 128, 1, 1, 128, 1),
+    AMRVAC_VARIANT(1, false, 64, 1, 1, 64, 1),
+    AMRVAC_VARIANT(1, true, 128, 1, 1, 128, 1),
+    AMRVAC_VARIANT(1, true, 64, 1, 1, 64, 1),
+    // 2D
+    AMRVAC_VARIANT(2, false, 16, 16, 1, 256, 1),
+    AMRVAC_VARIANT(2, false, 32, 8, 1, 256, 1),
+    AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 1),
+    AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 2),
+    AMRVAC_VARIANT(2, true, 32, 8, 1, 256, 2),
+    // 3D
+    AMRVAC_VARIANT(3, false, 8, 8, 8, 512, 2),
+    AMRVAC_VARIANT(3, false, 8, 8, 4, 256, 1),
+    AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 2),
+    AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 2),
+    AMRVAC_VARIANT(3, true, 8, 8, 8, 256, 2),
+};
+
+const StageVariant* stage_variants(int* count) {
+  *count = (int)(sizeof(g_variants) / sizeof(g_variants[0]));
+  return g_variants;
+}
+
+template <int NDIM, bool MHD>
+static void launch_cmax_t(const CmaxParams& p, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_cmax<NDIM, MHD>), dim3(grid), dim3(256), 0, s, p);
+}
+
+void launch_cmax(int ndim, int mhd, const CmaxParams& p, int grid, hipStream_t s) {
+  if (ndim == 1) mhd ? launch_cmax_t<1, true>(p, grid, s) : launch_cmax_t<1, false>(p, grid, s);
+  if (ndim == 2) mhd ? launch_cmax_t<2, true>(p, grid, s) : launch_cmax_t<2, false>(p, grid, s);
+  if (ndim == 3) mhd ? launch_cmax_t<3, true>(p, grid, s) : launch_cmax_t<3, false>(p, grid, s);
+}
+
+void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo, int clear_hi,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, s, ctl, dxtab, ndim, clear_lo, clear_hi);
+}
+
+void launch_set_control(Control* ctl, double dt_fixed, double cfl, double t, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_control, dim3(1), dim3(64), 0, s, ctl, dt_fixed, cfl, t);
+}
+
+void launch_clear_slot(Control* ctl, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_slot, dim3(1), dim3(64), 0, s, ctl, slot);
+}
+
+}  // namespace amrvac

@@ -1,0 +1,705 @@
+// Host runtime behind the C ABI of include/amrvac.h: argument validation,
+// block and tile tables, context-owned scratch, Shu-Osher stage recipes
+// (Sect. 2.3), per-block and batched (persistent, graph-replayed) execution.
+#include "amrvac.h"
+#include "amrvac_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+namespace amrvac {
+
+struct StageVariant {
+  int ndim, mhd, tx, ty, tz, nt, ngrp;
+  const void* fn;
+  void (*launch)(const StageParams&, int grid, hipStream_t);
+};
+const StageVariant* stage_variants(int* count);
+void launch_cmax(int ndim, int mhd, const CmaxParams& p, int grid, hipStream_t s);
+void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo, int clear_hi,
+                       hipStream_t s);
+void launch_clear_slot(Control* ctl, int slot, hipStream_t s);
+void launch_set_control(Control* ctl, double dt_fixed, double cfl, double t, hipStream_t s);
+
+}  // namespace amrvac
+
+using namespace amrvac;
+
+static const char* g_noctx_error = "";
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct amrvac_ctx {
+  amrvac_config cfg{};
+  int nvar = 0;
+  int exec = AMRVAC_EXEC_BATCHED;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  int device = 0;
+  int ncu = 0;
+  std::string err;
+
+  // blocks
+  std::vector<amrvac_block> hb;
+  std::vector<BlockDev> hdev;
+  BlockDev* d_blocks = nullptr;
+  long long total_cells = 0;    // interior cells of all blocks
+  long long slot_stride = 0;    // doubles per scratch slot
+
+  // tiles of the chosen variant
+  const StageVariant* var = nullptr;
+  std::vector<Tile> htiles;
+  Tile* d_tiles = nullptr;
+  std::vector<int> blk_tile_begin, blk_tile_count;
+  int grid_batched = 0;
+
+  // scratch
+  double* d_scr = nullptr;
+  int nslots = 0;
+
+  // control
+  Control* d_ctl = nullptr;
+  double* d_dxtab = nullptr;
+  int ndx = 0;
+  double** d_rhs_ptrs = nullptr;
+  std::vector<double*> hrhs;
+
+  std::map<int, GraphEntry> graphs;
+};
+
+static amrvac_status fail(amrvac_ctx* c, amrvac_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                     \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? AMRVAC_ERR_NOMEM : AMRVAC_ERR_DEVICE,       \
+                  "%s failed: %s", #expr, hipGetErrorString(e_));                              \
+  } while (0)
+
+static void drop_graphs(amrvac_ctx* c) {
+  for (auto& kv : c->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  c->graphs.clear();
+}
+
+static void free_tables(amrvac_ctx* c) {
+  if (c->d_blocks) (void)hipFree(c->d_blocks);
+  if (c->d_tiles) (void)hipFree(c->d_tiles);
+  if (c->d_scr) (void)hipFree(c->d_scr);
+  if (c->d_dxtab) (void)hipFree(c->d_dxtab);
+  if (c->d_rhs_ptrs) (void)hipFree(c->d_rhs_ptrs);
+  c->d_blocks = nullptr;
+  c->d_tiles = nullptr;
+  c->d_scr = nullptr;
+  c->d_dxtab = nullptr;
+  c->d_rhs_ptrs = nullptr;
+  c->nslots = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Tables
+// ---------------------------------------------------------------------------
+static uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  auto spread = [](uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+  };
+  return spread(x) | (spread(y) << 1) | (spread(z) << 2);
+}
+
+static const StageVariant* pick_variant(amrvac_ctx* c, int want) {
+  int nv = 0;
+  const StageVariant* v = stage_variants(&nv);
+  int k = 0;
+  for (int i = 0; i < nv; ++i) {
+    if (v[i].ndim == c->cfg.ndim && v[i].mhd == (c->cfg.physics == AMRVAC_MHD)) {
+      if (k == want) return &v[i];
+      ++k;
+    }
+  }
+  return nullptr;
+}
+
+// Build the tile list of the current variant: blocks ordered largest first,
+// then along a Morton curve of their origins; tiles of a block contiguous and
+// Morton-ordered.
+static amrvac_status build_tiles(amrvac_ctx* c) {
+  const StageVariant* V = c->var;
+  const int T[3] = {V->tx, V->ty, V->tz};
+  const int nb = (int)c->hb.size();
+  std::vector<int> order(nb);
+  std::vector<uint64_t> key(nb);
+  std::vector<long long> cells(nb);
+  for (int b = 0; b < nb; ++b) {
+    order[b] = b;
+    const amrvac_block& q = c->hb[b];
+    uint32_t o[3] = {0, 0, 0};
+    for (int d = 0; d < c->cfg.ndim; ++d) {
+      double x = q.xlo[d] / q.dx[d];
+      long long xi = (long long)std::llround(x) + (1ll << 20);
+      o[d] = (uint32_t)std::max(0ll, std::min(xi, (1ll << 21) - 1));
+    }
+    key[b] = morton3(o[0], o[1], o[2]);
+    cells[b] = (long long)q.n[0] * q.n[1] * q.n[2];
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (cells[a] != cells[b]) return cells[a] > cells[b];
+    return key[a] < key[b];
+  });
+  c->htiles.clear();
+  c->blk_tile_begin.assign(nb, 0);
+  c->blk_tile_count.assign(nb, 0);
+  for (int b : order) {
+    const amrvac_block& q = c->hb[b];
+    int nt[3];
+    for (int d = 0; d < 3; ++d) nt[d] = (q.n[d] + T[d] - 1) / T[d];
+    std::vector<std::pair<uint64_t, Tile>> tl;
+    for (int z = 0; z < nt[2]; ++z)
+      for (int y = 0; y < nt[1]; ++y)
+        for (int x = 0; x < nt[0]; ++x) {
+          Tile t;
+          t.block = b;
+          t.o[0] = x * T[0];
+          t.o[1] = y * T[1];
+          t.o[2] = z * T[2];
+          tl.push_back({morton3(x, y, z), t});
+        }
+    std::stable_sort(tl.begin(), tl.end(),
+                     [](const std::pair<uint64_t, Tile>& a, const std::pair<uint64_t, Tile>& b) {
+                       return a.first < b.first;
+                     });
+    c->blk_tile_begin[b] = (int)c->htiles.size();
+    c->blk_tile_count[b] = (int)tl.size();
+    for (auto& p : tl) c->htiles.push_back(p.second);
+  }
+  if (c->d_tiles) (void)hipFree(c->d_tiles);
+  c->d_tiles = nullptr;
+  HIP_TRY(c, hipMalloc(&c->d_tiles, sizeof(Tile) * c->htiles.size()));
+  HIP_TRY(c, hipMemcpyAsync(c->d_tiles, c->htiles.data(), sizeof(Tile) * c->htiles.size(),
+                            hipMemcpyHostToDevice, c->stream));
+  int per_cu = 0;
+  HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V->fn, V->nt, 0));
+  if (per_cu < 1) return fail(c, AMRVAC_ERR_DEVICE, "stage kernel cannot be resident");
+  c->grid_batched = (int)std::min<long long>((long long)per_cu * c->ncu, (long long)c->htiles.size());
+  // the tile list is copied from host memory that lives in the context
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return AMRVAC_OK;
+}
+
+static amrvac_status ensure_slots(amrvac_ctx* c, int n) {
+  if (c->nslots >= n) return AMRVAC_OK;
+  drop_graphs(c);
+  if (c->d_scr) (void)hipFree(c->d_scr);
+  c->d_scr = nullptr;
+  c->nslots = 0;
+  size_t bytes = sizeof(double) * (size_t)c->slot_stride * (size_t)n;
+  HIP_TRY(c, hipMalloc(&c->d_scr, bytes));
+  c->nslots = n;
+  return AMRVAC_OK;
+}
+
+static StateTable state_table(const amrvac_ctx* c) {
+  StateTable st;
+  st.blocks = c->d_blocks;
+  st.scr = c->d_scr;
+  st.slot_stride = c->slot_stride;
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// Stage recipes (Sect. 2.3).  Buffer ids: 0 = caller's u (U^n on entry,
+// U^{n+1} on exit); 1 = A, 2 = B, 3 = S (scratch slots 0..2).
+// ---------------------------------------------------------------------------
+struct Recipe {
+  int in;
+  int nsrc;
+  int src[MAX_SRC];
+  double a[MAX_SRC];
+  double b;
+  int dst;
+  int snsrc;
+  int ssrc[MAX_SRC];
+  double sa[MAX_SRC];
+  double sb;
+  int sdst;
+};
+
+static int scheme_stages(int scheme) { return scheme == AMRVAC_RK3 ? 3 : scheme == AMRVAC_SSPRK43 ? 4 : 5; }
+
+// SSPRK(5,4) coefficients as printed (Sect. 2.3.2); alpha_50 renormalised so
+// the row sums to one.
+static const double A20 = 0.44437049406734, A21 = 0.55562950593266;
+static const double A30 = 0.62010185138540, A32 = 0.37989814861460;
+static const double A40 = 0.17807995410773, A43 = 0.82192004589227;
+static const double A52 = 0.51723167208978, A53 = 0.12759831133288, A54 = 0.34833675773694;
+static const double B10 = 0.39175222700392, B21 = 0.36841059262959, B32 = 0.25189177424738;
+static const double B43 = 0.54497475021237, B53 = 0.08460416338212, B54 = 0.22600748319395;
+
+static Recipe rc(int in, std::initializer_list<std::pair<int, double>> srcs, double b, int dst) {
+  Recipe r{};
+  r.in = in;
+  r.nsrc = 0;
+  for (auto& s : srcs) {
+    r.src[r.nsrc] = s.first;
+    r.a[r.nsrc] = s.second;
+    ++r.nsrc;
+  }
+  r.b = b;
+  r.dst = dst;
+  r.sdst = -1;
+  r.snsrc = 0;
+  return r;
+}
+
+static Recipe with_s(Recipe r, std::initializer_list<std::pair<int, double>> srcs, double sb, int sdst) {
+  r.snsrc = 0;
+  for (auto& s : srcs) {
+    r.ssrc[r.snsrc] = s.first;
+    r.sa[r.snsrc] = s.second;
+    ++r.snsrc;
+  }
+  r.sb = sb;
+  r.sdst = sdst;
+  return r;
+}
+
+// Stage recipes with state buffers U (id u0, the step's input and output),
+// and scratch ids A, B, S.
+static std::vector<Recipe> recipes(int scheme, int U, int A, int Bf, int S, int out) {
+  std::vector<Recipe> r;
+  if (scheme == AMRVAC_RK3) {
+    r.push_back(rc(U, {{U, 1.0}}, 1.0, A));
+    r.push_back(rc(A, {{U, 0.75}, {A, 0.25}}, 0.25, Bf));
+    r.push_back(rc(Bf, {{U, 1.0 / 3.0}, {Bf, 2.0 / 3.0}}, 2.0 / 3.0, out));
+  } else if (scheme == AMRVAC_SSPRK43) {
+    r.push_back(rc(U, {{U, 1.0}}, 0.5, A));
+    r.push_back(rc(A, {{A, 1.0}}, 0.5, Bf));
+    r.push_back(rc(Bf, {{U, 2.0 / 3.0}, {Bf, 1.0 / 3.0}}, 1.0 / 6.0, A));
+    r.push_back(rc(A, {{A, 1.0}}, 0.5, out));
+  } else {
+    const double A50 = 1.0 - (A52 + A53 + A54);
+    r.push_back(rc(U, {{U, 1.0}}, B10, A));                                   // U1 -> A
+    r.push_back(rc(A, {{U, A20}, {A, A21}}, B21, Bf));                        // U2 -> B
+    r.push_back(with_s(rc(Bf, {{U, A30}, {Bf, A32}}, B32, A),                 // U3 -> A
+                       {{U, A50}, {Bf, A52}}, 0.0, S));                       // S = a50 U0 + a52 U2
+    r.push_back(with_s(rc(A, {{U, A40}, {A, A43}}, B43, Bf),                  // U4 -> B
+                       {{S, 1.0}, {A, A53}}, B53, S));                        // S += a53 U3 + dt b53 L(U3)
+    r.push_back(rc(Bf, {{S, 1.0}, {Bf, A54}}, B54, out));                     // U5 -> out
+  }
+  return r;
+}
+
+static StageParams make_params(const amrvac_ctx* c, const Recipe& r, int cm_in, int cm_out,
+                               int cm_reset) {
+  StageParams p{};
+  p.st = state_table(c);
+  p.tiles = c->d_tiles;
+  p.tile_begin = 0;
+  p.ntiles = (int)c->htiles.size();
+  p.ctl = c->d_ctl;
+  p.gamma = c->cfg.gamma;
+  p.in = r.in;
+  p.mode = 0;
+  p.cm_in = cm_in;
+  p.cm_out = cm_out;
+  p.cm_reset = cm_reset;
+  p.nsrc = r.nsrc;
+  for (int q = 0; q < MAX_SRC; ++q) {
+    p.src[q] = q < r.nsrc ? r.src[q] : 0;
+    p.a[q] = q < r.nsrc ? r.a[q] : 0.0;
+    p.ssrc[q] = q < r.snsrc ? r.ssrc[q] : 0;
+    p.sa[q] = q < r.snsrc ? r.sa[q] : 0.0;
+  }
+  p.b = r.b;
+  p.dst = r.dst;
+  p.snsrc = r.snsrc;
+  p.sb = r.sb;
+  p.sdst = r.sdst;
+  p.rhs_out = nullptr;
+  return p;
+}
+
+// Launch one stage in the context's execution form.
+static void launch_stage(amrvac_ctx* c, StageParams p, int exec, hipStream_t s) {
+  if (exec == AMRVAC_EXEC_BATCHED) {
+    c->var->launch(p, c->grid_batched, s);
+    return;
+  }
+  const int nb = (int)c->hb.size();
+  for (int b = 0; b < nb; ++b) {
+    StageParams q = p;
+    q.tile_begin = c->blk_tile_begin[b];
+    q.ntiles = c->blk_tile_count[b];
+    // the slot reset must run once, on the first launch only
+    if (b > 0) q.cm_reset = -1;
+    c->var->launch(q, q.ntiles, s);
+  }
+}
+
+static void launch_cmax_of(amrvac_ctx* c, int buf, int slot, hipStream_t s) {
+  CmaxParams q{};
+  q.st = state_table(c);
+  q.tiles = c->d_tiles;
+  q.ntiles = (int)c->htiles.size();
+  q.tx = c->var->tx;
+  q.ty = c->var->ty;
+  q.tz = c->var->tz;
+  q.ctl = c->d_ctl;
+  q.gamma = c->cfg.gamma;
+  q.in = buf;
+  q.slot = slot;
+  launch_clear_slot(c->d_ctl, slot, s);
+  int grid = (int)std::min<long long>((long long)c->ncu * 8, (long long)c->htiles.size());
+  launch_cmax(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD, q, grid, s);
+}
+
+// One step: dt, then the s stages.  c_max slots: slot 0 holds c_max(U^n);
+// stage i (1-based) reads slot i-1 and accumulates slot i (slot 0 for the
+// last stage, giving c_max(U^{n+1}) for the next step); stage 2 clears slot
+// 0 once stage 1 no longer needs it.
+static void enqueue_step(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U, int A, int Bf,
+                         int S, int out) {
+  const int ns = scheme_stages(scheme);
+  launch_step_begin(c->d_ctl, c->d_dxtab, c->cfg.ndim, 1, ns - 1, s);
+  std::vector<Recipe> r = recipes(scheme, U, A, Bf, S, out);
+  for (int i = 1; i <= ns; ++i) {
+    const int cm_in = i - 1;
+    const int cm_out = (i == ns) ? 0 : i;
+    const int cm_reset = (i == 2) ? 0 : -1;
+    launch_stage(c, make_params(c, r[i - 1], cm_in, cm_out, cm_reset), exec, s);
+  }
+}
+
+static amrvac_status read_status(amrvac_ctx* c) {
+  int err = 0;
+  HIP_TRY(c, hipMemcpyAsync(&err, &c->d_ctl->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (err) {
+    int zero = 0;
+    HIP_TRY(c, hipMemcpy(&c->d_ctl->err, &zero, sizeof(int), hipMemcpyHostToDevice));
+    return fail(c, AMRVAC_ERR_NONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or non-finite)");
+  }
+  return AMRVAC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Internal entry points used by the adjoint (adjoint.cpp).
+// ---------------------------------------------------------------------------
+namespace amrvac {
+amrvac_status ctx_ensure_slots(amrvac_ctx* c, int n) { return ensure_slots(c, n); }
+void ctx_enqueue_step(amrvac_ctx* c, int scheme, int U, int A, int Bf, int S, int out) {
+  enqueue_step(c, scheme, AMRVAC_EXEC_BATCHED, c->stream, U, A, Bf, S, out);
+}
+void ctx_cmax_of(amrvac_ctx* c, int buf, int slot) { launch_cmax_of(c, buf, slot, c->stream); }
+hipStream_t ctx_stream(amrvac_ctx* c) { return c->stream; }
+StateTable ctx_state(amrvac_ctx* c) { return state_table(c); }
+const Tile* ctx_tiles(amrvac_ctx* c, int* ntiles, int* tx, int* ty, int* tz) {
+  *ntiles = (int)c->htiles.size();
+  *tx = c->var->tx;
+  *ty = c->var->ty;
+  *tz = c->var->tz;
+  return c->d_tiles;
+}
+Control* ctx_control(amrvac_ctx* c) { return c->d_ctl; }
+int ctx_ncu(amrvac_ctx* c) { return c->ncu; }
+const amrvac_config& ctx_config(amrvac_ctx* c) { return c->cfg; }
+const std::vector<amrvac_block>& ctx_blocks(amrvac_ctx* c) { return c->hb; }
+long long ctx_slot_stride(amrvac_ctx* c) { return c->slot_stride; }
+amrvac_status ctx_fail(amrvac_ctx* c, amrvac_status st, const char* msg) { return fail(c, st, "%s", msg); }
+amrvac_status ctx_read_status(amrvac_ctx* c) { return read_status(c); }
+}  // namespace amrvac
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+static bool config_ok(const amrvac_config* cfg) {
+  return cfg && cfg->ndim >= 1 && cfg->ndim <= 3 &&
+         (cfg->physics == AMRVAC_HD || cfg->physics == AMRVAC_MHD) &&
+         (cfg->exec == AMRVAC_EXEC_PER_BLOCK || cfg->exec == AMRVAC_EXEC_BATCHED) &&
+         std::isfinite(cfg->gamma) && cfg->gamma > 1.0;
+}
+
+// Host-only validation shared by amrvac_set_blocks and
+// amrvac_validate_blocks; writes the first violation into msg.
+static bool blocks_ok(int nd, const amrvac_block* blocks, int nblocks, std::string& msg) {
+  char buf[256];
+  auto bad = [&](const char* fmt, int a, int b2, int c2) {
+    snprintf(buf, sizeof(buf), fmt, a, b2, c2);
+    msg = buf;
+    return false;
+  };
+  if (!blocks || nblocks < 1) return bad("no blocks (%d %d %d)", nblocks, 0, 0);
+  for (int b = 0; b < nblocks; ++b) {
+    const amrvac_block& q = blocks[b];
+    if (!q.u) return bad("block %d: u is NULL%s", b, 0, 0);
+    for (int d = 0; d < 3; ++d) {
+      if (d < nd) {
+        if (q.n[d] < NG) return bad("block %d: n[%d] = %d < 3", b, d, q.n[d]);
+        if (!std::isfinite(q.dx[d]) || !(q.dx[d] > 0.0))
+          return bad("block %d: dx[%d] must be finite and > 0 (%d)", b, d, 0);
+        for (int s = 0; s < 2; ++s) {
+          int nb = q.nbr[2 * d + s];
+          if (nb < -1 || nb >= nblocks) return bad("block %d: neighbour %d = %d out of range", b, 2 * d + s, nb);
+          if (nb >= 0) {
+            const amrvac_block& r = blocks[nb];
+            if (r.nbr[2 * d + (1 - s)] != b)
+              return bad("block %d face %d: neighbour %d does not point back", b, 2 * d + s, nb);
+            for (int e = 0; e < nd; ++e)
+              if (e != d && r.n[e] != q.n[e])
+                return bad("block %d face %d: face size differs from block %d", b, 2 * d + s, nb);
+          }
+        }
+      } else {
+        if (q.n[d] != 1) return bad("block %d: n[%d] must be 1 for an inactive direction (%d)", b, d, q.n[d]);
+        if (q.nbr[2 * d] != -1 || q.nbr[2 * d + 1] != -1)
+          return bad("block %d: inactive direction %d has neighbours (%d)", b, d, 0);
+      }
+    }
+  }
+  return true;
+}
+
+extern "C" {
+
+int amrvac_abi_version(void) { return AMRVAC_ABI_VERSION; }
+
+amrvac_status amrvac_create(const amrvac_config* cfg, void* hip_stream, amrvac_ctx** out) {
+  if (!out) {
+    g_noctx_error = "amrvac_create: out is NULL";
+    return AMRVAC_ERR_INVALID;
+  }
+  *out = nullptr;
+  if (!cfg) {
+    g_noctx_error = "amrvac_create: cfg is NULL";
+    return AMRVAC_ERR_INVALID;
+  }
+  if (!config_ok(cfg)) {
+    g_noctx_error = "amrvac_create: invalid config (ndim 1..3, physics HD/MHD, exec, gamma > 1)";
+    return AMRVAC_ERR_INVALID;
+  }
+  amrvac_ctx* c = new amrvac_ctx();
+  c->cfg = *cfg;
+  c->exec = cfg->exec;
+  c->nvar = cfg->physics == AMRVAC_MHD ? 8 : 2 + cfg->ndim;
+  c->stream = (hipStream_t)hip_stream;
+  c->var = pick_variant(c, 0);
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc(&c->d_ctl, sizeof(Control));
+  if (e == hipSuccess) e = hipMemset(c->d_ctl, 0, sizeof(Control));
+  if (e != hipSuccess || !c->var) {
+    g_noctx_error = "amrvac_create: HIP device setup failed";
+    if (c->d_ctl) (void)hipFree(c->d_ctl);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    delete c;
+    return e == hipErrorOutOfMemory ? AMRVAC_ERR_NOMEM : AMRVAC_ERR_DEVICE;
+  }
+  *out = c;
+  return AMRVAC_OK;
+}
+
+amrvac_status amrvac_validate_blocks(const amrvac_config* cfg, const amrvac_block* blocks, int nblocks,
+                                     char* msg, int msglen) {
+  std::string m;
+  amrvac_status st = AMRVAC_OK;
+  if (!config_ok(cfg)) {
+    m = "invalid config (ndim 1..3, physics HD/MHD, exec, gamma > 1)";
+    st = AMRVAC_ERR_INVALID;
+  } else if (!blocks_ok(cfg->ndim, blocks, nblocks, m)) {
+    st = AMRVAC_ERR_INVALID;
+  }
+  if (msg && msglen > 0) {
+    snprintf(msg, (size_t)msglen, "%s", m.c_str());
+  }
+  return st;
+}
+
+amrvac_status amrvac_set_blocks(amrvac_ctx* c, const amrvac_block* blocks, int nblocks) {
+  if (!c) return AMRVAC_ERR_INVALID;
+  const int nd = c->cfg.ndim;
+  {
+    std::string m;
+    if (!blocks_ok(nd, blocks, nblocks, m)) return fail(c, AMRVAC_ERR_INVALID, "set_blocks: %s", m.c_str());
+  }
+  drop_graphs(c);
+  free_tables(c);
+  c->hb.assign(blocks, blocks + nblocks);
+  c->hdev.resize(nblocks);
+  long long off = 0;
+  std::vector<double> dxt;
+  for (int b = 0; b < nblocks; ++b) {
+    const amrvac_block& q = blocks[b];
+    BlockDev& D = c->hdev[b];
+    D.u = q.u;
+    D.cells = (long long)q.n[0] * q.n[1] * q.n[2];
+    D.off = off;
+    off += D.cells * c->nvar;
+    for (int d = 0; d < 3; ++d) {
+      D.n[d] = q.n[d];
+      D.g[d] = d < nd ? NG : 0;
+      D.P[d] = q.n[d] + 2 * D.g[d];
+      D.dx[d] = d < nd ? q.dx[d] : 1.0;
+      D.inv_dx[d] = 1.0 / D.dx[d];
+    }
+    for (int f = 0; f < 6; ++f) D.nbr[f] = q.nbr[f];
+    bool seen = false;
+    for (size_t k = 0; k < dxt.size(); k += 3)
+      if (dxt[k] == D.dx[0] && dxt[k + 1] == D.dx[1] && dxt[k + 2] == D.dx[2]) seen = true;
+    if (!seen) {
+      dxt.push_back(D.dx[0]);
+      dxt.push_back(D.dx[1]);
+      dxt.push_back(D.dx[2]);
+    }
+  }
+  c->total_cells = off / c->nvar;
+  c->slot_stride = (off + 31) / 32 * 32;
+  c->ndx = (int)(dxt.size() / 3);
+  HIP_TRY(c, hipMalloc(&c->d_blocks, sizeof(BlockDev) * nblocks));
+  HIP_TRY(c, hipMemcpyAsync(c->d_blocks, c->hdev.data(), sizeof(BlockDev) * nblocks,
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMalloc(&c->d_dxtab, sizeof(double) * dxt.size()));
+  HIP_TRY(c, hipMemcpyAsync(c->d_dxtab, dxt.data(), sizeof(double) * dxt.size(), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMalloc(&c->d_rhs_ptrs, sizeof(double*) * nblocks));
+  amrvac_status st = build_tiles(c);
+  if (st != AMRVAC_OK) return st;
+  // control: ndx
+  Control h{};
+  HIP_TRY(c, hipMemcpyAsync(&h, c->d_ctl, sizeof(Control), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  h.ndx = c->ndx;
+  HIP_TRY(c, hipMemcpy(c->d_ctl, &h, sizeof(Control), hipMemcpyHostToDevice));
+  return AMRVAC_OK;
+}
+
+amrvac_status amrvac_set_exec(amrvac_ctx* c, int exec) {
+  if (!c) return AMRVAC_ERR_INVALID;
+  if (exec != AMRVAC_EXEC_PER_BLOCK && exec != AMRVAC_EXEC_BATCHED)
+    return fail(c, AMRVAC_ERR_INVALID, "set_exec: unknown execution form %d", exec);
+  c->exec = exec;
+  return AMRVAC_OK;
+}
+
+amrvac_status amrvac_fd_rhs(amrvac_ctx* c, double* const* rhs, double* cmax_out) {
+  if (!c) return AMRVAC_ERR_INVALID;
+  if (c->hb.empty()) return fail(c, AMRVAC_ERR_INVALID, "fd_rhs: no blocks set");
+  if (!rhs) return fail(c, AMRVAC_ERR_INVALID, "fd_rhs: rhs is NULL");
+  const int nb = (int)c->hb.size();
+  for (int b = 0; b < nb; ++b)
+    if (!rhs[b]) return fail(c, AMRVAC_ERR_INVALID, "fd_rhs: rhs[%d] is NULL", b);
+  c->hrhs.assign(rhs, rhs + nb);
+  HIP_TRY(c, hipMemcpyAsync(c->d_rhs_ptrs, c->hrhs.data(), sizeof(double*) * nb, hipMemcpyHostToDevice,
+                            c->stream));
+  launch_cmax_of(c, 0, 0, c->stream);
+  Recipe r = rc(0, {{0, 1.0}}, 0.0, 0);
+  StageParams p = make_params(c, r, 0, -1, -1);
+  p.mode = 1;
+  p.rhs_out = c->d_rhs_ptrs;
+  launch_stage(c, p, c->exec, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  if (cmax_out) {
+    unsigned long long cm[3];
+    HIP_TRY(c, hipMemcpyAsync(cm, c->d_ctl->cm[0], sizeof(cm), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int d = 0; d < 3; ++d) {
+      double v;
+      std::memcpy(&v, &cm[d], sizeof(double));
+      cmax_out[d] = v;
+    }
+    return read_status(c);
+  }
+  return AMRVAC_OK;
+}
+
+amrvac_status amrvac_ssprk_step(amrvac_ctx* c, int scheme, double cfl, const double* dt_fixed,
+                                int nsteps, double* t_inout) {
+  if (!c) return AMRVAC_ERR_INVALID;
+  if (c->hb.empty()) return fail(c, AMRVAC_ERR_INVALID, "ssprk_step: no blocks set");
+  if (scheme < AMRVAC_RK3 || scheme > AMRVAC_SSPRK54)
+    return fail(c, AMRVAC_ERR_INVALID, "ssprk_step: unknown scheme %d", scheme);
+  if (nsteps < 0) return fail(c, AMRVAC_ERR_INVALID, "ssprk_step: nsteps < 0");
+  if (dt_fixed) {
+    if (!std::isfinite(*dt_fixed) || !(*dt_fixed > 0.0))
+      return fail(c, AMRVAC_ERR_INVALID, "ssprk_step: dt must be finite and > 0");
+  } else if (!std::isfinite(cfl) || !(cfl > 0.0)) {
+    return fail(c, AMRVAC_ERR_INVALID, "ssprk_step: cfl must be finite and > 0");
+  }
+  amrvac_status st = ensure_slots(c, 3);
+  if (st != AMRVAC_OK) return st;
+  launch_set_control(c->d_ctl, dt_fixed ? *dt_fixed : 0.0, cfl, t_inout ? *t_inout : 0.0, c->stream);
+  if (nsteps > 0) launch_cmax_of(c, 0, 0, c->stream);
+  const int exec = c->exec;
+  if (exec == AMRVAC_EXEC_BATCHED && nsteps > 0) {
+    GraphEntry& g = c->graphs[scheme];
+    if (!g.exec) {
+      HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+      enqueue_step(c, scheme, exec, c->cap, 0, 1, 2, 3, 0);
+      hipError_t e = hipStreamEndCapture(c->cap, &g.graph);
+      if (e != hipSuccess) {
+        g.graph = nullptr;
+        return fail(c, AMRVAC_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+      }
+      HIP_TRY(c, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    }
+    for (int it = 0; it < nsteps; ++it) HIP_TRY(c, hipGraphLaunch(g.exec, c->stream));
+  } else {
+    for (int it = 0; it < nsteps; ++it) enqueue_step(c, scheme, exec, c->stream, 0, 1, 2, 3, 0);
+  }
+  HIP_TRY(c, hipGetLastError());
+  if (t_inout) {
+    double t = 0.0;
+    HIP_TRY(c, hipMemcpyAsync(&t, &c->d_ctl->t, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    st = read_status(c);
+    *t_inout = t;
+    return st;
+  }
+  return AMRVAC_OK;
+}
+
+amrvac_status amrvac_sync(amrvac_ctx* c) {
+  if (!c) return AMRVAC_ERR_INVALID;
+  return read_status(c);
+}
+
+const char* amrvac_last_error(const amrvac_ctx* c) {
+  if (!c) return g_noctx_error;
+  return c->err.c_str();
+}
+
+void amrvac_destroy(amrvac_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  free_tables(c);
+  if (c->d_ctl) (void)hipFree(c->d_ctl);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  delete c;
+}
+
+}  // extern "C"
