@@ -1,0 +1,184 @@
+"""Benchmark of the FP64 FD-MP5 / global-LF / SSPRK(5,4) hot path on one MI355X.
+
+Workload: 3D ideal MHD, 4096 independent blocks of 32^3 : 16^3 : 8^3 cells
+(1 : 2 : 4 by count; 25,160,192 interior cells), ghosts filled from a seeded
+8-mode field (amplitude 0.1) on rho = 1, p = 1, B = (1, 0, 0), CFL 0.4.
+
+A step is one full SSPRK(5,4) step over every block (5 fused stage launches
+plus the on-device dt computation), inputs resident in HBM.  The headline
+value is the batched form (one persistent launch per stage, replayed from a
+HIP graph); the plain per-block launch on the same block list is timed beside
+it.  One JSON line is printed.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 2]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MHD cell-updates/s (batched vs per-block, FP64) + adjoint/forward time ratio"
+
+# Algorithmic FP64 work of one cell in one stage of 3D ideal MHD (the
+# operation count of the scheme as defined, each +, -, *, /, sqrt, min, max
+# counted once; derivation in the design notes):
+#   per direction: primitive recovery 19, flux 30, split 40,
+#   8 variables x (2 MP5 x 68 + 1), difference 24           -> 1209
+#   three directions                                          -> 3627
+#   stage combination 56, next-stage c_max 67                 -> 3750
+FLOPS_PER_CELL_STAGE_MHD3D = 3750
+# Algorithmic HBM bytes per cell per SSPRK(5,4) step: 17 state passes x 8
+# variables x 8 bytes (low-storage form: 2+3+4+5+3 passes).
+BYTES_PER_CELL_STEP_MHD3D = 17 * 8 * 8
+PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+STAGES = 5
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "runtime.cpp", "amrvac_internal.h"):
+        with open(os.path.join(ROOT, "paper_1407_2052_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per stage launch from committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs, if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "stage_kernel_mhd3d_uneven4096_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(bs_full, min_seconds=10.0, max_steps=4):
+    """The oracle as it stands, on a bounded sample of the same block list:
+    512 blocks drawn with the same 1:2:4 size mix, SSPRK(5,4) steps until at
+    least `min_seconds` of wall time."""
+    import numpy as np
+    import oracle
+    from paper_1407_2052_amd import inputs
+
+    rng = np.random.default_rng(11)
+    sizes = bs_full.n[:, 0]
+    idx = []
+    for s, k in ((32, 73), (16, 146), (8, 293)):
+        pool = np.where(sizes == s)[0]
+        idx.extend(rng.choice(pool, min(k, len(pool)), replace=False).tolist())
+    idx = np.array(sorted(idx))
+    sub = bs_full.copy()
+    sub.u = [bs_full.u[i] for i in idx]
+    sub.n, sub.dx, sub.xlo, sub.nbr = bs_full.n[idx], bs_full.dx[idx], bs_full.xlo[idx], bs_full.nbr[idx]
+    cells = sub.interior_cells()
+    t0 = time.perf_counter()
+    steps = 0
+    cur = sub
+    while steps < max_steps:
+        cur, _ = oracle.run(cur, oracle.SSPRK54, 1, cfl=0.4)
+        steps += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    el = time.perf_counter() - t0
+    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{len(idx)} of the 4096 blocks (32^3:16^3:8^3 = 73:146:293, {cells} cells), "
+                      f"{steps} SSPRK(5,4) steps, {el:.1f} s wall, OpenMP over blocks"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--per-block-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-block", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs (--gpus > 1) are not "
+              "supported (the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1407_2052_amd import amrvac, inputs
+
+    print("bench: generating 3D MHD uneven block list (4096 blocks)", file=sys.stderr, flush=True)
+    bs = inputs.uneven_3d()
+    cells = bs.interior_cells()
+    torch.cuda.set_device(0)
+    ctx, flat, views = amrvac.context_for(bs, amrvac.EXEC_BATCHED)
+    stream = torch.cuda.current_stream()
+
+    def timed(nsteps, warmup):
+        if warmup:
+            ctx.ssprk_step(amrvac.SSPRK54, warmup, cfl=0.4, t=None)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.ssprk_step(amrvac.SSPRK54, nsteps, cfl=0.4, t=None)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ctx.sync()
+        return e0.elapsed_time(e1) / 1e3
+
+    print(f"bench: batched warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
+    el = timed(args.steps, args.warmup)
+    value = cells * args.steps / el
+    ms_per_step = 1e3 * el / args.steps
+    stage_s = el / (args.steps * STAGES)   # average stage-launch duration (step control included)
+
+    per_block = None
+    if not args.no_per_block:
+        print(f"bench: per-block launch, timed {args.per_block_steps}", file=sys.stderr, flush=True)
+        ctx.set_exec(amrvac.EXEC_PER_BLOCK)
+        elp = timed(args.per_block_steps, 1)
+        per_block = {"value": cells * args.per_block_steps / elp, "ms_per_step": 1e3 * elp / args.per_block_steps,
+                     "steps": args.per_block_steps}
+        ctx.set_exec(amrvac.EXEC_BATCHED)
+    ctx.close()
+
+    flops = FLOPS_PER_CELL_STAGE_MHD3D * cells
+    achieved = flops / stage_s / 1e12
+    traffic = measured_traffic()
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                "kernel": "k_stage<3,MHD> (fused SSPRK stage)",
+                "hbm_algorithmic_GBs": BYTES_PER_CELL_STEP_MHD3D * cells / STAGES / stage_s / 1e9,
+                "hbm_frac": BYTES_PER_CELL_STEP_MHD3D * cells / STAGES / stage_s / 1e9 / PEAK_HBM_GBS}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: oracle CPU baseline on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(bs)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D ideal MHD, 4096 uneven blocks 32^3:16^3:8^3 (1:2:4), fixed ghosts "
+                               "from a seeded 8-mode field, SSPRK(5,4)+MP5+global LF, CFL 0.4",
+                   "blocks": bs.nb, "cells": cells, "exec": "batched persistent, HIP graph per step",
+                   "parallelism": "single GPU"},
+        "per_block": per_block,
+        "batched_over_per_block": (value / per_block["value"]) if per_block else None,
+        "adjoint_forward_ratio": None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

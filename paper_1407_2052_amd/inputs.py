@@ -193,17 +193,25 @@ def random_modes(rng: np.random.Generator, ndim: int, nmodes: int, kmax: int = 4
 
 def lattice_modes(N: Sequence[int], ks, weights, phases) -> np.ndarray:
     """sum_m weights[m] * sin(2 pi k_m . x + phi_m) at the cell centres of the
-    periodic lattice N (x = (i + 1/2)/N per axis); separable complex
-    exponentials.  Returns an array (Nz, Ny, Nx)."""
+    periodic lattice N (x = (i + 1/2)/N per axis), via separable complex
+    exponentials: the (y, z) factors of all modes sharing k_x are summed
+    first, then one real outer product per distinct k_x.
+    Returns an array (Nz, Ny, Nx)."""
     N = list(N) + [1] * (3 - len(N))
     e = []
     for d in range(3):
         x = (np.arange(N[d]) + 0.5) / N[d]
         e.append({int(k): np.exp(2j * math.pi * k * x) for k in np.unique(ks[:, d])})
     out = np.zeros((N[2], N[1], N[0]))
-    for k, wgt, ph in zip(ks, weights, phases):
-        yz = np.exp(1j * ph) * (e[2][int(k[2])][:, None] * e[1][int(k[1])][None, :])
-        out += wgt * np.imag(yz[:, :, None] * e[0][int(k[0])][None, None, :])
+    for kx in np.unique(ks[:, 0]):
+        yz = np.zeros((N[2], N[1]), np.complex128)
+        for k, wgt, ph in zip(ks, weights, phases):
+            if int(k[0]) == int(kx):
+                yz += wgt * np.exp(1j * ph) * (e[2][int(k[2])][:, None] * e[1][int(k[1])][None, :])
+        ex = e[0][int(kx)]
+        # Im(yz * ex) = Re(yz) Im(ex) + Im(yz) Re(ex)
+        out += yz.real[:, :, None] * ex.imag[None, None, :]
+        out += yz.imag[:, :, None] * ex.real[None, None, :]
     return out
 
 
