@@ -127,6 +127,28 @@ amrvac_status amrvac_validate_blocks(const amrvac_config *cfg, const amrvac_bloc
 /* Chooses the execution form used by later calls (amrvac_exec). */
 amrvac_status amrvac_set_exec(amrvac_ctx *ctx, int exec);
 
+/* Tile shapes (work decomposition of the fused stage kernel) compiled for
+ * this context's (ndim, physics): their number, the name of shape i (a
+ * static string, NULL if i is out of range), and explicit selection of
+ * shape i for later calls (rebuilds the work list and drops cached graphs;
+ * results are bitwise identical for every shape).  Errors: INVALID. */
+int amrvac_num_variants(const amrvac_ctx *ctx);
+const char *amrvac_variant_name(const amrvac_ctx *ctx, int i);
+amrvac_status amrvac_set_variant(amrvac_ctx *ctx, int i);
+int amrvac_get_variant(const amrvac_ctx *ctx);   /* index in use, -1 for NULL ctx */
+
+/* Autotuner: times nsteps steps of `scheme` (CFL 0.4) with every compiled
+ * tile shape on the current block list, on scratch copies of the states
+ * (the caller's buffers are only read), and keeps the fastest.  If the
+ * environment variable AMRVAC_TUNE_CACHE names a file, a previous choice
+ * for the same (device, ndim, physics, block count, cell count, scheme) is
+ * reused without timing and new choices are appended.  ms_out (host, may
+ * be NULL, amrvac_num_variants entries) receives the milliseconds per step
+ * of each shape (-1 if not timed).  Synchronises the stream.
+ * Errors: INVALID (no blocks, scheme unknown, nsteps < 1), NONPHYSICAL,
+ * NOMEM, DEVICE. */
+amrvac_status amrvac_autotune(amrvac_ctx *ctx, int scheme, int nsteps, double *ms_out);
+
 /* Evaluates L(U) (Sect. 2.1 eq. timeoperator with S = 0, fluxes from
  * Sect. 2.2) of the current block states.  rhs: host array of nblocks
  * device pointers, each to nvar x n[0]*n[1]*n[2] doubles (interior only,

@@ -25,7 +25,9 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NONPHYSICAL"
 
 # Entry points declared in include/amrvac.h.
 SYMBOLS = ["amrvac_abi_version", "amrvac_create", "amrvac_set_blocks", "amrvac_validate_blocks",
-           "amrvac_set_exec", "amrvac_fd_rhs", "amrvac_ssprk_step", "amrvac_ssprk_adjoint",
+           "amrvac_set_exec", "amrvac_num_variants", "amrvac_variant_name", "amrvac_set_variant",
+           "amrvac_get_variant",
+           "amrvac_autotune", "amrvac_fd_rhs", "amrvac_ssprk_step", "amrvac_ssprk_adjoint",
            "amrvac_sync", "amrvac_last_error", "amrvac_destroy"]
 
 
@@ -63,6 +65,14 @@ def lib():
         L.amrvac_validate_blocks.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(Block), ip,
                                              ctypes.c_char_p, ip]
         L.amrvac_set_exec.argtypes = [vp, ip]
+        L.amrvac_num_variants.argtypes = [vp]
+        L.amrvac_num_variants.restype = ctypes.c_int
+        L.amrvac_variant_name.argtypes = [vp, ip]
+        L.amrvac_variant_name.restype = ctypes.c_char_p
+        L.amrvac_set_variant.argtypes = [vp, ip]
+        L.amrvac_get_variant.argtypes = [vp]
+        L.amrvac_get_variant.restype = ctypes.c_int
+        L.amrvac_autotune.argtypes = [vp, ip, ip, dp]
         L.amrvac_fd_rhs.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p), dp]
         L.amrvac_ssprk_step.argtypes = [vp, ip, ctypes.c_double, dp, ip, dp]
         L.amrvac_ssprk_adjoint.argtypes = [vp, ip, ctypes.c_double, ip, ip, ctypes.POINTER(ctypes.c_void_p)]
@@ -71,6 +81,7 @@ def lib():
         L.amrvac_last_error.argtypes = [vp]
         L.amrvac_destroy.argtypes = [vp]
         for name in ("amrvac_create", "amrvac_set_blocks", "amrvac_validate_blocks", "amrvac_set_exec",
+                     "amrvac_set_variant", "amrvac_autotune",
                      "amrvac_fd_rhs", "amrvac_ssprk_step", "amrvac_ssprk_adjoint", "amrvac_sync"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
@@ -151,6 +162,22 @@ class Context:
 
     def set_exec(self, exec: int):
         self._check(lib().amrvac_set_exec(self._h, exec))
+
+    def variants(self) -> List[str]:
+        n = lib().amrvac_num_variants(self._h)
+        return [lib().amrvac_variant_name(self._h, i).decode() for i in range(n)]
+
+    def set_variant(self, i: int):
+        self._check(lib().amrvac_set_variant(self._h, i))
+
+    def autotune(self, scheme: int = SSPRK54, nsteps: int = 2) -> Tuple[str, List[float]]:
+        n = lib().amrvac_num_variants(self._h)
+        ms = (ctypes.c_double * n)()
+        self._check(lib().amrvac_autotune(self._h, scheme, nsteps, ms))
+        return self.current_variant(), list(ms)
+
+    def current_variant(self) -> str:
+        return lib().amrvac_variant_name(self._h, lib().amrvac_get_variant(self._h)).decode()
 
     def fd_rhs(self, out: Optional[Sequence] = None, want_cmax: bool = True):
         t = self._torch

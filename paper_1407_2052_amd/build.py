@@ -4,7 +4,9 @@
 
 Compiles the HIP kernels and the host runtime behind include/amrvac.h with
 hipcc for gfx950.  All HIP code is compiled with packed-FP32 instructions
-disabled.
+disabled and without automatic FMA contraction (the kernels write their
+fused multiply-adds explicitly, which makes results independent of how the
+compiler schedules each template instantiation).
 """
 import os
 import subprocess
@@ -21,7 +23,7 @@ ARCH = os.environ.get("AMRVAC_ARCH", "gfx950")
 
 def build(verbose: bool = False) -> str:
     objs = []
-    common = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    common = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-function"]
     bdir = os.path.join(HERE, "_build")

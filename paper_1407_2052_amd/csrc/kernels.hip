@@ -25,6 +25,12 @@
 // the only HBM traffic beyond the algorithmic state passes is the 3-cell
 // halo of tiles (served mostly by L2).
 //
+// Floating point: automatic FMA contraction is off for this file (the build
+// passes -ffp-contract=off) and every fused multiply-add is written
+// explicitly, so the arithmetic is fixed by the source: every tile shape,
+// both execution forms and the adjoint's forward recompute produce bitwise
+// identical results.
+//
 // Accumulation order of L matches the definition: L = 0; for d: L -= diff_d
 // / dx_d (as a product with 1/dx_d).  MP5 is evaluated in its median form
 // median(fL, fmin, fmax); with eps = 0 the early exit of the published
@@ -122,14 +128,14 @@ __device__ __forceinline__ bool prim(const double* u, double gamma, PrimD& w) {
     w.B[k] = 0.0;
   }
 #pragma unroll
-  for (int k = 0; k < E::NC; ++k) mv += u[1 + k] * w.v[k];
-  double eint = u[E::IE] - 0.5 * mv;
+  for (int k = 0; k < E::NC; ++k) mv = fma(u[1 + k], w.v[k], mv);
+  double eint = fma(-0.5, mv, u[E::IE]);
   w.b2 = 0.0;
   if constexpr (MHD) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) w.B[k] = u[5 + k];
-    w.b2 = w.B[0] * w.B[0] + w.B[1] * w.B[1] + w.B[2] * w.B[2];
-    eint -= 0.5 * w.b2;
+    w.b2 = fma(w.B[2], w.B[2], fma(w.B[1], w.B[1], w.B[0] * w.B[0]));
+    eint = fma(-0.5, w.b2, eint);
   }
   w.p = (gamma - 1.0) * eint;
   return (w.rho > 0.0) && (w.p > 0.0) && (w.p < __builtin_huge_val()) &&
@@ -149,15 +155,15 @@ __device__ __forceinline__ void phys_flux(const double* u, const PrimD& w, doubl
     F[1 + D] += w.p;
     F[E::IE] = vd * (u[E::IE] + w.p);
   } else {
-    const double ptot = w.p + 0.5 * w.b2;
+    const double ptot = fma(0.5, w.b2, w.p);
     const double Bd = w.B[D];
-    const double bv = w.B[0] * w.v[0] + w.B[1] * w.v[1] + w.B[2] * w.v[2];
+    const double bv = fma(w.B[2], w.v[2], fma(w.B[1], w.v[1], w.B[0] * w.v[0]));
 #pragma unroll
-    for (int k = 0; k < 3; ++k) F[1 + k] = u[1 + k] * vd - Bd * w.B[k];
+    for (int k = 0; k < 3; ++k) F[1 + k] = fma(u[1 + k], vd, -(Bd * w.B[k]));
     F[1 + D] += ptot;
-    F[4] = vd * (u[4] + ptot) - Bd * bv;
+    F[4] = fma(vd, u[4] + ptot, -(Bd * bv));
 #pragma unroll
-    for (int k = 0; k < 3; ++k) F[5 + k] = (k == D) ? 0.0 : vd * w.B[k] - Bd * w.v[k];
+    for (int k = 0; k < 3; ++k) F[5 + k] = (k == D) ? 0.0 : fma(vd, w.B[k], -(Bd * w.v[k]));
   }
 }
 
@@ -171,7 +177,7 @@ __device__ __forceinline__ double fast_speed(const PrimD& w, int d, double gamma
     const double b2 = w.b2 * w.ri;
     const double bd2 = w.B[d] * w.B[d] * w.ri;
     const double s = a2 + b2;
-    double disc = s * s - 4.0 * a2 * bd2;
+    double disc = fma(s, s, -4.0 * a2 * bd2);
     disc = disc < 0.0 ? 0.0 : disc;
     return sqrt(0.5 * (s + sqrt(disc)));
   }
@@ -187,16 +193,16 @@ __device__ __forceinline__ double minmod4(double w, double x, double y, double z
 }
 
 __device__ __forceinline__ double mp5(double a, double b, double c, double d, double e) {
-  const double fL = (2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e) * (1.0 / 60.0);
+  const double fL = fma(2.0, a, fma(-13.0, b, fma(47.0, c, fma(27.0, d, -3.0 * e)))) * (1.0 / 60.0);
   const double cb = c - b;
-  const double dm = a - 2.0 * b + c;
-  const double d0 = b - 2.0 * c + d;
-  const double dp = c - 2.0 * d + e;
-  const double m4p = minmod4(4.0 * d0 - dp, 4.0 * dp - d0, d0, dp);
-  const double m4m = minmod4(4.0 * d0 - dm, 4.0 * dm - d0, d0, dm);
-  const double fUL = c + 4.0 * cb;
-  const double fMD = 0.5 * (c + d) - 0.5 * m4p;
-  const double fLC = c + 0.5 * cb + (4.0 / 3.0) * m4m;
+  const double dm = fma(-2.0, b, a) + c;
+  const double d0 = fma(-2.0, c, b) + d;
+  const double dp = fma(-2.0, d, c) + e;
+  const double m4p = minmod4(fma(4.0, d0, -dp), fma(4.0, dp, -d0), d0, dp);
+  const double m4m = minmod4(fma(4.0, d0, -dm), fma(4.0, dm, -d0), d0, dm);
+  const double fUL = fma(4.0, cb, c);
+  const double fMD = fma(-0.5, m4p, 0.5 * (c + d));
+  const double fLC = fma(4.0 / 3.0, m4m, fma(0.5, cb, c));
   const double fmn = fmax(fmin(fmin(c, d), fMD), fmin(fmin(c, fUL), fLC));
   const double fmx = fmin(fmax(fmax(c, d), fMD), fmax(fmax(c, fUL), fLC));
   return fmin(fmax(fL, fmn), fmx);
@@ -231,8 +237,8 @@ __device__ __forceinline__ double wave_max(double x) {
 // ---------------------------------------------------------------------------
 // Fused stage kernel.
 // ---------------------------------------------------------------------------
-template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP>
-__global__ void __launch_bounds__(NT) k_stage(StageParams P) {
+template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE>
+__global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
   using E = Eq<NDIM, MHD>;
   using S = TileShape<TX, TY, TZ>;
   constexpr int NV = E::NV;
@@ -327,8 +333,8 @@ __global__ void __launch_bounds__(NT) k_stage(StageParams P) {
               (void)dummy;
               const int v = G * VPG + vg;
               if (v < NV) {
-                lds[vg * NEXT_D + e] = 0.5 * (F[v] + c * u[v]);
-                lds[(VPG + vg) * NEXT_D + e] = 0.5 * (F[v] - c * u[v]);
+                lds[vg * NEXT_D + e] = 0.5 * fma(c, u[v], F[v]);
+                lds[(VPG + vg) * NEXT_D + e] = 0.5 * fma(-c, u[v], F[v]);
               }
             }
           }
@@ -389,7 +395,7 @@ __global__ void __launch_bounds__(NT) k_stage(StageParams P) {
                 const int v = G * VPG + vg;
                 if (v < NV) {
                   const double diff = lds[vg * NIFC_D + il + SI] - lds[vg * NIFC_D + il];
-                  L[r][v] -= diff * idx_d;
+                  L[r][v] = fma(-diff, idx_d, L[r][v]);
                 }
               }
             }
@@ -428,9 +434,8 @@ __global__ void __launch_bounds__(NT) k_stage(StageParams P) {
           double acc = P.a[0] * sp[0][v * vs[0]];
 #pragma unroll
           for (int q = 1; q < MAX_SRC; ++q)
-            if (q < P.nsrc) acc += P.a[q] * sp[q][v * vs[q]];
-          acc += dtb * L[r][v];
-          un[v] = acc;
+            if (q < P.nsrc) acc = fma(P.a[q], sp[q][v * vs[q]], acc);
+          un[v] = fma(dtb, L[r][v], acc);
         }
       }
       if (P.sdst >= 0) {
@@ -446,9 +451,8 @@ __global__ void __launch_bounds__(NT) k_stage(StageParams P) {
           double acc = P.sa[0] * sp[0][v * vs[0]];
 #pragma unroll
           for (int q = 1; q < MAX_SRC; ++q)
-            if (q < P.snsrc) acc += P.sa[q] * sp[q][v * vs[q]];
-          acc += dtsb * L[r][v];
-          sd[v * ws] = acc;
+            if (q < P.snsrc) acc = fma(P.sa[q], sp[q][v * vs[q]], acc);
+          sd[v * ws] = fma(dtsb, L[r][v], acc);
         }
       }
       {
@@ -548,7 +552,7 @@ __global__ void k_step_begin(Control* ctl, const double* dxtab, int ndim, int cl
     double worst = 0.0;
     for (int q = 0; q < ctl->ndx; ++q) {
       double s = 0.0;
-      for (int d = 0; d < ndim; ++d) s += cm[d] / dxtab[3 * q + d];
+      for (int d = 0; d < ndim; ++d) s = s + cm[d] / dxtab[3 * q + d];
       worst = fmax(worst, s);
     }
     dt = ctl->cfl / worst;
@@ -568,6 +572,24 @@ __global__ void k_set_control(Control* ctl, double dt_fixed, double cfl, double 
   }
 }
 
+// Copies the interior of every block from buffer `src` to buffer `dst`.
+__global__ void __launch_bounds__(256) k_copy_interior(StateTable st, const Tile* tiles, int ntiles, int tx,
+                                                     int ty, int tz, int nv, int src, int dst) {
+  const int tcells = tx * ty * tz;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Tile tl = tiles[t];
+    const BlockDev& B = st.blocks[tl.block];
+    for (int c = threadIdx.x; c < tcells; c += 256) {
+      const int i = tl.o[0] + c % tx, j = tl.o[1] + (c / tx) % ty, k = tl.o[2] + c / (tx * ty);
+      if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
+      long long vs, ws;
+      const double* p = cell_addr(st, B, src, i, j, k, vs);
+      double* q = cell_addr_w(st, B, dst, i, j, k, ws);
+      for (int v = 0; v < nv; ++v) q[v * ws] = p[v * vs];
+    }
+  }
+}
+
 // Clears one c_max slot (used before a standalone c_max reduction).
 __global__ void k_clear_slot(Control* ctl, int slot) {
   if (threadIdx.x < 3 && blockIdx.x == 0) ctl->cm[slot][threadIdx.x] = 0ull;
@@ -577,38 +599,49 @@ __global__ void k_clear_slot(Control* ctl, int slot) {
 // Variant table.
 // ---------------------------------------------------------------------------
 struct StageVariant {
-  int ndim, mhd, tx, ty, tz, nt, ngrp;
+  int ndim, mhd, tx, ty, tz, nt, ngrp, wpe;
   const void* fn;
   void (*launch)(const StageParams&, int grid, hipStream_t);
+  const char* name;
 };
 
-template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP>
+template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE>
 static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP>), dim3(grid), dim3(NT), 0, s, p);
+  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE>), dim3(grid), dim3(NT), 0, s, p);
 }
 
-#define AMRVAC_VARIANT(ND, M, TX, TY, TZ, NT, NGRP)                                 \
-  {ND, M, TX, TY, TZ, NT, NGRP, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP>, \
-   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP>}
+#define AMRVAC_VARIANT(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                       \
+  {ND, M, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE>,                                          \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE}
 
+// Tile shapes the autotuner chooses from (the first of each (ndim,
+// physics) is the default).  WPE = minimum waves per SIMD requested from
+// the register allocator.
 static const StageVariant g_variants[] = {
     // 1D
-    AMRVAC_VARIANT(1, false, 128, 1, 1, 128, 1),
-    AMRVAC_VARIANT(1, false, 64, 1, 1, 64, 1),
-    AMRVAC_VARIANT(1, true, 128, 1, 1, 128, 1),
-    AMRVAC_VARIANT(1, true, 64, 1, 1, 64, 1),
+    AMRVAC_VARIANT(1, false, 128, 1, 1, 128, 1, 1),
+    AMRVAC_VARIANT(1, false, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT(1, true, 128, 1, 1, 128, 1, 1),
+    AMRVAC_VARIANT(1, true, 64, 1, 1, 64, 1, 1),
     // 2D
-    AMRVAC_VARIANT(2, false, 16, 16, 1, 256, 1),
-    AMRVAC_VARIANT(2, false, 32, 8, 1, 256, 1),
-    AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 1),
-    AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 2),
-    AMRVAC_VARIANT(2, true, 32, 8, 1, 256, 2),
+    AMRVAC_VARIANT(2, false, 16, 16, 1, 256, 1, 1),
+    AMRVAC_VARIANT(2, false, 16, 16, 1, 256, 1, 3),
+    AMRVAC_VARIANT(2, false, 32, 8, 1, 256, 1, 1),
+    AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 2, 1),
+    AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 1, 1),
+    AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 2, 3),
+    AMRVAC_VARIANT(2, true, 32, 8, 1, 256, 2, 1),
     // 3D
-    AMRVAC_VARIANT(3, false, 8, 8, 8, 512, 2),
-    AMRVAC_VARIANT(3, false, 8, 8, 4, 256, 1),
-    AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 2),
-    AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 2),
-    AMRVAC_VARIANT(3, true, 8, 8, 8, 256, 2),
+    AMRVAC_VARIANT(3, false, 8, 8, 8, 512, 2, 1),
+    AMRVAC_VARIANT(3, false, 8, 8, 4, 256, 1, 1),
+    AMRVAC_VARIANT(3, false, 8, 8, 8, 512, 2, 4),
+    AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 2, 1),
+    AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 2, 4),
+    AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 2, 1),
+    AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 2, 3),
+    AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 4, 4),
+    AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 4, 4),
 };
 
 const StageVariant* stage_variants(int* count) {
@@ -634,6 +667,12 @@ void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo
 
 void launch_set_control(Control* ctl, double dt_fixed, double cfl, double t, hipStream_t s) {
   hipLaunchKernelGGL(k_set_control, dim3(1), dim3(64), 0, s, ctl, dt_fixed, cfl, t);
+}
+
+void launch_copy_interior(const StateTable& st, const Tile* tiles, int ntiles, int tx, int ty, int tz, int nv,
+                          int src, int dst, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_interior, dim3(grid), dim3(256), 0, s, st, tiles, ntiles, tx, ty, tz, nv, src,
+                     dst);
 }
 
 void launch_clear_slot(Control* ctl, int slot, hipStream_t s) {

@@ -8,17 +8,21 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
 namespace amrvac {
 
 struct StageVariant {
-  int ndim, mhd, tx, ty, tz, nt, ngrp;
+  int ndim, mhd, tx, ty, tz, nt, ngrp, wpe;
   const void* fn;
   void (*launch)(const StageParams&, int grid, hipStream_t);
+  const char* name;
 };
 const StageVariant* stage_variants(int* count);
 void launch_cmax(int ndim, int mhd, const CmaxParams& p, int grid, hipStream_t s);
@@ -26,6 +30,8 @@ void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo
                        hipStream_t s);
 void launch_clear_slot(Control* ctl, int slot, hipStream_t s);
 void launch_set_control(Control* ctl, double dt_fixed, double cfl, double t, hipStream_t s);
+void launch_copy_interior(const StateTable& st, const Tile* tiles, int ntiles, int tx, int ty, int tz, int nv,
+                          int src, int dst, int grid, hipStream_t s);
 
 }  // namespace amrvac
 
@@ -57,6 +63,7 @@ struct amrvac_ctx {
 
   // tiles of the chosen variant
   const StageVariant* var = nullptr;
+  int var_index = 0;
   std::vector<Tile> htiles;
   Tile* d_tiles = nullptr;
   std::vector<int> blk_tile_begin, blk_tile_count;
@@ -132,7 +139,15 @@ static uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   return spread(x) | (spread(y) << 1) | (spread(z) << 2);
 }
 
-static const StageVariant* pick_variant(amrvac_ctx* c, int want) {
+static int count_variants(const amrvac_ctx* c) {
+  int nv = 0, k = 0;
+  const StageVariant* v = stage_variants(&nv);
+  for (int i = 0; i < nv; ++i)
+    if (v[i].ndim == c->cfg.ndim && v[i].mhd == (c->cfg.physics == AMRVAC_MHD)) ++k;
+  return k;
+}
+
+static const StageVariant* pick_variant(const amrvac_ctx* c, int want) {
   int nv = 0;
   const StageVariant* v = stage_variants(&nv);
   int k = 0;
@@ -144,6 +159,8 @@ static const StageVariant* pick_variant(amrvac_ctx* c, int want) {
   }
   return nullptr;
 }
+
+static amrvac_status select_variant(amrvac_ctx* c, int i);
 
 // Build the tile list of the current variant: blocks ordered largest first,
 // then along a Morton curve of their origins; tiles of a block contiguous and
@@ -221,6 +238,17 @@ static amrvac_status ensure_slots(amrvac_ctx* c, int n) {
   HIP_TRY(c, hipMalloc(&c->d_scr, bytes));
   c->nslots = n;
   return AMRVAC_OK;
+}
+
+static amrvac_status select_variant(amrvac_ctx* c, int i) {
+  const StageVariant* v = pick_variant(c, i);
+  if (!v) return fail(c, AMRVAC_ERR_INVALID, "variant %d does not exist", i);
+  if (v == c->var && !c->htiles.empty()) return AMRVAC_OK;
+  drop_graphs(c);
+  c->var = v;
+  c->var_index = i;
+  if (c->hb.empty()) return AMRVAC_OK;
+  return build_tiles(c);
 }
 
 static StateTable state_table(const amrvac_ctx* c) {
@@ -604,6 +632,98 @@ amrvac_status amrvac_set_exec(amrvac_ctx* c, int exec) {
     return fail(c, AMRVAC_ERR_INVALID, "set_exec: unknown execution form %d", exec);
   c->exec = exec;
   return AMRVAC_OK;
+}
+
+int amrvac_num_variants(const amrvac_ctx* c) { return c ? count_variants(c) : 0; }
+
+const char* amrvac_variant_name(const amrvac_ctx* c, int i) {
+  if (!c) return nullptr;
+  const StageVariant* v = pick_variant(c, i);
+  return v ? v->name : nullptr;
+}
+
+int amrvac_get_variant(const amrvac_ctx* c) { return c ? c->var_index : -1; }
+
+amrvac_status amrvac_set_variant(amrvac_ctx* c, int i) {
+  if (!c) return AMRVAC_ERR_INVALID;
+  if (i < 0 || i >= count_variants(c)) return fail(c, AMRVAC_ERR_INVALID, "set_variant: %d out of range", i);
+  return select_variant(c, i);
+}
+
+amrvac_status amrvac_autotune(amrvac_ctx* c, int scheme, int nsteps, double* ms_out) {
+  if (!c) return AMRVAC_ERR_INVALID;
+  if (c->hb.empty()) return fail(c, AMRVAC_ERR_INVALID, "autotune: no blocks set");
+  if (scheme < AMRVAC_RK3 || scheme > AMRVAC_SSPRK54 || nsteps < 1)
+    return fail(c, AMRVAC_ERR_INVALID, "autotune: invalid scheme or nsteps");
+  const int nv = count_variants(c);
+  if (ms_out)
+    for (int i = 0; i < nv; ++i) ms_out[i] = -1.0;
+  // cache lookup
+  char key[256];
+  hipDeviceProp_t prop;
+  HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+  snprintf(key, sizeof(key), "%s|%d|%d|%zu|%lld|%d", prop.gcnArchName, c->cfg.ndim, c->cfg.physics, c->hb.size(),
+           c->total_cells, scheme);
+  const char* cache = std::getenv("AMRVAC_TUNE_CACHE");
+  if (cache && *cache) {
+    std::ifstream in(cache);
+    std::string line;
+    std::string found;
+    while (std::getline(in, line)) {
+      size_t sp = line.rfind(' ');
+      if (sp != std::string::npos && line.substr(0, sp) == key) found = line.substr(sp + 1);
+    }
+    if (!found.empty())
+      for (int i = 0; i < nv; ++i)
+        if (found == pick_variant(c, i)->name) return select_variant(c, i);
+  }
+  // time every shape on scratch copies: slot ids 1..3 = A, B, S; 4 = U copy
+  amrvac_status st = ensure_slots(c, 4);
+  if (st != AMRVAC_OK) return st;
+  const int keep = c->var_index;
+  const int keep_exec = c->exec;
+  c->exec = AMRVAC_EXEC_BATCHED;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  int best = keep;
+  float best_ms = 1e30f;
+  for (int i = 0; i < nv; ++i) {
+    st = select_variant(c, i);
+    if (st != AMRVAC_OK) continue;
+    launch_copy_interior(state_table(c), c->d_tiles, (int)c->htiles.size(), c->var->tx, c->var->ty, c->var->tz,
+                         c->nvar, 0, 4, std::min<int>(c->ncu * 8, (int)c->htiles.size()), c->stream);
+    launch_set_control(c->d_ctl, 0.0, 0.4, 0.0, c->stream);
+    launch_cmax_of(c, 4, 0, c->stream);
+    enqueue_step(c, scheme, AMRVAC_EXEC_BATCHED, c->stream, 4, 1, 2, 3, 4);   // warm-up
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    for (int it = 0; it < nsteps; ++it) enqueue_step(c, scheme, AMRVAC_EXEC_BATCHED, c->stream, 4, 1, 2, 3, 4);
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    if (hipGetLastError() != hipSuccess) continue;
+    float ms = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+    ms /= nsteps;
+    if (ms_out) ms_out[i] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = i;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->exec = keep_exec;
+  st = read_status(c);
+  if (st != AMRVAC_OK) {
+    select_variant(c, keep);
+    return st;
+  }
+  st = select_variant(c, best);
+  if (st == AMRVAC_OK && cache && *cache) {
+    std::ofstream out(cache, std::ios::app);
+    out << key << " " << c->var->name << "\n";
+  }
+  return st;
 }
 
 amrvac_status amrvac_fd_rhs(amrvac_ctx* c, double* const* rhs, double* cmax_out) {

@@ -282,3 +282,46 @@ def test_full_size_3d_rhs_on_sampled_blocks(which):
     sub = sample_blocks_with_true_ghosts(bs, idx)
     Lo, _ = oracle.rhs(sub, cmax=cmo)
     compare_rhs(sub, [Lg[i] for i in idx], Lo, cmo)
+
+
+# ---------------------------------------------------------------- tile shapes
+@pytest.mark.parametrize("case", ["dwave1d_8blk", "ot2d", "hydro2d", "ragged2d_mhd", "mhd3d", "uneven3d",
+                                  "ragged3d_hd", "ragged3d_mhd"])
+def test_every_tile_shape_is_bitwise_identical(case):
+    bs = CASES[case]()
+    ref = None
+    ctx0, _, _ = A.context_for(bs)
+    names = ctx0.variants()
+    ctx0.close()
+    for i, name in enumerate(names):
+        say(f"[variant] {case} {name}")
+        ctx, flat, views = A.context_for(bs)
+        ctx.set_variant(i)
+        t = ctx.ssprk_step(oracle.SSPRK54, 3, t=0.0)
+        got = host_blocks(views), t
+        ctx.close()
+        if ref is None:
+            ref = got
+            continue
+        assert got[1] == ref[1], name
+        for x, y in zip(got[0], ref[0]):
+            assert np.array_equal(x, y), name
+
+
+def test_autotune_reads_but_never_writes_the_state():
+    say("[autotune] mhd3d")
+    bs = CASES["mhd3d"]()
+    ctx, flat, views = A.context_for(bs)
+    before = flat.clone()
+    name, ms = ctx.autotune(oracle.SSPRK54, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(before, flat)
+    assert name in ctx.variants()
+    timed = [m for m in ms if m >= 0]
+    assert timed and min(timed) == ms[ctx.variants().index(name)]
+    out_o, _ = oracle.run(bs, oracle.SSPRK54, 5)
+    t = ctx.ssprk_step(oracle.SSPRK54, 5, t=0.0)
+    out_g = bs.copy()
+    out_g.u = host_blocks(views)
+    ctx.close()
+    assert_state_parity(bs, out_g, out_o)
