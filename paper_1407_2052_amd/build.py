@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libamrvac.so")
-SOURCES = ["kernels.hip", "runtime.cpp", "adjoint.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "runtime.cpp", "adjoint.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("AMRVAC_ARCH", "gfx950")
 

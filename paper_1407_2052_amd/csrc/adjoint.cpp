@@ -1,21 +1,286 @@
-// Reverse mode of the SSPRK time integration (amrvac_ssprk_adjoint).
-#include "amrvac.h"
-#include "amrvac_internal.h"
+// Reverse mode of the SSPRK time integration (Porth et al. 2014, Sect. 2.3)
+// with checkpoint-and-recompute: amrvac_ssprk_adjoint.
+//
+// Forward map of one step (Shu-Osher form):
+//   U(0) = U^n,  U(i) = sum_{k<i} alpha_ik U(k) + dt beta_ik L(U(k)),  U^{n+1} = U(s).
+// Reverse of one step, given lam(s) = dJ/dU^{n+1}, for k = s-1 .. 0:
+//   mu      = sum_{i>k} beta_ik lam(i)
+//   lam(k)  = sum_{i>k} alpha_ik lam(i) + dt J_L(U(k))^T mu
+// and dJ/dU^n = lam(0).  Every lam(i), i > k, is complete when stage k is
+// processed, so each stage state costs exactly one vector-Jacobian product.
+//
+// Memory: checkpoints of U every ckpt_every steps; a segment is recomputed
+// from its checkpoint with every stage state stored, then reversed.
+#include "runtime_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
 namespace amrvac {
-amrvac_status ctx_fail(amrvac_ctx* c, amrvac_status st, const char* msg);
-}
+struct VjpVariant {
+  int ndim, mhd, tx, ty, tz, nt;
+  const void* fn;
+  void (*launch)(const VjpParams&, int grid, hipStream_t);
+  void (*argmax)(StateTable, const Tile*, int, int, int, int, double, int, double*, long long*, int, hipStream_t);
+  void (*cmax_term)(StateTable, int, const double*, int, Control*, double, int, int, double, hipStream_t);
+};
+struct CombineParams {
+  StateTable st;
+  const Tile* tiles;
+  int ntiles, tx, ty, tz, nv;
+  int n;
+  int src[6];
+  double a[6];
+  int dst;
+};
+const VjpVariant* vjp_variant(int ndim, int mhd);
+void launch_argmax_reduce(const double* tmax, const long long* targ, int ntiles, Control* ctl, int slot,
+                          hipStream_t s);
+void launch_combine(const CombineParams& p, int grid, hipStream_t s);
+void launch_lam_import(StateTable st, double* const* ptrs, int nv, int dst, int nblocks, hipStream_t s);
+void launch_lam_export(StateTable st, double* const* ptrs, int nv, int src, int nblocks, hipStream_t s);
+}  // namespace amrvac
+
 using namespace amrvac;
 
-extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double dt, int nsteps,
-                                              int ckpt_every, double* const* lam) {
+namespace {
+
+constexpr int VJP_SLOT = MAX_SLOTS - 1;   // c_max slot used by the reverse pass
+
+struct Adj {
+  amrvac_ctx* c;
+  const VjpVariant* V;
+  std::vector<Tile> htiles;
+  Tile* d_tiles = nullptr;
+  double* d_tmax = nullptr;
+  long long* d_targ = nullptr;
+  double* d_cpart = nullptr;
+  double** d_ptrs = nullptr;
+  int grid_vjp = 0;
+  int grid_small = 0;
+
+  ~Adj() {
+    if (d_tiles) (void)hipFree(d_tiles);
+    if (d_tmax) (void)hipFree(d_tmax);
+    if (d_targ) (void)hipFree(d_targ);
+    if (d_cpart) (void)hipFree(d_cpart);
+    if (d_ptrs) (void)hipFree(d_ptrs);
+  }
+
+  int ntiles() const { return (int)htiles.size(); }
+
+  // dst = sum of coefficient * buffer over `terms` (launches of at most 6
+  // sources; later launches carry the partial sum in dst).
+  void combine(int dst, const std::vector<std::pair<int, double>>& terms) {
+    size_t q = 0;
+    bool first = true;
+    while (q < terms.size()) {
+      CombineParams p{};
+      p.dst = dst;
+      p.st = state_table(c);
+      p.tiles = d_tiles;
+      p.ntiles = ntiles();
+      p.tx = V->tx;
+      p.ty = V->ty;
+      p.tz = V->tz;
+      p.nv = c->nvar;
+      p.n = 0;
+      if (!first) {   // continue an accumulation of more than 6 terms
+        p.src[p.n] = dst;
+        p.a[p.n] = 1.0;
+        ++p.n;
+      }
+      for (; q < terms.size() && p.n < 6; ++q) {
+        p.src[p.n] = terms[q].first;
+        p.a[p.n] = terms[q].second;
+        ++p.n;
+      }
+      launch_combine(p, grid_small, c->stream);
+      first = false;
+    }
+  }
+
+  // lam += dt * J_L(state)^T mu, including the c_max term
+  void vjp(int state, int mu, int lam, double dt) {
+    StateTable st = state_table(c);
+    V->argmax(st, d_tiles, ntiles(), V->tx, V->ty, V->tz, c->cfg.gamma, state, d_tmax, d_targ, grid_small,
+              c->stream);
+    launch_argmax_reduce(d_tmax, d_targ, ntiles(), c->d_ctl, VJP_SLOT, c->stream);
+    VjpParams p{};
+    p.st = st;
+    p.tiles = d_tiles;
+    p.ntiles = ntiles();
+    p.ctl = c->d_ctl;
+    p.gamma = c->cfg.gamma;
+    p.in = state;
+    p.mu = mu;
+    p.lam = lam;
+    p.scale = dt;
+    p.cm_slot = VJP_SLOT;
+    p.cpart = d_cpart;
+    V->launch(p, grid_vjp, c->stream);
+    V->cmax_term(st, (int)c->hb.size(), d_cpart, ntiles(), c->d_ctl, c->cfg.gamma, state, lam, dt, c->stream);
+  }
+};
+
+}  // namespace
+
+extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double dt, int nsteps, int ckpt_every,
+                                              double* const* lam) {
   if (!c) return AMRVAC_ERR_INVALID;
+  if (c->hb.empty()) return ctx_fail(c, AMRVAC_ERR_INVALID, "ssprk_adjoint: no blocks set");
   if (!lam) return ctx_fail(c, AMRVAC_ERR_INVALID, "ssprk_adjoint: lam is NULL");
-  if (scheme < AMRVAC_RK3 || scheme > AMRVAC_SSPRK54 || nsteps < 0 || ckpt_every < 1 ||
-      !std::isfinite(dt) || !(dt > 0.0))
+  const int nb = (int)c->hb.size();
+  for (int b = 0; b < nb; ++b)
+    if (!lam[b]) return ctx_fail(c, AMRVAC_ERR_INVALID, "ssprk_adjoint: lam[%d] is NULL", b);
+  if (scheme < AMRVAC_RK3 || scheme > AMRVAC_SSPRK54 || nsteps < 0 || ckpt_every < 1 || !std::isfinite(dt) ||
+      !(dt > 0.0))
     return ctx_fail(c, AMRVAC_ERR_INVALID, "ssprk_adjoint: invalid scheme, nsteps, ckpt_every or dt");
-  return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: not available in this build");
+  for (int b = 0; b < nb; ++b)
+    for (int d = 0; d < c->cfg.ndim; ++d) {
+      if (c->hb[b].nbr[2 * d] < 0 || c->hb[b].nbr[2 * d + 1] < 0)
+        return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: block %d has a fixed face (direction %d)", b, d);
+      if (c->hb[b].n[d] < 5)
+        return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: block %d has n[%d] < 5", b, d);
+    }
+  for (int b = 0; b < nb; ++b)
+    for (int d = 0; d < c->cfg.ndim; ++d)
+      for (int s = 0; s < 2; ++s)
+        if (c->hb[c->hb[b].nbr[2 * d + s]].n[d] < 5)
+          return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: neighbour of block %d has n[%d] < 5", b, d);
+
+  const int s = scheme_stages(scheme);
+  const int N = nsteps;
+  const int k = std::max(1, std::min(ckpt_every, std::max(N, 1)));
+  const int M = (N + k - 1) / k;   // segments
+  // buffer ids (scratch slot = id - 1)
+  const int A = 1, Bf = 2, S = 3, W0 = 4, W1 = 5;
+  int next = 6;
+  std::vector<int> ck(std::max(M, 1), 0);   // ck[0] = caller's U0 (id 0)
+  for (int m = 1; m < M; ++m) ck[m] = next++;
+  std::vector<std::vector<int>> X(k, std::vector<int>(s, 0));
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i < s; ++i) X[j][i] = next++;
+  std::vector<int> Lm(s + 1);
+  for (int i = 0; i <= s; ++i) Lm[i] = next++;
+  const int MU = next++;
+  amrvac_status st = ensure_slots(c, next - 1);
+  if (st != AMRVAC_OK) return st;
+
+  Adj adj;
+  adj.c = c;
+  adj.V = vjp_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD);
+  if (!adj.V) return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: no kernel for this ndim/physics");
+  {
+    const int T[3] = {adj.V->tx, adj.V->ty, adj.V->tz};
+    for (int b = 0; b < nb; ++b) {
+      const amrvac_block& q = c->hb[b];
+      int nt[3];
+      for (int d = 0; d < 3; ++d) nt[d] = (q.n[d] + T[d] - 1) / T[d];
+      for (int z = 0; z < nt[2]; ++z)
+        for (int y = 0; y < nt[1]; ++y)
+          for (int x = 0; x < nt[0]; ++x) {
+            Tile t;
+            t.block = b;
+            t.o[0] = x * T[0];
+            t.o[1] = y * T[1];
+            t.o[2] = z * T[2];
+            adj.htiles.push_back(t);
+          }
+    }
+  }
+  const int nt = adj.ntiles();
+  auto hip_ok = [&](hipError_t e, const char* what) -> amrvac_status {
+    if (e == hipSuccess) return AMRVAC_OK;
+    return ctx_fail(c, e == hipErrorOutOfMemory ? AMRVAC_ERR_NOMEM : AMRVAC_ERR_DEVICE, "%s: %s", what,
+                    hipGetErrorString(e));
+  };
+  if ((st = hip_ok(hipMalloc(&adj.d_tiles, sizeof(Tile) * nt), "hipMalloc")) != AMRVAC_OK) return st;
+  if ((st = hip_ok(hipMalloc(&adj.d_tmax, sizeof(double) * 3 * nt), "hipMalloc")) != AMRVAC_OK) return st;
+  if ((st = hip_ok(hipMalloc(&adj.d_targ, sizeof(long long) * 3 * nt), "hipMalloc")) != AMRVAC_OK) return st;
+  if ((st = hip_ok(hipMalloc(&adj.d_cpart, sizeof(double) * 3 * nt), "hipMalloc")) != AMRVAC_OK) return st;
+  if ((st = hip_ok(hipMalloc(&adj.d_ptrs, sizeof(double*) * nb), "hipMalloc")) != AMRVAC_OK) return st;
+  if ((st = hip_ok(hipMemcpyAsync(adj.d_tiles, adj.htiles.data(), sizeof(Tile) * nt, hipMemcpyHostToDevice,
+                                  c->stream), "upload")) != AMRVAC_OK)
+    return st;
+  std::vector<double*> hptrs(lam, lam + nb);
+  if ((st = hip_ok(hipMemcpyAsync(adj.d_ptrs, hptrs.data(), sizeof(double*) * nb, hipMemcpyHostToDevice, c->stream),
+                   "upload")) != AMRVAC_OK)
+    return st;
+  int per_cu = 0;
+  if ((st = hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj.V->fn, adj.V->nt, 0), "occupancy")) !=
+      AMRVAC_OK)
+    return st;
+  adj.grid_vjp = std::max(1, std::min(std::max(per_cu, 1) * c->ncu, nt));
+  adj.grid_small = std::max(1, std::min(c->ncu * 8, nt));
+
+  double alpha[6][6], beta[6][6];
+  scheme_table(scheme, alpha, beta);
+  const int exec = AMRVAC_EXEC_BATCHED;
+
+  // ---- forward pass to the checkpoints (U0 = caller's u, read only) ----
+  launch_set_control(c->d_ctl, dt, 0.4, 0.0, c->stream);
+  int cur = 0;
+  const int last_needed = (M - 1) * k;   // states beyond the last checkpoint are not needed
+  if (last_needed > 0) launch_cmax_of(c, cur, 0, c->stream);
+  for (int n = 0; n < last_needed; ++n) {
+    int nxt;
+    if ((n + 1) % k == 0) {
+      nxt = ck[(n + 1) / k];
+    } else {
+      nxt = (cur == W0) ? W1 : W0;
+    }
+    int outs[6];
+    for (int i = 1; i <= s; ++i) outs[i] = (i == s) ? nxt : ((i % 2) ? A : Bf);
+    enqueue_step_outs(c, scheme, exec, c->stream, cur, outs, S);
+    cur = nxt;
+  }
+
+  // ---- reverse sweep over segments ----
+  int R = Lm[s];   // running adjoint of the current output state
+  launch_lam_import(state_table(c), adj.d_ptrs, c->nvar, R, nb, c->stream);
+  std::vector<int> lslots(Lm.begin(), Lm.end());
+  for (int m = M - 1; m >= 0; --m) {
+    const int n0 = m * k;
+    const int kk = std::min(k, N - n0);
+    // recompute the segment, storing every stage state
+    X[0][0] = ck[m];
+    launch_cmax_of(c, X[0][0], 0, c->stream);
+    for (int j = 0; j < kk; ++j) {
+      int outs[6];
+      for (int i = 1; i < s; ++i) outs[i] = X[j][i];
+      outs[s] = (j + 1 < kk) ? X[j + 1][0] : W0;   // the segment's last output is not needed
+      enqueue_step_outs(c, scheme, exec, c->stream, X[j][0], outs, S);
+    }
+    // reverse the segment's steps
+    for (int j = kk - 1; j >= 0; --j) {
+      // lam(s) = R; lam(i) for i < s are the other slots
+      std::vector<int> L(s + 1);
+      L[s] = R;
+      {
+        int q = 0;
+        for (int id : lslots)
+          if (id != R && q < s) L[q++] = id;
+      }
+      for (int kst = s - 1; kst >= 0; --kst) {
+        std::vector<std::pair<int, double>> mu_t, lam_t;
+        for (int i = kst + 1; i <= s; ++i) {
+          if (beta[i][kst] != 0.0) mu_t.push_back({L[i], beta[i][kst]});
+          if (alpha[i][kst] != 0.0) lam_t.push_back({L[i], alpha[i][kst]});
+        }
+        if (lam_t.empty()) lam_t.push_back({L[s], 0.0});
+        adj.combine(L[kst], lam_t);
+        if (!mu_t.empty()) {
+          adj.combine(MU, mu_t);
+          adj.vjp(X[j][kst], MU, L[kst], dt);
+        }
+      }
+      R = L[0];
+    }
+  }
+  launch_lam_export(state_table(c), adj.d_ptrs, c->nvar, R, nb, c->stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_ok(e, "adjoint launch");
+  return read_status(c);
 }

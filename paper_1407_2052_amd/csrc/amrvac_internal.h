@@ -38,6 +38,9 @@ struct Control {
   int err;              // sticky: 1 = non-physical state met
   int ndx;              // number of distinct dx tuples in dxtab
   int pad[2];
+  // c_max maximiser per direction ((block << 32) | interior linear index),
+  // filled by the adjoint's argmax reduction
+  long long arg[3];
 };
 
 // Buffers: id 0 = caller's padded u; id k >= 1 = scratch slot k-1 with the
@@ -90,6 +93,22 @@ struct CmaxParams {
   double gamma;
   int in;
   int slot;
+};
+
+// Parameters of one vector-Jacobian product of L (adjoint of a stage):
+//   lam += scale * J_L(U)^T mu      (U = buffer `in`, mu = buffer `mu`)
+// local part only; the c_max part (through the maximising cell) is added by
+// a separate reduction from the per-tile sums written to cpart[tile*3+d].
+struct VjpParams {
+  StateTable st;
+  const Tile* tiles;
+  int ntiles;
+  Control* ctl;
+  double gamma;
+  int in, mu, lam;
+  double scale;
+  int cm_slot;
+  double* cpart;
 };
 
 }  // namespace amrvac

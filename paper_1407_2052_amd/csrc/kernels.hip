@@ -36,203 +36,9 @@
 // median(fL, fmin, fmax); with eps = 0 the early exit of the published
 // algorithm returns the same value (fL lies inside both bounds whenever the
 // early-exit test holds).
-#include "amrvac_internal.h"
-
-#include <type_traits>
-#include <utility>
+#include "device_math.h"
 
 namespace amrvac {
-
-template <int NDIM, bool MHD>
-struct Eq {
-  static constexpr int NV = MHD ? 8 : 2 + NDIM;
-  static constexpr int NC = MHD ? 3 : NDIM;
-  static constexpr int IE = 1 + NC;
-};
-
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Addressing of state buffers.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ const double* cell_addr(const StateTable& st, const BlockDev& B, int buf,
-                                                   int i, int j, int k, long long& vstride) {
-  if (buf == 0) {
-    vstride = (long long)B.P[0] * B.P[1] * B.P[2];
-    return B.u + (((long long)(k + B.g[2]) * B.P[1] + (j + B.g[1])) * B.P[0] + (i + B.g[0]));
-  }
-  vstride = B.cells;
-  return st.scr + (long long)(buf - 1) * st.slot_stride + B.off +
-         (((long long)k * B.n[1] + j) * B.n[0] + i);
-}
-
-__device__ __forceinline__ double* cell_addr_w(const StateTable& st, const BlockDev& B, int buf,
-                                               int i, int j, int k, long long& vstride) {
-  return const_cast<double*>(cell_addr(st, B, buf, i, j, k, vstride));
-}
-
-// Load all NV variables of cell (i,j,k) of block blk, where only coordinate
-// D may lie outside [0, n_D): then the value comes from the face neighbour's
-// interior (same buffer), or from this block's fixed ghost layer (buffer 0).
-template <int NV, int D>
-__device__ __forceinline__ void load_cell(const StateTable& st, int blk, int buf, int i, int j, int k,
-                                          double* u) {
-  const BlockDev* B = &st.blocks[blk];
-  int c[3] = {i, j, k};
-  int bf = buf;
-  if (c[D] < 0) {
-    int nb = B->nbr[2 * D];
-    if (nb >= 0) {
-      B = &st.blocks[nb];
-      c[D] += B->n[D];
-    } else {
-      bf = 0;
-    }
-  } else if (c[D] >= B->n[D]) {
-    int nb = B->nbr[2 * D + 1];
-    if (nb >= 0) {
-      c[D] -= B->n[D];
-      B = &st.blocks[nb];
-    } else {
-      bf = 0;
-    }
-  }
-  long long vs;
-  const double* p = cell_addr(st, *B, bf, c[0], c[1], c[2], vs);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = p[v * vs];
-}
-
-// ---------------------------------------------------------------------------
-// Physics: primitive recovery, flux along D, fast speed.
-// ---------------------------------------------------------------------------
-struct PrimD {
-  double rho, ri, v[3], p, B[3], b2;
-};
-
-template <int NDIM, bool MHD>
-__device__ __forceinline__ bool prim(const double* u, double gamma, PrimD& w) {
-  using E = Eq<NDIM, MHD>;
-  w.rho = u[0];
-  w.ri = 1.0 / w.rho;
-  double mv = 0.0;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    w.v[k] = (k < E::NC) ? u[1 + k] * w.ri : 0.0;
-    w.B[k] = 0.0;
-  }
-#pragma unroll
-  for (int k = 0; k < E::NC; ++k) mv = fma(u[1 + k], w.v[k], mv);
-  double eint = fma(-0.5, mv, u[E::IE]);
-  w.b2 = 0.0;
-  if constexpr (MHD) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) w.B[k] = u[5 + k];
-    w.b2 = fma(w.B[2], w.B[2], fma(w.B[1], w.B[1], w.B[0] * w.B[0]));
-    eint = fma(-0.5, w.b2, eint);
-  }
-  w.p = (gamma - 1.0) * eint;
-  return (w.rho > 0.0) && (w.p > 0.0) && (w.p < __builtin_huge_val()) &&
-         (w.rho < __builtin_huge_val());
-}
-
-// Physical flux along D (Sect. 3 eqs. masscons, momentum, total; Sect. 4.1
-// eq. b1eq and Sect. 4.3 eqs. momentummhd, fractional with B0 = 0).
-template <int NDIM, bool MHD, int D>
-__device__ __forceinline__ void phys_flux(const double* u, const PrimD& w, double* F) {
-  using E = Eq<NDIM, MHD>;
-  const double vd = w.v[D];
-  F[0] = u[1 + D];
-  if constexpr (!MHD) {
-#pragma unroll
-    for (int k = 0; k < E::NC; ++k) F[1 + k] = u[1 + k] * vd;
-    F[1 + D] += w.p;
-    F[E::IE] = vd * (u[E::IE] + w.p);
-  } else {
-    const double ptot = fma(0.5, w.b2, w.p);
-    const double Bd = w.B[D];
-    const double bv = fma(w.B[2], w.v[2], fma(w.B[1], w.v[1], w.B[0] * w.v[0]));
-#pragma unroll
-    for (int k = 0; k < 3; ++k) F[1 + k] = fma(u[1 + k], vd, -(Bd * w.B[k]));
-    F[1 + D] += ptot;
-    F[4] = fma(vd, u[4] + ptot, -(Bd * bv));
-#pragma unroll
-    for (int k = 0; k < 3; ++k) F[5 + k] = (k == D) ? 0.0 : fma(vd, w.B[k], -(Bd * w.v[k]));
-  }
-}
-
-// Fast magnetosonic speed along d (sound speed for hydro).
-template <bool MHD>
-__device__ __forceinline__ double fast_speed(const PrimD& w, int d, double gamma) {
-  const double a2 = gamma * w.p * w.ri;
-  if constexpr (!MHD) {
-    return sqrt(a2);
-  } else {
-    const double b2 = w.b2 * w.ri;
-    const double bd2 = w.B[d] * w.B[d] * w.ri;
-    const double s = a2 + b2;
-    double disc = fma(s, s, -4.0 * a2 * bd2);
-    disc = disc < 0.0 ? 0.0 : disc;
-    return sqrt(0.5 * (s + sqrt(disc)));
-  }
-}
-
-// ---------------------------------------------------------------------------
-// MP5 (Suresh & Huynh 1997), alpha = 4, eps = 0, median form.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double minmod4(double w, double x, double y, double z) {
-  const double lo = fmin(fmin(w, x), fmin(y, z));
-  const double hi = fmax(fmax(w, x), fmax(y, z));
-  return fmax(lo, 0.0) + fmin(hi, 0.0);
-}
-
-__device__ __forceinline__ double mp5(double a, double b, double c, double d, double e) {
-  const double fL = fma(2.0, a, fma(-13.0, b, fma(47.0, c, fma(27.0, d, -3.0 * e)))) * (1.0 / 60.0);
-  const double cb = c - b;
-  const double dm = fma(-2.0, b, a) + c;
-  const double d0 = fma(-2.0, c, b) + d;
-  const double dp = fma(-2.0, d, c) + e;
-  const double m4p = minmod4(fma(4.0, d0, -dp), fma(4.0, dp, -d0), d0, dp);
-  const double m4m = minmod4(fma(4.0, d0, -dm), fma(4.0, dm, -d0), d0, dm);
-  const double fUL = fma(4.0, cb, c);
-  const double fMD = fma(-0.5, m4p, 0.5 * (c + d));
-  const double fLC = fma(4.0 / 3.0, m4m, fma(0.5, cb, c));
-  const double fmn = fmax(fmin(fmin(c, d), fMD), fmin(fmin(c, fUL), fLC));
-  const double fmx = fmin(fmax(fmax(c, d), fMD), fmax(fmax(c, fUL), fLC));
-  return fmin(fmax(fL, fmn), fmx);
-}
-
-// ---------------------------------------------------------------------------
-// Tile geometry helpers (compile time).
-// ---------------------------------------------------------------------------
-template <int TX, int TY, int TZ>
-struct TileShape {
-  static constexpr int T(int d) { return d == 0 ? TX : d == 1 ? TY : TZ; }
-  static constexpr int TC = TX * TY * TZ;
-  // extended box along D (halo of 3 on both sides)
-  static constexpr int E(int D, int d) { return T(d) + (d == D ? 2 * NG : 0); }
-  static constexpr int NEXT(int D) { return E(D, 0) * E(D, 1) * E(D, 2); }
-  static constexpr int SD(int D) { return D == 0 ? 1 : D == 1 ? E(D, 0) : E(D, 0) * E(D, 1); }
-  // interface box along D
-  static constexpr int I(int D, int d) { return T(d) + (d == D ? 1 : 0); }
-  static constexpr int NIFC(int D) { return I(D, 0) * I(D, 1) * I(D, 2); }
-  static constexpr int SI(int D) { return D == 0 ? 1 : D == 1 ? I(D, 0) : I(D, 0) * I(D, 1); }
-};
-
-template <int A, int B>
-struct cmax_i { static constexpr int v = A > B ? A : B; };
-
-__device__ __forceinline__ double wave_max(double x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x = fmax(x, __shfl_xor(x, m, 64));
-  return x;
-}
 
 // ---------------------------------------------------------------------------
 // Fused stage kernel.

@@ -16,72 +16,11 @@
 #include <string>
 #include <vector>
 
-namespace amrvac {
-
-struct StageVariant {
-  int ndim, mhd, tx, ty, tz, nt, ngrp, wpe;
-  const void* fn;
-  void (*launch)(const StageParams&, int grid, hipStream_t);
-  const char* name;
-};
-const StageVariant* stage_variants(int* count);
-void launch_cmax(int ndim, int mhd, const CmaxParams& p, int grid, hipStream_t s);
-void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo, int clear_hi,
-                       hipStream_t s);
-void launch_clear_slot(Control* ctl, int slot, hipStream_t s);
-void launch_set_control(Control* ctl, double dt_fixed, double cfl, double t, hipStream_t s);
-void launch_copy_interior(const StateTable& st, const Tile* tiles, int ntiles, int tx, int ty, int tz, int nv,
-                          int src, int dst, int grid, hipStream_t s);
-
-}  // namespace amrvac
+#include "runtime_internal.h"
 
 using namespace amrvac;
 
 static const char* g_noctx_error = "";
-
-struct GraphEntry {
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-};
-
-struct amrvac_ctx {
-  amrvac_config cfg{};
-  int nvar = 0;
-  int exec = AMRVAC_EXEC_BATCHED;
-  hipStream_t stream = nullptr;
-  hipStream_t cap = nullptr;
-  int device = 0;
-  int ncu = 0;
-  std::string err;
-
-  // blocks
-  std::vector<amrvac_block> hb;
-  std::vector<BlockDev> hdev;
-  BlockDev* d_blocks = nullptr;
-  long long total_cells = 0;    // interior cells of all blocks
-  long long slot_stride = 0;    // doubles per scratch slot
-
-  // tiles of the chosen variant
-  const StageVariant* var = nullptr;
-  int var_index = 0;
-  std::vector<Tile> htiles;
-  Tile* d_tiles = nullptr;
-  std::vector<int> blk_tile_begin, blk_tile_count;
-  int grid_batched = 0;
-
-  // scratch
-  double* d_scr = nullptr;
-  int nslots = 0;
-
-  // control
-  Control* d_ctl = nullptr;
-  double* d_dxtab = nullptr;
-  int ndx = 0;
-  double** d_rhs_ptrs = nullptr;
-  std::vector<double*> hrhs;
-
-  std::map<int, GraphEntry> graphs;
-};
 
 static amrvac_status fail(amrvac_ctx* c, amrvac_status st, const char* fmt, ...) {
   char buf[512];
@@ -228,7 +167,8 @@ static amrvac_status build_tiles(amrvac_ctx* c) {
   return AMRVAC_OK;
 }
 
-static amrvac_status ensure_slots(amrvac_ctx* c, int n) {
+namespace amrvac {
+amrvac_status ensure_slots(amrvac_ctx* c, int n) {
   if (c->nslots >= n) return AMRVAC_OK;
   drop_graphs(c);
   if (c->d_scr) (void)hipFree(c->d_scr);
@@ -239,6 +179,7 @@ static amrvac_status ensure_slots(amrvac_ctx* c, int n) {
   c->nslots = n;
   return AMRVAC_OK;
 }
+}  // namespace amrvac
 
 static amrvac_status select_variant(amrvac_ctx* c, int i) {
   const StageVariant* v = pick_variant(c, i);
@@ -251,13 +192,15 @@ static amrvac_status select_variant(amrvac_ctx* c, int i) {
   return build_tiles(c);
 }
 
-static StateTable state_table(const amrvac_ctx* c) {
+namespace amrvac {
+StateTable state_table(const amrvac_ctx* c) {
   StateTable st;
   st.blocks = c->d_blocks;
   st.scr = c->d_scr;
   st.slot_stride = c->slot_stride;
   return st;
 }
+}  // namespace amrvac
 
 // ---------------------------------------------------------------------------
 // Stage recipes (Sect. 2.3).  Buffer ids: 0 = caller's u (U^n on entry,
@@ -277,7 +220,9 @@ struct Recipe {
   int sdst;
 };
 
-static int scheme_stages(int scheme) { return scheme == AMRVAC_RK3 ? 3 : scheme == AMRVAC_SSPRK43 ? 4 : 5; }
+namespace amrvac {
+int scheme_stages(int scheme) { return scheme == AMRVAC_RK3 ? 3 : scheme == AMRVAC_SSPRK43 ? 4 : 5; }
+}  // namespace amrvac
 
 // SSPRK(5,4) coefficients as printed (Sect. 2.3.2); alpha_50 renormalised so
 // the row sums to one.
@@ -316,31 +261,56 @@ static Recipe with_s(Recipe r, std::initializer_list<std::pair<int, double>> src
   return r;
 }
 
-// Stage recipes with state buffers U (id u0, the step's input and output),
-// and scratch ids A, B, S.
-static std::vector<Recipe> recipes(int scheme, int U, int A, int Bf, int S, int out) {
+// Stage recipes with state buffer U (the step's input, read only), per-stage
+// output buffers outs[1..s] (outs[s] receives U^{n+1}) and the low-storage
+// accumulator S (SSPRK(5,4) only).
+static std::vector<Recipe> recipes(int scheme, int U, const int* o, int S) {
   std::vector<Recipe> r;
   if (scheme == AMRVAC_RK3) {
-    r.push_back(rc(U, {{U, 1.0}}, 1.0, A));
-    r.push_back(rc(A, {{U, 0.75}, {A, 0.25}}, 0.25, Bf));
-    r.push_back(rc(Bf, {{U, 1.0 / 3.0}, {Bf, 2.0 / 3.0}}, 2.0 / 3.0, out));
+    r.push_back(rc(U, {{U, 1.0}}, 1.0, o[1]));
+    r.push_back(rc(o[1], {{U, 0.75}, {o[1], 0.25}}, 0.25, o[2]));
+    r.push_back(rc(o[2], {{U, 1.0 / 3.0}, {o[2], 2.0 / 3.0}}, 2.0 / 3.0, o[3]));
   } else if (scheme == AMRVAC_SSPRK43) {
-    r.push_back(rc(U, {{U, 1.0}}, 0.5, A));
-    r.push_back(rc(A, {{A, 1.0}}, 0.5, Bf));
-    r.push_back(rc(Bf, {{U, 2.0 / 3.0}, {Bf, 1.0 / 3.0}}, 1.0 / 6.0, A));
-    r.push_back(rc(A, {{A, 1.0}}, 0.5, out));
+    r.push_back(rc(U, {{U, 1.0}}, 0.5, o[1]));
+    r.push_back(rc(o[1], {{o[1], 1.0}}, 0.5, o[2]));
+    r.push_back(rc(o[2], {{U, 2.0 / 3.0}, {o[2], 1.0 / 3.0}}, 1.0 / 6.0, o[3]));
+    r.push_back(rc(o[3], {{o[3], 1.0}}, 0.5, o[4]));
   } else {
     const double A50 = 1.0 - (A52 + A53 + A54);
-    r.push_back(rc(U, {{U, 1.0}}, B10, A));                                   // U1 -> A
-    r.push_back(rc(A, {{U, A20}, {A, A21}}, B21, Bf));                        // U2 -> B
-    r.push_back(with_s(rc(Bf, {{U, A30}, {Bf, A32}}, B32, A),                 // U3 -> A
-                       {{U, A50}, {Bf, A52}}, 0.0, S));                       // S = a50 U0 + a52 U2
-    r.push_back(with_s(rc(A, {{U, A40}, {A, A43}}, B43, Bf),                  // U4 -> B
-                       {{S, 1.0}, {A, A53}}, B53, S));                        // S += a53 U3 + dt b53 L(U3)
-    r.push_back(rc(Bf, {{S, 1.0}, {Bf, A54}}, B54, out));                     // U5 -> out
+    r.push_back(rc(U, {{U, 1.0}}, B10, o[1]));                                 // U1
+    r.push_back(rc(o[1], {{U, A20}, {o[1], A21}}, B21, o[2]));                 // U2
+    r.push_back(with_s(rc(o[2], {{U, A30}, {o[2], A32}}, B32, o[3]),           // U3
+                       {{U, A50}, {o[2], A52}}, 0.0, S));                      // S = a50 U0 + a52 U2
+    r.push_back(with_s(rc(o[3], {{U, A40}, {o[3], A43}}, B43, o[4]),           // U4
+                       {{S, 1.0}, {o[3], A53}}, B53, S));                      // S += a53 U3 + dt b53 L(U3)
+    r.push_back(rc(o[4], {{S, 1.0}, {o[4], A54}}, B54, o[5]));                 // U5
   }
   return r;
 }
+
+namespace amrvac {
+void scheme_table(int scheme, double alpha[6][6], double beta[6][6]) {
+  for (int i = 0; i < 6; ++i)
+    for (int k = 0; k < 6; ++k) alpha[i][k] = beta[i][k] = 0.0;
+  if (scheme == AMRVAC_RK3) {
+    alpha[1][0] = 1.0; beta[1][0] = 1.0;
+    alpha[2][0] = 0.75; alpha[2][1] = 0.25; beta[2][1] = 0.25;
+    alpha[3][0] = 1.0 / 3.0; alpha[3][2] = 2.0 / 3.0; beta[3][2] = 2.0 / 3.0;
+  } else if (scheme == AMRVAC_SSPRK43) {
+    alpha[1][0] = 1.0; beta[1][0] = 0.5;
+    alpha[2][1] = 1.0; beta[2][1] = 0.5;
+    alpha[3][0] = 2.0 / 3.0; alpha[3][2] = 1.0 / 3.0; beta[3][2] = 1.0 / 6.0;
+    alpha[4][3] = 1.0; beta[4][3] = 0.5;
+  } else {
+    alpha[1][0] = 1.0; beta[1][0] = B10;
+    alpha[2][0] = A20; alpha[2][1] = A21; beta[2][1] = B21;
+    alpha[3][0] = A30; alpha[3][2] = A32; beta[3][2] = B32;
+    alpha[4][0] = A40; alpha[4][3] = A43; beta[4][3] = B43;
+    alpha[5][0] = 1.0 - (A52 + A53 + A54); alpha[5][2] = A52; alpha[5][3] = A53; alpha[5][4] = A54;
+    beta[5][3] = B53; beta[5][4] = B54;
+  }
+}
+}  // namespace amrvac
 
 static StageParams make_params(const amrvac_ctx* c, const Recipe& r, int cm_in, int cm_out,
                                int cm_reset) {
@@ -389,7 +359,8 @@ static void launch_stage(amrvac_ctx* c, StageParams p, int exec, hipStream_t s) 
   }
 }
 
-static void launch_cmax_of(amrvac_ctx* c, int buf, int slot, hipStream_t s) {
+namespace amrvac {
+void launch_cmax_of(amrvac_ctx* c, int buf, int slot, hipStream_t s) {
   CmaxParams q{};
   q.st = state_table(c);
   q.tiles = c->d_tiles;
@@ -405,16 +376,17 @@ static void launch_cmax_of(amrvac_ctx* c, int buf, int slot, hipStream_t s) {
   int grid = (int)std::min<long long>((long long)c->ncu * 8, (long long)c->htiles.size());
   launch_cmax(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD, q, grid, s);
 }
+}  // namespace amrvac
 
 // One step: dt, then the s stages.  c_max slots: slot 0 holds c_max(U^n);
 // stage i (1-based) reads slot i-1 and accumulates slot i (slot 0 for the
 // last stage, giving c_max(U^{n+1}) for the next step); stage 2 clears slot
 // 0 once stage 1 no longer needs it.
-static void enqueue_step(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U, int A, int Bf,
-                         int S, int out) {
+namespace amrvac {
+void enqueue_step_outs(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U, const int* outs, int S) {
   const int ns = scheme_stages(scheme);
   launch_step_begin(c->d_ctl, c->d_dxtab, c->cfg.ndim, 1, ns - 1, s);
-  std::vector<Recipe> r = recipes(scheme, U, A, Bf, S, out);
+  std::vector<Recipe> r = recipes(scheme, U, outs, S);
   for (int i = 1; i <= ns; ++i) {
     const int cm_in = i - 1;
     const int cm_out = (i == ns) ? 0 : i;
@@ -422,8 +394,19 @@ static void enqueue_step(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int
     launch_stage(c, make_params(c, r[i - 1], cm_in, cm_out, cm_reset), exec, s);
   }
 }
+}  // namespace amrvac
 
-static amrvac_status read_status(amrvac_ctx* c) {
+// Ping-pong form: stages alternate between A and B, the last writes out.
+static void enqueue_step(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U, int A, int Bf, int S,
+                         int out) {
+  const int ns = scheme_stages(scheme);
+  int outs[6];
+  for (int i = 1; i <= ns; ++i) outs[i] = (i == ns) ? out : ((i % 2) ? A : Bf);
+  enqueue_step_outs(c, scheme, exec, s, U, outs, S);
+}
+
+namespace amrvac {
+amrvac_status read_status(amrvac_ctx* c) {
   int err = 0;
   HIP_TRY(c, hipMemcpyAsync(&err, &c->d_ctl->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -435,31 +418,15 @@ static amrvac_status read_status(amrvac_ctx* c) {
   return AMRVAC_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Internal entry points used by the adjoint (adjoint.cpp).
-// ---------------------------------------------------------------------------
-namespace amrvac {
-amrvac_status ctx_ensure_slots(amrvac_ctx* c, int n) { return ensure_slots(c, n); }
-void ctx_enqueue_step(amrvac_ctx* c, int scheme, int U, int A, int Bf, int S, int out) {
-  enqueue_step(c, scheme, AMRVAC_EXEC_BATCHED, c->stream, U, A, Bf, S, out);
+amrvac_status ctx_fail(amrvac_ctx* c, amrvac_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
 }
-void ctx_cmax_of(amrvac_ctx* c, int buf, int slot) { launch_cmax_of(c, buf, slot, c->stream); }
-hipStream_t ctx_stream(amrvac_ctx* c) { return c->stream; }
-StateTable ctx_state(amrvac_ctx* c) { return state_table(c); }
-const Tile* ctx_tiles(amrvac_ctx* c, int* ntiles, int* tx, int* ty, int* tz) {
-  *ntiles = (int)c->htiles.size();
-  *tx = c->var->tx;
-  *ty = c->var->ty;
-  *tz = c->var->tz;
-  return c->d_tiles;
-}
-Control* ctx_control(amrvac_ctx* c) { return c->d_ctl; }
-int ctx_ncu(amrvac_ctx* c) { return c->ncu; }
-const amrvac_config& ctx_config(amrvac_ctx* c) { return c->cfg; }
-const std::vector<amrvac_block>& ctx_blocks(amrvac_ctx* c) { return c->hb; }
-long long ctx_slot_stride(amrvac_ctx* c) { return c->slot_stride; }
-amrvac_status ctx_fail(amrvac_ctx* c, amrvac_status st, const char* msg) { return fail(c, st, "%s", msg); }
-amrvac_status ctx_read_status(amrvac_ctx* c) { return read_status(c); }
 }  // namespace amrvac
 
 // ---------------------------------------------------------------------------

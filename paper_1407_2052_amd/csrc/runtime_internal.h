@@ -1,0 +1,96 @@
+// Host runtime internals shared by runtime.cpp (forward path, C ABI) and
+// adjoint.cpp (reverse mode).
+#pragma once
+#include "amrvac.h"
+#include "amrvac_internal.h"
+
+#include <map>
+#include <string>
+#include <vector>
+
+namespace amrvac {
+
+struct StageVariant {
+  int ndim, mhd, tx, ty, tz, nt, ngrp, wpe;
+  const void* fn;
+  void (*launch)(const StageParams&, int grid, hipStream_t);
+  const char* name;
+};
+const StageVariant* stage_variants(int* count);
+void launch_cmax(int ndim, int mhd, const CmaxParams& p, int grid, hipStream_t s);
+void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo, int clear_hi,
+                       hipStream_t s);
+void launch_clear_slot(Control* ctl, int slot, hipStream_t s);
+void launch_set_control(Control* ctl, double dt_fixed, double cfl, double t, hipStream_t s);
+void launch_copy_interior(const StateTable& st, const Tile* tiles, int ntiles, int tx, int ty, int tz, int nv,
+                          int src, int dst, int grid, hipStream_t s);
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace amrvac
+
+// The context behind the opaque handle of the C ABI.
+struct amrvac_ctx {
+  using BlockDev = amrvac::BlockDev;
+  using StageVariant = amrvac::StageVariant;
+  using Tile = amrvac::Tile;
+  using Control = amrvac::Control;
+  using GraphEntry = amrvac::GraphEntry;
+
+  amrvac_config cfg{};
+  int nvar = 0;
+  int exec = AMRVAC_EXEC_BATCHED;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  int device = 0;
+  int ncu = 0;
+  std::string err;
+
+  // blocks
+  std::vector<amrvac_block> hb;
+  std::vector<BlockDev> hdev;
+  BlockDev* d_blocks = nullptr;
+  long long total_cells = 0;    // interior cells of all blocks
+  long long slot_stride = 0;    // doubles per scratch slot
+
+  // tiles of the chosen variant
+  const StageVariant* var = nullptr;
+  int var_index = 0;
+  std::vector<Tile> htiles;
+  Tile* d_tiles = nullptr;
+  std::vector<int> blk_tile_begin, blk_tile_count;
+  int grid_batched = 0;
+
+  // scratch
+  double* d_scr = nullptr;
+  int nslots = 0;
+
+  // control
+  Control* d_ctl = nullptr;
+  double* d_dxtab = nullptr;
+  int ndx = 0;
+  double** d_rhs_ptrs = nullptr;
+  std::vector<double*> hrhs;
+
+  std::map<int, GraphEntry> graphs;
+};
+
+
+namespace amrvac {
+// Helpers implemented in runtime.cpp.
+amrvac_status ctx_fail(amrvac_ctx* c, amrvac_status st, const char* fmt, ...);
+amrvac_status ensure_slots(amrvac_ctx* c, int n);
+StateTable state_table(const amrvac_ctx* c);
+int scheme_stages(int scheme);
+// One step of `scheme` with state buffer U (read), per-stage output buffers
+// outs[1..s] (outs[s] receives U^{n+1}) and low-storage accumulator S.
+void enqueue_step_outs(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U, const int* outs, int S);
+void launch_cmax_of(amrvac_ctx* c, int buf, int slot, hipStream_t s);
+amrvac_status read_status(amrvac_ctx* c);
+// Shu-Osher table (Sect. 2.3) as used by the stage recipes: alpha[i][k],
+// beta[i][k] for stages i = 1..s.
+void scheme_table(int scheme, double alpha[6][6], double beta[6][6]);
+}  // namespace amrvac

@@ -1,0 +1,210 @@
+"""GPU adjoint (amrvac_ssprk_adjoint, through the C ABI) against the oracle's
+forward-mode JVP and against central differences.
+
+Bar: <lam_0, dU_0> (GPU reverse mode) equals <lam_N, J dU_0> (oracle dual
+numbers) to 1e-10 relative on non-kinked states; the full gradient of a
+tiny grid equals the brute-force oracle Jacobian (one JVP per input) to
+1e-10 of its largest entry; checkpoint intervals change nothing (bitwise);
+gradients match central differences of the GPU forward map to 1e-6.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import smooth_fields
+from paper_1407_2052_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1407_2052_amd import amrvac as A  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def periodic_state(ndim, mhd, N, block, seed, gamma=None):
+    n, dx, xlo, nbr, _ = inputs.uniform_blocks(ndim, [N] * ndim, [block] * ndim)
+    g = gamma if gamma is not None else (5 / 3 if mhd else 1.4)
+    return inputs.sample_blocks(ndim, mhd, g, n, dx, xlo, nbr, smooth_fields(ndim, mhd, seed, amp=0.08))
+
+
+def gpu_adjoint(bs, scheme, dt, nsteps, ckpt, lam_n):
+    ctx, flat, views = A.context_for(bs)
+    before = flat.clone()
+    lam = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in lam_n]
+    ctx.ssprk_adjoint(scheme, dt, nsteps, ckpt, lam)
+    torch.cuda.synchronize()
+    assert torch.equal(before, flat), "the adjoint must not modify U_0"
+    out = [x.cpu().numpy() for x in lam]
+    ctx.close()
+    return out
+
+
+def fixed_dt(bs, cfl=0.3):
+    _, cm = oracle.rhs(bs)
+    return cfl / sum(cm[d] / bs.dx[0, d] for d in range(bs.ndim))
+
+
+def interior_dot(bs, a, b):
+    return math.fsum(float(np.vdot(bs.interior(i, x), bs.interior(i, y))) for i, (x, y) in enumerate(zip(a, b)))
+
+
+def random_cotangent(bs, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(bs.nb):
+        x = np.zeros(bs.padded_shape(b))
+        bs.interior(b, x)[...] = rng.normal(size=bs.interior(b).shape)
+        out.append(x)
+    return out
+
+
+CASES = [
+    ("hydro1d", 1, False, 64, 16, oracle.SSPRK54, 6, 2),
+    ("mhd1d", 1, True, 64, 32, oracle.RK3, 6, 4),
+    ("hydro2d", 2, False, 32, 16, oracle.SSPRK54, 4, 3),
+    ("hydro2d_rk3", 2, False, 32, 16, oracle.RK3, 5, 2),
+    ("mhd2d", 2, True, 32, 16, oracle.SSPRK54, 3, 2),
+    ("mhd2d_43", 2, True, 32, 16, oracle.SSPRK43, 3, 1),
+    ("hydro3d", 3, False, 16, 8, oracle.SSPRK54, 2, 1),
+    ("mhd3d", 3, True, 16, 8, oracle.SSPRK54, 2, 2),
+]
+
+
+@pytest.mark.parametrize("case,ndim,mhd,N,block,scheme,nsteps,ckpt", CASES, ids=[c[0] for c in CASES])
+def test_dot_product_against_oracle_jvp(case, ndim, mhd, N, block, scheme, nsteps, ckpt):
+    say(f"[adjoint dot] {case}")
+    bs = periodic_state(ndim, mhd, N, block, seed=ndim * 10 + mhd)
+    dt = fixed_dt(bs)
+    tang = inputs.random_tangent(bs, 3)
+    lam_n = random_cotangent(bs, 4)
+    _, du = oracle.run_jvp(bs, tang, scheme, nsteps, dt)
+    lam0 = gpu_adjoint(bs, scheme, dt, nsteps, ckpt, lam_n)
+    lhs = interior_dot(bs, lam0, tang)
+    rhs = interior_dot(bs, lam_n, du)
+    assert abs(lhs - rhs) <= 1e-10 * max(abs(rhs), 1e-300), (lhs, rhs)
+    for b in range(bs.nb):   # ghost layers of the gradient are zero
+        g = lam0[b].copy()
+        bs.interior(b, g)[...] = 0.0
+        assert np.all(g == 0.0)
+
+
+@pytest.mark.parametrize("mhd", [False, True])
+def test_full_gradient_against_brute_force_jacobian(mhd):
+    say(f"[adjoint brute force] mhd={mhd}")
+    bs = periodic_state(2, mhd, 8, 8, seed=7 + mhd)
+    dt = fixed_dt(bs)
+    nsteps = 2
+    lam_n = random_cotangent(bs, 9)
+    lam0 = gpu_adjoint(bs, oracle.SSPRK54, dt, nsteps, 1, lam_n)[0]
+    ref = np.zeros_like(lam0)
+    for v in range(bs.nvar):
+        for j in range(8):
+            for i in range(8):
+                e = np.zeros(bs.padded_shape(0))
+                e[v, 0, j + 3, i + 3] = 1.0
+                _, du = oracle.run_jvp(bs, [e], oracle.SSPRK54, nsteps, dt)
+                ref[v, 0, j + 3, i + 3] = interior_dot(bs, lam_n, du)
+    scale = np.abs(ref).max()
+    assert np.abs(lam0 - ref).max() <= 1e-10 * scale, np.abs(lam0 - ref).max() / scale
+
+
+def test_checkpoint_interval_changes_nothing_bitwise():
+    say("[adjoint checkpoints]")
+    bs = periodic_state(2, True, 32, 16, seed=3)
+    dt = fixed_dt(bs)
+    lam_n = random_cotangent(bs, 5)
+    ref = gpu_adjoint(bs, oracle.SSPRK54, dt, 7, 7, lam_n)
+    for k in (1, 2, 3, 10):
+        got = gpu_adjoint(bs, oracle.SSPRK54, dt, 7, k, lam_n)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), k
+
+
+def test_zero_steps_is_identity():
+    bs = periodic_state(2, False, 32, 16, seed=1)
+    lam_n = random_cotangent(bs, 2)
+    got = gpu_adjoint(bs, oracle.SSPRK54, 1e-3, 0, 1, lam_n)
+    for x, y in zip(got, lam_n):
+        assert np.array_equal(x, y)
+
+
+def test_unsupported_inputs_are_reported():
+    bs = inputs.sod(64)   # fixed faces
+    ctx, flat, views = A.context_for(bs)
+    lam = [torch.zeros_like(v) for v in views]
+    with pytest.raises(A.AmrvacError) as ei:
+        ctx.ssprk_adjoint(oracle.SSPRK54, 1e-3, 1, 1, lam)
+    assert ei.value.status == A.ERR_UNSUPPORTED
+    ctx.close()
+    n, dx, xlo, nbr, _ = inputs.uniform_blocks(1, [16], [4])   # blocks of 4 < 5 cells
+    bs = inputs.sample_blocks(1, False, 1.4, n, dx, xlo, nbr, smooth_fields(1, False, 0))
+    ctx, flat, views = A.context_for(bs)
+    lam = [torch.zeros_like(v) for v in views]
+    with pytest.raises(A.AmrvacError) as ei:
+        ctx.ssprk_adjoint(oracle.SSPRK54, 1e-3, 1, 1, lam)
+    assert ei.value.status == A.ERR_UNSUPPORTED
+    with pytest.raises(A.AmrvacError) as ei:
+        ctx.ssprk_adjoint(oracle.SSPRK54, -1.0, 1, 1, lam)
+    assert ei.value.status == A.ERR_INVALID
+    ctx.close()
+
+
+def loss_and_forward(bs, rho0_interior, target, dt, nsteps, device_views=None):
+    """J = 1/2 sum (rho_N - rho*)^2 with v = 0, p = 1 fixed (E = p/(gamma-1))."""
+    cur = bs.copy()
+    for b in range(bs.nb):
+        cur.interior(b)[0] = rho0_interior[b]
+    ctx, flat, views = A.context_for(cur)
+    ctx.ssprk_step(oracle.SSPRK54, nsteps, dt=dt, t=0.0)
+    J = 0.0
+    rhoN = []
+    for b, v in enumerate(views):
+        r = cur.interior(b, v.cpu().numpy())[0]
+        rhoN.append(r)
+        J += 0.5 * float(((r - target[b]) ** 2).sum())
+    ctx.close()
+    return J, rhoN
+
+
+def test_hydro_density_gradient_matches_central_differences_full_size():
+    """256^2 periodic Euler (256 blocks of 16^2), 200 SSPRK(5,4) steps at a
+    fixed dt, checkpoints every 20 steps; gradient of J w.r.t. the initial
+    density at fixed v = 0, p = 1 (dJ/drho_0 = lam_0 in the density slot)."""
+    say("[adjoint FD] 2D hydro 256^2, 200 steps")
+    bs = inputs.hydro_random_2d()
+    target = inputs.hydro_target_density()
+    nsteps = 200
+    _, cm = oracle.rhs(bs)
+    dt = 0.4 / sum(cm[d] / bs.dx[0, d] for d in range(2))
+    rho0 = [bs.interior(b)[0].copy() for b in range(bs.nb)]
+    J0, rhoN = loss_and_forward(bs, rho0, target, dt, nsteps)
+    lam_n = []
+    for b in range(bs.nb):
+        x = np.zeros(bs.padded_shape(b))
+        bs.interior(b, x)[0] = rhoN[b] - target[b]
+        lam_n.append(x)
+    lam0 = gpu_adjoint(bs, oracle.SSPRK54, dt, nsteps, 20, lam_n)
+    grad = [bs.interior(b, lam0[b])[0] for b in range(bs.nb)]
+    # smooth random direction in density (4 modes)
+    dirs = inputs.random_tangent(bs, 41, vars_=[0])
+    drho = [bs.interior(b, dirs[b])[0] for b in range(bs.nb)]
+    an = math.fsum(float((g * d).sum()) for g, d in zip(grad, drho))
+    fds = []
+    for h in (1e-6, 5e-7):
+        Jp, _ = loss_and_forward(bs, [r + h * d for r, d in zip(rho0, drho)], target, dt, nsteps)
+        Jm, _ = loss_and_forward(bs, [r - h * d for r, d in zip(rho0, drho)], target, dt, nsteps)
+        fds.append((Jp - Jm) / (2 * h))
+    say(f"  analytic {an:.15e}  fd {fds[0]:.15e} {fds[1]:.15e}")
+    # the two step sizes agree (non-kinked) and the adjoint matches them
+    assert abs(fds[0] - fds[1]) <= 1e-7 * abs(an)
+    assert abs(an - fds[1]) <= 1e-6 * abs(an), (an, fds)
