@@ -24,14 +24,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MHD cell-updates/s (batched vs per-block, FP64) + adjoint/forward time ratio"
 
-# Algorithmic FP64 work of one cell in one stage of 3D ideal MHD (the
-# operation count of the scheme as defined, each +, -, *, /, sqrt, min, max
-# counted once; derivation in the design notes):
-#   per direction: primitive recovery 19, flux 30, split 40,
-#   8 variables x (2 MP5 x 68 + 1), difference 24           -> 1209
-#   three directions                                          -> 3627
-#   stage combination 56, next-stage c_max 67                 -> 3750
-FLOPS_PER_CELL_STAGE_MHD3D = 3750
+# Algorithmic FP64 work of one cell in one stage of 3D ideal MHD: the
+# operation count of the scheme as defined (each cell's flux evaluated once
+# per direction, each interface once), each +, -, *, /, sqrt, min, max
+# counted once and a fused multiply-add as two:
+#   per direction: primitive recovery 20, flux 27, split 40,
+#   8 variables x (2 MP5 x 68 + 1), difference 24           -> 1207
+#   three directions                                          -> 3621
+#   stage combination 50 (SSPRK(5,4) average), c_max of the
+#   new state 65                                              -> 3736
+FLOPS_PER_CELL_STAGE_MHD3D = 3736
 # Algorithmic HBM bytes per cell per SSPRK(5,4) step: 17 state passes x 8
 # variables x 8 bytes (low-storage form: 2+3+4+5+3 passes).
 BYTES_PER_CELL_STEP_MHD3D = 17 * 8 * 8
@@ -95,6 +97,49 @@ def cpu_baseline(bs_full, min_seconds=10.0, max_steps=4):
                       f"{steps} SSPRK(5,4) steps, {el:.1f} s wall, OpenMP over blocks"}
 
 
+def adjoint_ratio(nsteps, ckpt):
+    """Adjoint / forward wall-time ratio on 3D ideal MHD, 256^3 periodic as
+    4096 blocks of 16^3 (16-mode velocity and field perturbations, plasma
+    beta 1): nsteps fixed-dt SSPRK(5,4) steps forward, then the adjoint of
+    the same nsteps (checkpoints every `ckpt` steps, recompute included)."""
+    import torch
+    from paper_1407_2052_amd import amrvac, inputs
+
+    print("bench: generating 3D MHD 256^3 periodic (4096 x 16^3)", file=sys.stderr, flush=True)
+    bs = inputs.mhd_turbulence_3d()
+    cells = bs.interior_cells()
+    ctx, flat, views = amrvac.context_for(bs, amrvac.EXEC_BATCHED)
+    _, cm = ctx.fd_rhs()
+    dt = 0.4 / sum(cm[d] / bs.dx[0, d] for d in range(3))
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    u0 = flat.clone()
+    ctx.ssprk_step(amrvac.SSPRK54, 1, dt=dt, t=None)      # warm-up (graph capture)
+    flat.copy_(u0)
+    torch.cuda.synchronize()
+    e[0].record(stream)
+    ctx.ssprk_step(amrvac.SSPRK54, nsteps, dt=dt, t=None)
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    ctx.sync()
+    fwd = e[0].elapsed_time(e[1]) / 1e3
+    lam = [torch.zeros_like(v) for v in views]
+    for l in lam:
+        l[0, 3:-3, 3:-3, 3:-3] = 1e-3
+    flat.copy_(u0)
+    print(f"bench: adjoint of {nsteps} steps (checkpoints every {ckpt})", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    e[2].record(stream)
+    ctx.ssprk_adjoint(amrvac.SSPRK54, dt, nsteps, ckpt, lam)
+    e[3].record(stream)
+    torch.cuda.synchronize()
+    adj = e[2].elapsed_time(e[3]) / 1e3
+    ctx.close()
+    return {"workload": "3D ideal MHD 256^3 periodic, 4096 x 16^3, SSPRK(5,4)", "steps": nsteps,
+            "ckpt_every": ckpt, "forward_s": fwd, "adjoint_s": adj, "ratio": adj / fwd,
+            "forward_cell_updates_per_s": cells * nsteps / fwd}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +148,11 @@ def main():
     ap.add_argument("--per-block-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-block", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=20)
+    ap.add_argument("--ckpt", type=int, default=5)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also run one plain device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs (--gpus > 1) are not "
@@ -118,6 +168,8 @@ def main():
     torch.cuda.set_device(0)
     ctx, flat, views = amrvac.context_for(bs, amrvac.EXEC_BATCHED)
     stream = torch.cuda.current_stream()
+    print("bench: autotuning the tile shape", file=sys.stderr, flush=True)
+    variant, tune_ms = ctx.autotune(amrvac.SSPRK54, 2)
 
     def timed(nsteps, warmup):
         if warmup:
@@ -148,6 +200,21 @@ def main():
         ctx.set_exec(amrvac.EXEC_BATCHED)
     ctx.close()
 
+    if args.copy_probe > 0:
+        # a plain copy kernel of known size: FETCH_SIZE / WRITE_SIZE of this
+        # dispatch calibrate the counters against bytes really moved
+        n = args.copy_probe // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = adjoint_ratio(args.adjoint_steps, args.ckpt)
+
     flops = FLOPS_PER_CELL_STAGE_MHD3D * cells
     achieved = flops / stage_s / 1e12
     traffic = measured_traffic()
@@ -170,10 +237,12 @@ def main():
         "config": {"workload": "3D ideal MHD, 4096 uneven blocks 32^3:16^3:8^3 (1:2:4), fixed ghosts "
                                "from a seeded 8-mode field, SSPRK(5,4)+MP5+global LF, CFL 0.4",
                    "blocks": bs.nb, "cells": cells, "exec": "batched persistent, HIP graph per step",
+                   "tile_shape": variant,
                    "parallelism": "single GPU"},
         "per_block": per_block,
         "batched_over_per_block": (value / per_block["value"]) if per_block else None,
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": adjoint["ratio"] if adjoint else None,
+        "adjoint": adjoint,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
