@@ -44,7 +44,7 @@ STAGES = 5
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "runtime.cpp", "amrvac_internal.h"):
+    for f in ("kernels.hip", "device_math.h", "runtime.cpp", "amrvac_internal.h"):
         with open(os.path.join(ROOT, "paper_1407_2052_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

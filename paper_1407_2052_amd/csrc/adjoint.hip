@@ -273,7 +273,8 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) cin[d] = __longlong_as_double((long long)P.ctl->cm[P.cm_slot][d]);
 
-  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) {
+  const TileSchedule sched(P.ntiles);
+  for (int t = sched.t; t < sched.end; t += sched.step) {
     const Tile tl = P.tiles[t];
     const BlockDev& B = st.blocks[tl.block];
     int tend[3];

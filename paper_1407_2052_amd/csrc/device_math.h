@@ -226,6 +226,31 @@ struct TileShape {
 template <int A, int B>
 struct cmax_i { static constexpr int v = A > B ? A : B; };
 
+// XCD-aware persistent tile schedule.  Work-groups of a launch are
+// dispatched round-robin over the 8 XCDs (work-group w on XCD w % 8), each
+// XCD with its own L2.  The tile list (Morton-ordered, so contiguous ranges
+// are compact in space) is cut into 8 contiguous chunks and chunk x is
+// processed only by the work-groups of XCD x, so tiles whose halos overlap
+// mostly share one L2.  Every tile is visited exactly once; with fewer than
+// 8 work-groups the schedule is the plain grid stride.
+struct TileSchedule {
+  int t, end, step;
+  __device__ __forceinline__ TileSchedule(int ntiles) {
+    const int G = (int)gridDim.x, w = (int)blockIdx.x;
+    if (G < 8) {
+      t = w;
+      end = ntiles;
+      step = G;
+    } else {
+      const int x = w & 7, r = w >> 3;
+      const int gx = (G - x + 7) >> 3;   // work-groups on XCD x
+      t = (int)((long long)ntiles * x / 8) + r;
+      end = (int)((long long)ntiles * (x + 1) / 8);
+      step = gx;
+    }
+  }
+};
+
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) x = fmax(x, __shfl_xor(x, m, 64));

@@ -78,7 +78,8 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
   double run[3] = {0.0, 0.0, 0.0};
   bool ok_all = true;
 
-  for (int t = blockIdx.x; t < P.ntiles; t += gridDim.x) {
+  const TileSchedule sched(P.ntiles);
+  for (int t = sched.t; t < sched.end; t += sched.step) {
     const Tile tl = P.tiles[P.tile_begin + t];
     const BlockDev& B = st.blocks[tl.block];
     int tend[3];

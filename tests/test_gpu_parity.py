@@ -284,6 +284,51 @@ def test_full_size_3d_rhs_on_sampled_blocks(which):
     compare_rhs(sub, [Lg[i] for i in idx], Lo, cmo)
 
 
+def test_full_size_uneven3d_10_steps_in_bench_configuration():
+    """The 4096-block uneven 3D MHD list in the configuration bench.py times
+    (autotuned tile shape, batched persistent launch, one graph per step):
+    10 SSPRK(5,4) steps are bitwise equal to the per-block launch form, and
+    the right-hand side of the state they reach matches the oracle on
+    sampled blocks."""
+    say("[full] uneven3d 4096 blocks: autotune + 10 batched steps")
+    bs = inputs.uneven_3d()
+    ctx, flat, views = A.context_for(bs, A.EXEC_BATCHED)
+    ctx.autotune(oracle.SSPRK54, 1)
+    t_b = ctx.ssprk_step(oracle.SSPRK54, 10, cfl=0.4, t=0.0)
+    out = bs.copy()
+    out.u = host_blocks(views)
+    ctx.close()
+    say("[full] uneven3d 4096 blocks: 10 per-block steps")
+    ref, t_p = gpu_run(bs, oracle.SSPRK54, 10, exec=A.EXEC_PER_BLOCK)
+    assert t_b == t_p
+    for x, y in zip(out.u, ref.u):
+        assert np.array_equal(x, y)
+    say("[full] uneven3d 4096 blocks: rhs of the stepped state, sampled blocks")
+    Lg, cmg = gpu_rhs(out)
+    cmo = oracle.cmax(out)
+    np.testing.assert_allclose(cmg, cmo, rtol=1e-14)
+    rng = np.random.default_rng(1)
+    idx = np.unique(np.concatenate([rng.choice(out.nb, 24, replace=False), [0, out.nb - 1]]))
+    sub = sample_blocks_with_true_ghosts(out, idx)
+    Lo, _ = oracle.rhs(sub, cmax=cmo)
+    compare_rhs(sub, [Lg[i] for i in idx], Lo, cmo)
+
+
+def test_full_size_mhd3d_256_conserves_totals():
+    """256^3 periodic 3D MHD (4096 blocks of 16^3): after 10 batched
+    SSPRK(5,4) steps the totals of all eight conserved variables equal their
+    initial totals to rounding (the scheme is conservative and the grid is
+    periodic)."""
+    say("[full] mhd3d 256^3: 10 steps, conserved totals")
+    bs = inputs.mhd_turbulence_3d()
+    tot0 = [math.fsum(float(bs.interior(b)[v].sum()) for b in range(bs.nb)) for v in range(bs.nvar)]
+    mag = [math.fsum(float(np.abs(bs.interior(b)[v]).sum()) for b in range(bs.nb)) for v in range(bs.nvar)]
+    out, _ = gpu_run(bs, oracle.SSPRK54, 10)
+    tot1 = [math.fsum(float(out.interior(b)[v].sum()) for b in range(out.nb)) for v in range(out.nvar)]
+    for v in range(bs.nvar):
+        assert abs(tot1[v] - tot0[v]) <= 1e-12 * mag[v], (v, tot0[v], tot1[v], mag[v])
+
+
 # ---------------------------------------------------------------- tile shapes
 @pytest.mark.parametrize("case", ["dwave1d_8blk", "ot2d", "hydro2d", "ragged2d_mhd", "mhd3d", "uneven3d",
                                   "ragged3d_hd", "ragged3d_mhd"])
