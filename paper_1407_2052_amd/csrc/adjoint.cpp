@@ -10,7 +10,9 @@
 // processed, so each stage state costs exactly one vector-Jacobian product.
 //
 // Memory: checkpoints of U every ckpt_every steps; a segment is recomputed
-// from its checkpoint with every stage state stored, then reversed.
+// from its checkpoint with every stage state stored, together with the MP5
+// linear-piece codes of L at each of them (8 bytes per cell and direction),
+// then reversed.
 #include "runtime_internal.h"
 
 #include <algorithm>
@@ -57,7 +59,10 @@ struct Adj {
   long long* d_targ = nullptr;
   double* d_cpart = nullptr;
   double** d_ptrs = nullptr;
+  unsigned char* d_codes = nullptr;   // MP5 piece codes of every stage state of a segment
+  long long code_plane = 0;           // bytes per direction: 8 per cell
   int grid_vjp = 0;
+  int grid_emit = 0;
   int grid_small = 0;
 
   ~Adj() {
@@ -66,6 +71,7 @@ struct Adj {
     if (d_targ) (void)hipFree(d_targ);
     if (d_cpart) (void)hipFree(d_cpart);
     if (d_ptrs) (void)hipFree(d_ptrs);
+    if (d_codes) (void)hipFree(d_codes);
   }
 
   int ntiles() const { return (int)htiles.size(); }
@@ -101,8 +107,10 @@ struct Adj {
     }
   }
 
-  // lam += dt * J_L(state)^T mu, including the c_max term
-  void vjp(int state, int mu, int lam, double dt) {
+  // dst = sum lam_t + dt * J_L(state)^T (sum mu_t), including the c_max
+  // term; `codes` are the MP5 pieces of L(state) from the recompute
+  void vjp(int state, const unsigned char* codes, const std::vector<std::pair<int, double>>& mu_t,
+           const std::vector<std::pair<int, double>>& lam_t, int dst, double dt) {
     StateTable st = state_table(c);
     V->argmax(st, d_tiles, ntiles(), V->tx, V->ty, V->tz, c->cfg.gamma, state, d_tmax, d_targ, grid_small,
               c->stream);
@@ -114,13 +122,24 @@ struct Adj {
     p.ctl = c->d_ctl;
     p.gamma = c->cfg.gamma;
     p.in = state;
-    p.mu = mu;
-    p.lam = lam;
+    p.codes = codes;
+    p.code_plane = code_plane;
+    p.nmu = (int)mu_t.size();
+    for (int q = 0; q < p.nmu; ++q) {
+      p.mu_src[q] = mu_t[q].first;
+      p.mu_a[q] = mu_t[q].second;
+    }
+    p.nlam = (int)lam_t.size();
+    for (int q = 0; q < p.nlam; ++q) {
+      p.lam_src[q] = lam_t[q].first;
+      p.lam_a[q] = lam_t[q].second;
+    }
+    p.dst = dst;
     p.scale = dt;
     p.cm_slot = VJP_SLOT;
     p.cpart = d_cpart;
     V->launch(p, grid_vjp, c->stream);
-    V->cmax_term(st, (int)c->hb.size(), d_cpart, ntiles(), c->d_ctl, c->cfg.gamma, state, lam, dt, c->stream);
+    V->cmax_term(st, (int)c->hb.size(), d_cpart, ntiles(), c->d_ctl, c->cfg.gamma, state, dst, dt, c->stream);
   }
 };
 
@@ -164,14 +183,16 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
     for (int i = 0; i < s; ++i) X[j][i] = next++;
   std::vector<int> Lm(s + 1);
   for (int i = 0; i <= s; ++i) Lm[i] = next++;
-  const int MU = next++;
   amrvac_status st = ensure_slots(c, next - 1);
   if (st != AMRVAC_OK) return st;
 
   Adj adj;
   adj.c = c;
   adj.V = vjp_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD);
-  if (!adj.V) return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: no kernel for this ndim/physics");
+  const StageVariant* EV = emit_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD);
+  if (!adj.V || !EV) return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: no kernel for this ndim/physics");
+  if (EV->tx != adj.V->tx || EV->ty != adj.V->ty || EV->tz != adj.V->tz)
+    return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: recompute and adjoint tile shapes differ");
   {
     const int T[3] = {adj.V->tx, adj.V->ty, adj.V->tz};
     for (int b = 0; b < nb; ++b) {
@@ -208,11 +229,23 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
   if ((st = hip_ok(hipMemcpyAsync(adj.d_ptrs, hptrs.data(), sizeof(double*) * nb, hipMemcpyHostToDevice, c->stream),
                    "upload")) != AMRVAC_OK)
     return st;
+  // codes of the k * s stage states of one segment, ndim planes each
+  adj.code_plane = c->total_cells * 8;
+  const size_t code_bytes = (size_t)adj.code_plane * (size_t)c->cfg.ndim * (size_t)s * (size_t)k;
+  if ((st = hip_ok(hipMalloc(&adj.d_codes, code_bytes), "hipMalloc (MP5 piece codes)")) != AMRVAC_OK) return st;
+  auto codes_of = [&](int j, int kst) {
+    return adj.d_codes + ((size_t)j * s + kst) * (size_t)c->cfg.ndim * (size_t)adj.code_plane;
+  };
   int per_cu = 0;
   if ((st = hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj.V->fn, adj.V->nt, 0), "occupancy")) !=
       AMRVAC_OK)
     return st;
   adj.grid_vjp = std::max(1, std::min(std::max(per_cu, 1) * c->ncu, nt));
+  per_cu = 0;
+  if ((st = hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, EV->fn, EV->nt, 0), "occupancy")) !=
+      AMRVAC_OK)
+    return st;
+  adj.grid_emit = std::max(1, std::min(std::max(per_cu, 1) * c->ncu, nt));
   adj.grid_small = std::max(1, std::min(c->ncu * 8, nt));
 
   double alpha[6][6], beta[6][6];
@@ -251,7 +284,14 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
       int outs[6];
       for (int i = 1; i < s; ++i) outs[i] = X[j][i];
       outs[s] = (j + 1 < kk) ? X[j + 1][0] : W0;   // the segment's last output is not needed
-      enqueue_step_outs(c, scheme, exec, c->stream, X[j][0], outs, S);
+      EmitPlan plan{};
+      plan.var = EV;
+      plan.tiles = adj.d_tiles;
+      plan.ntiles = nt;
+      plan.grid = adj.grid_emit;
+      for (int i = 0; i < s; ++i) plan.codes[i] = codes_of(j, i);
+      plan.code_plane = adj.code_plane;
+      enqueue_step_outs(c, scheme, exec, c->stream, X[j][0], outs, S, &plan);
     }
     // reverse the segment's steps
     for (int j = kk - 1; j >= 0; --j) {
@@ -270,11 +310,10 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
           if (alpha[i][kst] != 0.0) lam_t.push_back({L[i], alpha[i][kst]});
         }
         if (lam_t.empty()) lam_t.push_back({L[s], 0.0});
-        adj.combine(L[kst], lam_t);
-        if (!mu_t.empty()) {
-          adj.combine(MU, mu_t);
-          adj.vjp(X[j][kst], MU, L[kst], dt);
-        }
+        if (mu_t.empty())
+          adj.combine(L[kst], lam_t);
+        else
+          adj.vjp(X[j][kst], codes_of(j, kst), mu_t, lam_t, L[kst], dt);
       }
       R = L[0];
     }

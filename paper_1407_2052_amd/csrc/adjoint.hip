@@ -2,23 +2,20 @@
 // Sects. 2.1-2.2) on gfx950, used by the adjoint of the SSPRK time
 // integration (Sect. 2.3).
 //
-// k_vjp computes lam += scale * J_L(U)^T mu for the local dependence of L
-// on U (everything but the global c_max), as a gather per cell so that no
-// atomics are needed and the result is deterministic.  Per tile, direction D
-// and variable group:
-//   A) F+ and F- of the tile extended by 5 cells along D (recomputed with the
-//      forward's own device functions, so bitwise equal to the forward), and
-//      mu on the tile extended by 3 cells, into LDS;
-//   B) for every interface i+1/2 with i in [o-3, o+T+2): the interface
-//      adjoint lamFhat = (mu_{i+1} - mu_i) / dx and the linear piece of MP5
-//      taken at the F+ and F- stencils.  MP5 with eps = 0 is continuous and
-//      piecewise linear, so each piece is one of 14 constant weight vectors
-//      and is stored as a one-byte code;
-//   C) for every owned cell j: lamF+_j = sum_{i=j-2..j+2} lamFhat_i w+_i,
-//      lamF-_j = sum_{i=j-3..j+1} lamFhat_i w-_i (fixed order), then the
-//      split adjoint (lamF = (lamF+ + lamF-)/2, c (lamF+ - lamF-)/2) and the
-//      transpose of the flux Jacobian (hand-written reverse of the primitive
-//      recovery and flux).
+// k_vjp computes dst = sum_q a_q lam_q + scale * J_L(U)^T mu for the local
+// dependence of L on U (everything but the global c_max), as a gather per
+// cell so that no atomics are needed and the result is deterministic.  MP5
+// with eps = 0 is continuous and piecewise linear, so its derivative at U is
+// one of 14 constant weight vectors per reconstruction; the forward
+// recompute of U's stage records which one as a 4-bit code per (interface,
+// variable, sign), and k_vjp reads those codes instead of re-evaluating the
+// split fluxes and the limiter.  Per cell j and direction d:
+//   lamFhat_{i+1/2} = (mu_{i+1} - mu_i) / dx_d,
+//   lamF+_j = sum over interfaces i = j-2 .. j+2 of lamFhat w+_i,
+//   lamF-_j = sum over interfaces i = j-3 .. j+1 of lamFhat w-_i,
+// then the split adjoint (lamF = (lamF+ + lamF-)/2, c (lamF+ - lamF-)/2) and
+// the transpose of the flux Jacobian (hand-written reverse of the primitive
+// recovery and flux).
 // The c_max term sum_j U_j (lamF+_j - lamF-_j)/2 is summed per tile; a
 // second kernel adds its product with d(|v_d| + c_f,d)/dU at the maximising
 // cell (lowest block, then lowest cell index, on ties).
@@ -45,65 +42,6 @@ __constant__ double c_mp5w[14][5] = {
     {0.0, 5.0 / 6.0, -7.0 / 6.0, 4.0 / 3.0, 0.0},
     {4.0 / 3.0, -19.0 / 6.0, 17.0 / 6.0, 0.0, 0.0},
 };
-
-// Argument (1..4) that minmod4 returns, 0 when it returns zero; ties go to
-// the earlier argument.
-__device__ __forceinline__ int minmod4_pick(double w, double x, double y, double z) {
-  if (w > 0.0 && x > 0.0 && y > 0.0 && z > 0.0) {
-    int k = 1;
-    double m = w;
-    if (x < m) { m = x; k = 2; }
-    if (y < m) { m = y; k = 3; }
-    if (z < m) { k = 4; }
-    return k;
-  }
-  if (w < 0.0 && x < 0.0 && y < 0.0 && z < 0.0) {
-    int k = 1;
-    double m = w;
-    if (x > m) { m = x; k = 2; }
-    if (y > m) { m = y; k = 3; }
-    if (z > m) { k = 4; }
-    return k;
-  }
-  return 0;
-}
-
-// Linear piece of mp5(a, b, c, d, e) (same arithmetic as the forward): the
-// forward returns clamp(fL, fmin, fmax); ties go to fL, and within min/max
-// chains to the earlier candidate.
-__device__ __forceinline__ int mp5_code(double a, double b, double c, double d, double e) {
-  const double fL = fma(2.0, a, fma(-13.0, b, fma(47.0, c, fma(27.0, d, -3.0 * e)))) * (1.0 / 60.0);
-  const double cb = c - b;
-  const double dm = fma(-2.0, b, a) + c;
-  const double d0 = fma(-2.0, c, b) + d;
-  const double dp = fma(-2.0, d, c) + e;
-  const double w1p = fma(4.0, d0, -dp), w2p = fma(4.0, dp, -d0);
-  const double w1m = fma(4.0, d0, -dm), w2m = fma(4.0, dm, -d0);
-  const double m4p = minmod4(w1p, w2p, d0, dp);
-  const double m4m = minmod4(w1m, w2m, d0, dm);
-  const int kp = minmod4_pick(w1p, w2p, d0, dp);
-  const int km = minmod4_pick(w1m, w2m, d0, dm);
-  const double fUL = fma(4.0, cb, c);
-  const double fMD = fma(-0.5, m4p, 0.5 * (c + d));
-  const double fLC = fma(4.0 / 3.0, m4m, fma(0.5, cb, c));
-  double v1 = c, v2 = c, u1 = c, u2 = c;
-  int k1 = 1, k2 = 1, j1 = 1, j2 = 1;
-  if (d < v1) { v1 = d; k1 = 2; }
-  if (fMD < v1) { v1 = fMD; k1 = 4 + kp; }
-  if (fUL < v2) { v2 = fUL; k2 = 3; }
-  if (fLC < v2) { v2 = fLC; k2 = 9 + km; }
-  if (d > u1) { u1 = d; j1 = 2; }
-  if (fMD > u1) { u1 = fMD; j1 = 4 + kp; }
-  if (fUL > u2) { u2 = fUL; j2 = 3; }
-  if (fLC > u2) { u2 = fLC; j2 = 9 + km; }
-  double lo = v1, hi = u1;
-  int klo = k1, khi = j1;
-  if (v2 > lo) { lo = v2; klo = k2; }
-  if (u2 < hi) { hi = u2; khi = j2; }
-  if (fL < lo) return klo;
-  if (fL > hi) return khi;
-  return 0;
-}
 
 // Reverse of the primitive recovery: adjoints of the primitives (lv, lp,
 // lri = d/d(1/rho), lB = d/dB used directly) accumulated into lu.
@@ -234,44 +172,83 @@ __device__ void speed_vjp(const double* u, double gamma, int d, double ls, doubl
 }
 
 template <int TX, int TY, int TZ>
-struct AdjShape {
+struct SweepShape {
   static constexpr int T(int d) { return d == 0 ? TX : d == 1 ? TY : TZ; }
   static constexpr int TC = TX * TY * TZ;
-  static constexpr int EF(int D, int d) { return T(d) + (d == D ? 10 : 0); }   // F+-: cells o-5 .. o+T+4
-  static constexpr int NF(int D) { return EF(D, 0) * EF(D, 1) * EF(D, 2); }
-  static constexpr int SF(int D) { return D == 0 ? 1 : D == 1 ? EF(D, 0) : EF(D, 0) * EF(D, 1); }
-  static constexpr int EM(int D, int d) { return T(d) + (d == D ? 6 : 0); }    // mu: cells o-3 .. o+T+2
-  static constexpr int NM(int D) { return EM(D, 0) * EM(D, 1) * EM(D, 2); }
-  static constexpr int SM(int D) { return D == 0 ? 1 : D == 1 ? EM(D, 0) : EM(D, 0) * EM(D, 1); }
-  static constexpr int EI(int D, int d) { return T(d) + (d == D ? 5 : 0); }    // interfaces o-3 .. o+T+1 (+1/2)
-  static constexpr int NI(int D) { return EI(D, 0) * EI(D, 1) * EI(D, 2); }
-  static constexpr int SI(int D) { return D == 0 ? 1 : D == 1 ? EI(D, 0) : EI(D, 0) * EI(D, 1); }
+  // pencils along D (the tile's cross-section), LDS row stride made odd
+  static constexpr int NP(int D) { return TC / T(D); }
+  static constexpr int PSTR(int D) { return NP(D) | 1; }
+  // a sweep item covers SEG consecutive cells of one pencil
+  static constexpr int SEG(int D) { return T(D) < 8 ? T(D) : 8; }
+  static constexpr int NSEG(int D) { return T(D) / SEG(D); }
+  // mu rows: cells o_D-3 .. o_D+T_D+2; code rows: lower faces of cells
+  // o_D-2 .. o_D+T_D+2 (interfaces i+1/2, i = o_D-3 .. o_D+T_D+1)
+  static constexpr int MROWS(int D) { return T(D) + 6; }
+  static constexpr int CROWS(int D) { return T(D) + 5; }
+  static constexpr int PENC(int D, int a0, int a1, int a2) {
+    return D == 0 ? a1 + TY * a2 : D == 1 ? a0 + TX * a2 : a0 + TX * a1;
+  }
 };
 
-template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP>
+// Cell (c[0], c[1], c[2]) of block blk where only c[D] may lie outside the
+// block: the face neighbour that holds it, with c[D] moved into it (nullptr
+// for a fixed face, which the adjoint rejects before any launch).
+template <int D>
+__device__ __forceinline__ const BlockDev* resolve_cell(const StateTable& st, int blk, int* c) {
+  const BlockDev* B = &st.blocks[blk];
+  if (c[D] < 0) {
+    const int nb = B->nbr[2 * D];
+    if (nb < 0) return nullptr;
+    B = &st.blocks[nb];
+    c[D] += B->n[D];
+  } else if (c[D] >= B->n[D]) {
+    const int nb = B->nbr[2 * D + 1];
+    if (nb < 0) return nullptr;
+    c[D] -= B->n[D];
+    B = &st.blocks[nb];
+  }
+  return B;
+}
+
+// Per tile and direction D:
+//   A) mu = sum_q mu_a[q] lam_q on the tile extended by 3 cells along D, and
+//      the 8 code bytes of every interface the tile's cells depend on, into
+//      LDS (rows along D, pencils contiguous);
+//   B) one work item per (pencil, variable, segment of SEG cells) walks the
+//      SEG + 5 interfaces that reach the segment: lamFhat = (mu_{i+1} -
+//      mu_i)/dx, then lamF+ and lamF- of the cells in the interface's two
+//      stencils += lamFhat * weight of the stencil position in the coded
+//      piece, all in registers (each cell receives its terms in increasing
+//      interface order);
+//   C) per owned cell: split adjoint and flux transpose.
+// Then dst = sum_q lam_a[q] lam_q + scale * nu for the owned cells.
+template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT>
 __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
   using E = Eq<NDIM, MHD>;
-  using S = AdjShape<TX, TY, TZ>;
+  using S = SweepShape<TX, TY, TZ>;
   constexpr int NV = E::NV;
-  constexpr int VPG = (NV + NGRP - 1) / NGRP;
   constexpr int TC = S::TC;
   constexpr int CPT = (TC + NT - 1) / NT;
-  constexpr int NFM = cmax_i<cmax_i<S::NF(0), NDIM >= 2 ? S::NF(1) : 0>::v, NDIM >= 3 ? S::NF(2) : 0>::v;
-  constexpr int NMM = cmax_i<cmax_i<S::NM(0), NDIM >= 2 ? S::NM(1) : 0>::v, NDIM >= 3 ? S::NM(2) : 0>::v;
-  constexpr int NIM = cmax_i<cmax_i<S::NI(0), NDIM >= 2 ? S::NI(1) : 0>::v, NDIM >= 3 ? S::NI(2) : 0>::v;
-  __shared__ double sF[2 * VPG * NFM];
-  __shared__ double sMu[VPG * NMM];
-  __shared__ double sLF[VPG * NIM];
-  __shared__ unsigned char sCP[VPG * NIM];
-  __shared__ unsigned char sCM[VPG * NIM];
+  constexpr int MB = cmax_i<cmax_i<NV * S::MROWS(0) * S::PSTR(0), NDIM >= 2 ? NV * S::MROWS(1) * S::PSTR(1) : 0>::v,
+                            NDIM >= 3 ? NV * S::MROWS(2) * S::PSTR(2) : 0>::v;
+  constexpr int OB = cmax_i<cmax_i<2 * NV * S::T(0) * S::PSTR(0), NDIM >= 2 ? 2 * NV * S::T(1) * S::PSTR(1) : 0>::v,
+                            NDIM >= 3 ? 2 * NV * S::T(2) * S::PSTR(2) : 0>::v;
+  constexpr int CB = cmax_i<cmax_i<S::CROWS(0) * S::PSTR(0), NDIM >= 2 ? S::CROWS(1) * S::PSTR(1) : 0>::v,
+                            NDIM >= 3 ? S::CROWS(2) * S::PSTR(2) : 0>::v;
+  // mu box, reused for the sweep outputs once every item has read it
+  __shared__ double sMu[cmax_i<MB, OB>::v];
+  __shared__ unsigned long long sCode[CB];
+  __shared__ double sW[16 * 5];
   __shared__ double red[NT / 64][3];
 
   const int tid = threadIdx.x;
   const StateTable& st = P.st;
   const double gamma = P.gamma;
+  for (int q = tid; q < 16 * 5; q += NT) sW[q] = q < 14 * 5 ? c_mp5w[q / 5][q % 5] : 0.0;
   double cin[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) cin[d] = __longlong_as_double((long long)P.ctl->cm[P.cm_slot][d]);
+  __syncthreads();
 
   const TileSchedule sched(P.ntiles);
   for (int t = sched.t; t < sched.end; t += sched.step) {
@@ -292,7 +269,7 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
       const int cidx = tid + r * NT;
-      int a0 = cidx % TX, a1 = (cidx / TX) % TY, a2 = cidx / (TX * TY);
+      const int a0 = cidx % TX, a1 = (cidx / TX) % TY, a2 = cidx / (TX * TY);
       own[r] = cidx < TC && a0 < tend[0] && a1 < tend[1] && a2 < tend[2];
 #pragma unroll
       for (int v = 0; v < NV; ++v) nu[r][v] = 0.0;
@@ -311,120 +288,154 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
 
     static_for<0, NDIM>([&](auto Dc) {
       constexpr int D = decltype(Dc)::value;
-      constexpr int NF_D = S::NF(D), NM_D = S::NM(D), NI_D = S::NI(D);
-      constexpr int F0 = S::EF(D, 0), F1 = S::EF(D, 1);
-      constexpr int M0 = S::EM(D, 0), M1 = S::EM(D, 1);
-      constexpr int I0 = S::EI(D, 0), I1 = S::EI(D, 1);
-      constexpr int SFD = S::SF(D), SMD = S::SM(D), SID = S::SI(D);
+      constexpr int TD = S::T(D), NP = S::NP(D), PS = S::PSTR(D);
+      constexpr int MR = S::MROWS(D), CR = S::CROWS(D);
+      constexpr int SEG = S::SEG(D), NSEG = S::NSEG(D);
+      constexpr int E0 = D == 0 ? MR : TX, E1 = D == 1 ? MR : TY, E2 = D == 2 ? MR : TZ;
+      constexpr int C0 = D == 0 ? CR : TX, C1 = D == 1 ? CR : TY, C2 = D == 2 ? CR : TZ;
       const double c = cin[D];
       const double idx_d = B.inv_dx[D];
 
-      static_for<0, NGRP>([&](auto Gc) {
-        constexpr int G = decltype(Gc)::value;
-        constexpr int V0 = G * VPG;
-        constexpr int VN = (V0 + VPG <= NV) ? VPG : NV - V0;
-        // A) split fluxes on o-5 .. o+T+4 and mu on o-3 .. o+T+2 along D
-        for (int e = tid; e < NF_D; e += NT) {
-          int a[3] = {e % F0, (e / F0) % F1, e / (F0 * F1)};
-          bool valid = true;
-          int cc[3];
+      // A) mu on the extended box, codes on the interface box (memory order)
+      for (int e = tid; e < E0 * E1 * E2; e += NT) {
+        const int a[3] = {e % E0, (e / E0) % E1, e / (E0 * E1)};
+        bool valid = true;
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            valid = valid && (a[d] < tend[d] + (d == D ? 10 : 0));
-            cc[d] = tl.o[d] + a[d] - (d == D ? 5 : 0);
+        for (int d = 0; d < 3; ++d) valid = valid && a[d] < tend[d] + (d == D ? 6 : 0);
+        if (!valid) continue;
+        int cc[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cc[d] = tl.o[d] + a[d] - (d == D ? 3 : 0);
+        const BlockDev* Bn = resolve_cell<D>(st, tl.block, cc);
+        double mu[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) mu[v] = 0.0;
+        if (Bn) {
+          for (int q = 0; q < P.nmu; ++q) {
+            long long vs;
+            const double* p = cell_addr(st, *Bn, P.mu_src[q], cc[0], cc[1], cc[2], vs);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) mu[v] = fma(P.mu_a[q], p[v * vs], mu[v]);
           }
-          if (valid) {
-            double u[NV];
-            load_cell<NV, D>(st, tl.block, P.in, cc[0], cc[1], cc[2], u);
-            PrimD w;
-            prim<NDIM, MHD>(u, gamma, w);
-            double F[NV];
-            phys_flux<NDIM, MHD, D>(u, w, F);
+        }
+        const int row = a[D], pen = S::PENC(D, a[0], a[1], a[2]);
 #pragma unroll
-            for (int vg = 0; vg < VN; ++vg) {
-              sF[vg * NF_D + e] = 0.5 * fma(c, u[V0 + vg], F[V0 + vg]);
-              sF[(VPG + vg) * NF_D + e] = 0.5 * fma(-c, u[V0 + vg], F[V0 + vg]);
+        for (int v = 0; v < NV; ++v) sMu[(v * MR + row) * PS + pen] = mu[v];
+      }
+      for (int e = tid; e < C0 * C1 * C2; e += NT) {
+        const int a[3] = {e % C0, (e / C0) % C1, e / (C0 * C1)};
+        bool valid = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) valid = valid && a[d] < tend[d] + (d == D ? 5 : 0);
+        if (!valid) continue;
+        int cc[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cc[d] = tl.o[d] + a[d] - (d == D ? 2 : 0);
+        const BlockDev* Bn = resolve_cell<D>(st, tl.block, cc);
+        unsigned long long code = 0ull;
+        if (Bn) {
+          const long long cell = ((long long)cc[2] * Bn->n[1] + cc[1]) * Bn->n[0] + cc[0];
+          code = *reinterpret_cast<const unsigned long long*>(P.codes + D * P.code_plane + (Bn->coff + cell) * 8);
+        }
+        sCode[a[D] * PS + S::PENC(D, a[0], a[1], a[2])] = code;
+      }
+      __syncthreads();
+
+      // B) sweeps
+      constexpr int NITEM = NP * NV * NSEG;
+      constexpr int IPT = (NITEM + NT - 1) / NT;
+      double rp[IPT][SEG], rm[IPT][SEG];
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const int item = tid + r * NT;
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) { rp[r][j] = 0.0; rm[r][j] = 0.0; }
+        if (item < NITEM) {
+          const int pen = item % NP;
+          const int v = (item / NP) % NV;
+          const int g = item / (NP * NV);
+          const double* mu = &sMu[(v * MR) * PS + pen];
+          const unsigned char* cd = reinterpret_cast<const unsigned char*>(&sCode[pen]) + v;
+          double mprev = mu[(g * SEG) * PS];
+#pragma unroll
+          for (int kk = 0; kk < SEG + 5; ++kk) {
+            const int k = g * SEG + kk;
+            const double mnext = mu[(k + 1) * PS];
+            const double lf = (mnext - mprev) * idx_d;
+            mprev = mnext;
+            const int code = cd[k * PS * 8];
+            const double* wp = &sW[(code & 15) * 5];
+            const double* wm = &sW[(code >> 4) * 5];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+              const int j = kk - 5 + s;   // F+ stencil: cell i-2+s
+              if (j >= 0 && j < SEG) rp[r][j] = fma(lf, wp[s], rp[r][j]);
+            }
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+              const int j = kk - s;       // F- stencil: cell i+3-s
+              if (j >= 0 && j < SEG) rm[r][j] = fma(lf, wm[s], rm[r][j]);
             }
           }
         }
-        for (int m = tid; m < NM_D; m += NT) {
-          int a[3] = {m % M0, (m / M0) % M1, m / (M0 * M1)};
-          bool valid = true;
-          int cc[3];
+      }
+      __syncthreads();
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            valid = valid && (a[d] < tend[d] + (d == D ? 6 : 0));
-            cc[d] = tl.o[d] + a[d] - (d == D ? 3 : 0);
-          }
-          if (valid) {
-            double mu[VN];
-            load_cell_vars<V0, VN, D>(st, tl.block, P.mu, cc[0], cc[1], cc[2], mu);
+      for (int r = 0; r < IPT; ++r) {
+        const int item = tid + r * NT;
+        if (item < NITEM) {
+          const int pen = item % NP;
+          const int v = (item / NP) % NV;
+          const int g = item / (NP * NV);
 #pragma unroll
-            for (int vg = 0; vg < VN; ++vg) sMu[vg * NM_D + m] = mu[vg];
+          for (int j = 0; j < SEG; ++j) {
+            const int row = g * SEG + j;
+            sMu[((0 * NV + v) * TD + row) * PS + pen] = 0.5 * (rp[r][j] + rm[r][j]);
+            sMu[((1 * NV + v) * TD + row) * PS + pen] = rp[r][j] - rm[r][j];
           }
         }
-        __syncthreads();
-        // B) interface adjoints and MP5 pieces
-        for (int wi = tid; wi < VN * NI_D; wi += NT) {
-          const int vg = wi / NI_D;
-          const int q = wi - vg * NI_D;
-          int a[3] = {q % I0, (q / I0) % I1, q / (I0 * I1)};
-          bool valid = true;
+      }
+      __syncthreads();
+
+      // C) split adjoint and flux transpose per owned cell
 #pragma unroll
-          for (int d = 0; d < 3; ++d) valid = valid && (a[d] < tend[d] + (d == D ? 5 : 0));
-          if (!valid) continue;
-          // stencil cells i-2 .. i+3 are F-box indices a_D .. a_D + 5 along D
-          const int eb = a[0] + F0 * (a[1] + F1 * a[2]);
-          const double* fp = &sF[vg * NF_D + eb];
-          const double* fm = &sF[(VPG + vg) * NF_D + eb];
-          sCP[vg * NI_D + q] = (unsigned char)mp5_code(fp[0], fp[SFD], fp[2 * SFD], fp[3 * SFD], fp[4 * SFD]);
-          sCM[vg * NI_D + q] = (unsigned char)mp5_code(fm[5 * SFD], fm[4 * SFD], fm[3 * SFD], fm[2 * SFD], fm[SFD]);
-          // mu_i and mu_{i+1} are mu-box indices a_D and a_D + 1 along D
-          const int mb = a[0] + M0 * (a[1] + M1 * a[2]);
-          sLF[vg * NI_D + q] = (sMu[vg * NM_D + mb + SMD] - sMu[vg * NM_D + mb]) * idx_d;
+      for (int r = 0; r < CPT; ++r) {
+        if (!own[r]) continue;
+        const int cidx = tid + r * NT;
+        const int a[3] = {cidx % TX, (cidx / TX) % TY, cidx / (TX * TY)};
+        const int base = a[D] * PS + S::PENC(D, a[0], a[1], a[2]);
+        double lF[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          lF[v] = sMu[(0 * NV + v) * TD * PS + base];
+          const double dF = sMu[(1 * NV + v) * TD * PS + base];
+          nu[r][v] = fma(0.5 * c, dF, nu[r][v]);
+          cp[D] = fma(0.5 * uo[r][v], dF, cp[D]);
         }
-        __syncthreads();
-        // C) gather into the owned cells
-#pragma unroll
-        for (int r = 0; r < CPT; ++r) {
-          if (!own[r]) continue;
-          const int cidx = tid + r * NT;
-          const int a0 = cidx % TX, a1 = (cidx / TX) % TY, a2 = cidx / (TX * TY);
-          const int ib = a0 + I0 * (a1 + I1 * a2);
-          double lF[NV];
-#pragma unroll
-          for (int v = 0; v < NV; ++v) lF[v] = 0.0;
-#pragma unroll
-          for (int vg = 0; vg < VN; ++vg) {
-            const double* lf = &sLF[vg * NI_D + ib];
-            const unsigned char* kp = &sCP[vg * NI_D + ib];
-            const unsigned char* km = &sCM[vg * NI_D + ib];
-            double lm = 0.0, lp = 0.0;
-#pragma unroll
-            for (int s = 0; s <= 4; ++s) lm = fma(lf[s * SID], c_mp5w[km[s * SID]][s], lm);
-#pragma unroll
-            for (int s = 1; s <= 5; ++s) lp = fma(lf[s * SID], c_mp5w[kp[s * SID]][5 - s], lp);
-            const int v = V0 + vg;
-            lF[v] = 0.5 * (lp + lm);
-            nu[r][v] = fma(0.5 * c, lp - lm, nu[r][v]);
-            cp[D] = fma(0.5 * uo[r][v], lp - lm, cp[D]);
-          }
-          flux_vjp<NDIM, MHD, D>(uo[r], wo[r], gamma, lF, nu[r]);
-        }
-        __syncthreads();
-      });
+        flux_vjp<NDIM, MHD, D>(uo[r], wo[r], gamma, lF, nu[r]);
+      }
+      __syncthreads();
     });
 
-    // lam += scale * nu
+    // dst = sum_q lam_a[q] lam_q + scale * nu
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
       if (!own[r]) continue;
       const int cidx = tid + r * NT;
-      const int a0 = cidx % TX, a1 = (cidx / TX) % TY, a2 = cidx / (TX * TY);
-      long long vs;
-      double* p = const_cast<double*>(cell_addr(st, B, P.lam, tl.o[0] + a0, tl.o[1] + a1, tl.o[2] + a2, vs));
+      const int i = tl.o[0] + cidx % TX, j = tl.o[1] + (cidx / TX) % TY, k = tl.o[2] + cidx / (TX * TY);
+      double acc[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) p[v * vs] = fma(P.scale, nu[r][v], p[v * vs]);
+      for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+      for (int q = 0; q < P.nlam; ++q) {
+        long long vs;
+        const double* p = cell_addr(st, B, P.lam_src[q], i, j, k, vs);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = fma(P.lam_a[q], p[v * vs], acc[v]);
+      }
+      long long ws;
+      double* p = cell_addr_w(st, B, P.dst, i, j, k, ws);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) p[v * ws] = fma(P.scale, nu[r][v], acc[v]);
     }
     // per-tile c_max adjoint sums (fixed reduction order)
 #pragma unroll
@@ -666,9 +677,9 @@ struct VjpVariant {
   void (*cmax_term)(StateTable, int, const double*, int, Control*, double, int, int, double, hipStream_t);
 };
 
-template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP>
+template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT>
 static void launch_vjp_t(const VjpParams& p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_vjp<NDIM, MHD, TX, TY, TZ, NT, NGRP>), dim3(grid), dim3(NT), 0, s, p);
+  hipLaunchKernelGGL((k_vjp<NDIM, MHD, TX, TY, TZ, NT>), dim3(grid), dim3(NT), 0, s, p);
 }
 
 template <int NDIM, bool MHD>
@@ -685,17 +696,19 @@ static void launch_cmax_term_t(StateTable st, int nblocks, const double* cpart, 
                      lam, scale);
 }
 
-#define AMRVAC_VJP(ND, M, TX, TY, TZ, NT, NGRP)                                                          \
-  {ND, M, TX, TY, TZ, NT, (const void*)&k_vjp<ND, M, TX, TY, TZ, NT, NGRP>,                               \
-   &launch_vjp_t<ND, M, TX, TY, TZ, NT, NGRP>, &launch_argmax_t<ND, M>, &launch_cmax_term_t<ND, M>}
+#define AMRVAC_VJP(ND, M, TX, TY, TZ, NT)                                                               \
+  {ND, M, TX, TY, TZ, NT, (const void*)&k_vjp<ND, M, TX, TY, TZ, NT>, &launch_vjp_t<ND, M, TX, TY, TZ, NT>, \
+   &launch_argmax_t<ND, M>, &launch_cmax_term_t<ND, M>}
 
+// Tile shapes must match the code-emitting stage kernels of the same
+// (ndim, physics): both use one tile list.
 static const VjpVariant g_vjp[] = {
-    AMRVAC_VJP(1, false, 64, 1, 1, 64, 1),
-    AMRVAC_VJP(1, true, 64, 1, 1, 64, 2),
-    AMRVAC_VJP(2, false, 16, 16, 1, 256, 1),
-    AMRVAC_VJP(2, true, 16, 16, 1, 256, 2),
-    AMRVAC_VJP(3, false, 8, 8, 4, 256, 3),
-    AMRVAC_VJP(3, true, 8, 8, 4, 256, 4),
+    AMRVAC_VJP(1, false, 64, 1, 1, 64),
+    AMRVAC_VJP(1, true, 64, 1, 1, 64),
+    AMRVAC_VJP(2, false, 16, 16, 1, 256),
+    AMRVAC_VJP(2, true, 16, 16, 1, 256),
+    AMRVAC_VJP(3, false, 8, 8, 4, 256),
+    AMRVAC_VJP(3, true, 8, 8, 4, 256),
 };
 
 const VjpVariant* vjp_variant(int ndim, int mhd) {

@@ -12,6 +12,7 @@ constexpr int MAX_SLOTS = 8;   // c_max slots per step (stages + 1)
 struct BlockDev {
   double* u;            // caller's padded state (buffer id 0)
   long long off;        // offset (doubles) of this block inside one scratch slot
+  long long coff;       // offset (cells) of this block in per-cell arrays (off / nvar)
   long long cells;      // interior cells n0*n1*n2
   int n[3];             // interior extents (1 for inactive directions)
   int P[3];             // padded extents
@@ -82,6 +83,13 @@ struct StageParams {
   double sb;
   int sdst;
   double* const* rhs_out;
+  // Optional (only the code-emitting kernels write it): MP5 linear-piece
+  // codes of L(in), one byte per (direction, cell, variable) for the
+  // interface on the cell's lower face, low nibble for the F+ stencil and
+  // high nibble for the F- stencil, at
+  //   codes + D * code_plane + (block.coff + cell) * 8 + v.
+  unsigned char* codes;
+  long long code_plane;
 };
 
 struct CmaxParams {
@@ -95,17 +103,32 @@ struct CmaxParams {
   int slot;
 };
 
-// Parameters of one vector-Jacobian product of L (adjoint of a stage):
-//   lam += scale * J_L(U)^T mu      (U = buffer `in`, mu = buffer `mu`)
-// local part only; the c_max part (through the maximising cell) is added by
-// a separate reduction from the per-tile sums written to cpart[tile*3+d].
+constexpr int MAX_TERMS = 6;
+
+// Parameters of one vector-Jacobian product of L (adjoint of one stage
+// state U = buffer `in`):
+//   mu   = sum_q mu_a[q]  * buffer mu_src[q]                (on the fly)
+//   dst  = sum_q lam_a[q] * buffer lam_src[q] + scale * J_L(U)^T mu
+// for the local dependence of L on U; the MP5 linear pieces come from the
+// codes the forward recompute of U's stage wrote (layout as in
+// StageParams).  The c_max part (through the maximising cell) is added by a
+// separate reduction from the per-tile sums written to cpart[tile*3+d].
 struct VjpParams {
   StateTable st;
   const Tile* tiles;
   int ntiles;
   Control* ctl;
   double gamma;
-  int in, mu, lam;
+  int in;
+  const unsigned char* codes;
+  long long code_plane;
+  int nmu;
+  int mu_src[MAX_TERMS];
+  double mu_a[MAX_TERMS];
+  int nlam;
+  int lam_src[MAX_TERMS];
+  double lam_a[MAX_TERMS];
+  int dst;
   double scale;
   int cm_slot;
   double* cpart;

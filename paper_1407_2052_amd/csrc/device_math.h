@@ -206,6 +206,51 @@ __device__ __forceinline__ double mp5(double a, double b, double c, double d, do
   return fmin(fmax(fL, fmn), fmx);
 }
 
+// Linear pieces of MP5.  With eps = 0, mp5 is continuous and piecewise
+// linear in its five inputs; mp5_coded names the piece it evaluates (the
+// adjoint multiplies by that piece's constant weights):
+//   0 fL;  1 c;  2 d;  3 fUL;  4 + k fMD and 9 + k fLC, where k (0..4) is
+//   the argument minmod4 returned for the curvature at j+1/2 (fMD) or
+//   j-1/2 (fLC), k = 0 for zero.
+// mp5 together with the code of the linear piece it evaluates (same
+// numbering as above), computed from mp5's own intermediate values with
+// selects only.  The value is bitwise that of mp5.  The piece: fL when fmin
+// <= fL <= fmax; else the candidate that realised fmin (fL < fmin) or fmax
+// (fL > fmax), searched as a minimum over sigma * candidate with sigma = +1
+// or -1 (ties to the earlier candidate, as in the min/max chains); a
+// minmod4 result that is not zero equals its first extremal argument.
+__device__ __forceinline__ double mp5_coded(double a, double b, double c, double d, double e, int& code) {
+  const double fL = fma(2.0, a, fma(-13.0, b, fma(47.0, c, fma(27.0, d, -3.0 * e)))) * (1.0 / 60.0);
+  const double cb = c - b;
+  const double dm = fma(-2.0, b, a) + c;
+  const double d0 = fma(-2.0, c, b) + d;
+  const double dp = fma(-2.0, d, c) + e;
+  const double w1p = fma(4.0, d0, -dp), w2p = fma(4.0, dp, -d0);
+  const double w1m = fma(4.0, d0, -dm), w2m = fma(4.0, dm, -d0);
+  const double m4p = minmod4(w1p, w2p, d0, dp);
+  const double m4m = minmod4(w1m, w2m, d0, dm);
+  const double fUL = fma(4.0, cb, c);
+  const double fMD = fma(-0.5, m4p, 0.5 * (c + d));
+  const double fLC = fma(4.0 / 3.0, m4m, fma(0.5, cb, c));
+  const double fmn = fmax(fmin(fmin(c, d), fMD), fmin(fmin(c, fUL), fLC));
+  const double fmx = fmin(fmax(fmax(c, d), fMD), fmax(fmax(c, fUL), fLC));
+  const double r = fmin(fmax(fL, fmn), fmx);
+  // piece
+  const bool lo = fL < fmn, hi = fL > fmx;
+  const double sg = hi ? -1.0 : 1.0;
+  const int kp = m4p == 0.0 ? 0 : w1p == m4p ? 1 : w2p == m4p ? 2 : d0 == m4p ? 3 : 4;
+  const int km = m4m == 0.0 ? 0 : w1m == m4m ? 1 : w2m == m4m ? 2 : d0 == m4m ? 3 : 4;
+  const double sc = sg * c, sd = sg * d, sMD = sg * fMD, sUL = sg * fUL, sLC = sg * fLC;
+  double t1 = sc, t2 = sc;
+  int k1 = 1, k2 = 1;
+  if (sd < t1) { t1 = sd; k1 = 2; }
+  if (sMD < t1) { t1 = sMD; k1 = 4 + kp; }
+  if (sUL < t2) { t2 = sUL; k2 = 3; }
+  if (sLC < t2) { t2 = sLC; k2 = 9 + km; }
+  code = (lo || hi) ? (t2 > t1 ? k2 : k1) : 0;
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Tile geometry helpers (compile time).
 // ---------------------------------------------------------------------------

@@ -43,7 +43,7 @@ namespace amrvac {
 // ---------------------------------------------------------------------------
 // Fused stage kernel.
 // ---------------------------------------------------------------------------
-template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE>
+template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false>
 __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
   using E = Eq<NDIM, MHD>;
   using S = TileShape<TX, TY, TZ>;
@@ -173,8 +173,21 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
               }
               const double* fp = &lds[vg * NEXT_D + eb];
               const double* fm = &lds[(VPG + vg) * NEXT_D + eb];
-              res[r] = mp5(fp[0], fp[SD], fp[2 * SD], fp[3 * SD], fp[4 * SD]) +
-                       mp5(fm[5 * SD], fm[4 * SD], fm[3 * SD], fm[2 * SD], fm[SD]);
+              if constexpr (EMIT) {
+                // both linear pieces, stored on the lower face of cell a_D
+                int kp, km;
+                res[r] = mp5_coded(fp[0], fp[SD], fp[2 * SD], fp[3 * SD], fp[4 * SD], kp) +
+                         mp5_coded(fm[5 * SD], fm[4 * SD], fm[3 * SD], fm[2 * SD], fm[SD], km);
+                if (a[D] < tend[D]) {
+                  const long long cell =
+                      ((long long)(tl.o[2] + a[2]) * B.n[1] + (tl.o[1] + a[1])) * B.n[0] + (tl.o[0] + a[0]);
+                  P.codes[D * P.code_plane + (B.coff + cell) * 8 + (G * VPG + vg)] =
+                      (unsigned char)(kp | (km << 4));
+                }
+              } else {
+                res[r] = mp5(fp[0], fp[SD], fp[2 * SD], fp[3 * SD], fp[4 * SD]) +
+                         mp5(fm[5 * SD], fm[4 * SD], fm[3 * SD], fm[2 * SD], fm[SD]);
+              }
             }
           }
         }
@@ -412,9 +425,9 @@ struct StageVariant {
   const char* name;
 };
 
-template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE>
+template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false>
 static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE>), dim3(grid), dim3(NT), 0, s, p);
+  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE, EMIT>), dim3(grid), dim3(NT), 0, s, p);
 }
 
 #define AMRVAC_VARIANT(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                       \
@@ -454,6 +467,28 @@ static const StageVariant g_variants[] = {
 const StageVariant* stage_variants(int* count) {
   *count = (int)(sizeof(g_variants) / sizeof(g_variants[0]));
   return g_variants;
+}
+
+// Code-emitting stage kernels (the adjoint's forward recompute), one per
+// (ndim, physics); their tile shapes match the adjoint kernels'.
+#define AMRVAC_EMIT(ND, M, TX, TY, TZ, NT, NGRP)                                       \
+  {ND, M, TX, TY, TZ, NT, NGRP, 1, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, 1, true>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, 1, true>,                                \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-emit"}
+
+static const StageVariant g_emit[] = {
+    AMRVAC_EMIT(1, false, 64, 1, 1, 64, 1),
+    AMRVAC_EMIT(1, true, 64, 1, 1, 64, 1),
+    AMRVAC_EMIT(2, false, 16, 16, 1, 256, 1),
+    AMRVAC_EMIT(2, true, 16, 16, 1, 256, 2),
+    AMRVAC_EMIT(3, false, 8, 8, 4, 256, 1),
+    AMRVAC_EMIT(3, true, 8, 8, 4, 256, 2),
+};
+
+const StageVariant* emit_variant(int ndim, int mhd) {
+  for (const StageVariant& v : g_emit)
+    if (v.ndim == ndim && v.mhd == mhd) return &v;
+  return nullptr;
 }
 
 template <int NDIM, bool MHD>

@@ -383,7 +383,8 @@ void launch_cmax_of(amrvac_ctx* c, int buf, int slot, hipStream_t s) {
 // last stage, giving c_max(U^{n+1}) for the next step); stage 2 clears slot
 // 0 once stage 1 no longer needs it.
 namespace amrvac {
-void enqueue_step_outs(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U, const int* outs, int S) {
+void enqueue_step_outs(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U, const int* outs, int S,
+                       const EmitPlan* emit) {
   const int ns = scheme_stages(scheme);
   launch_step_begin(c->d_ctl, c->d_dxtab, c->cfg.ndim, 1, ns - 1, s);
   std::vector<Recipe> r = recipes(scheme, U, outs, S);
@@ -391,7 +392,17 @@ void enqueue_step_outs(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U
     const int cm_in = i - 1;
     const int cm_out = (i == ns) ? 0 : i;
     const int cm_reset = (i == 2) ? 0 : -1;
-    launch_stage(c, make_params(c, r[i - 1], cm_in, cm_out, cm_reset), exec, s);
+    StageParams p = make_params(c, r[i - 1], cm_in, cm_out, cm_reset);
+    if (emit) {
+      p.tiles = emit->tiles;
+      p.tile_begin = 0;
+      p.ntiles = emit->ntiles;
+      p.codes = emit->codes[i - 1];
+      p.code_plane = emit->code_plane;
+      emit->var->launch(p, emit->grid, s);
+    } else {
+      launch_stage(c, p, exec, s);
+    }
   }
 }
 }  // namespace amrvac
@@ -554,6 +565,7 @@ amrvac_status amrvac_set_blocks(amrvac_ctx* c, const amrvac_block* blocks, int n
     D.u = q.u;
     D.cells = (long long)q.n[0] * q.n[1] * q.n[2];
     D.off = off;
+    D.coff = off / c->nvar;
     off += D.cells * c->nvar;
     for (int d = 0; d < 3; ++d) {
       D.n[d] = q.n[d];

@@ -17,6 +17,8 @@ struct StageVariant {
   const char* name;
 };
 const StageVariant* stage_variants(int* count);
+// Code-emitting stage kernel for (ndim, physics), or nullptr.
+const StageVariant* emit_variant(int ndim, int mhd);
 void launch_cmax(int ndim, int mhd, const CmaxParams& p, int grid, hipStream_t s);
 void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo, int clear_hi,
                        hipStream_t s);
@@ -87,7 +89,18 @@ StateTable state_table(const amrvac_ctx* c);
 int scheme_stages(int scheme);
 // One step of `scheme` with state buffer U (read), per-stage output buffers
 // outs[1..s] (outs[s] receives U^{n+1}) and low-storage accumulator S.
-void enqueue_step_outs(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U, const int* outs, int S);
+// Stages launched by a code-emitting kernel on its own tile list, with the
+// MP5 piece codes of L(stage input) of stage i written to codes[i - 1].
+struct EmitPlan {
+  const StageVariant* var;
+  const Tile* tiles;
+  int ntiles;
+  int grid;
+  unsigned char* codes[6];
+  long long code_plane;
+};
+void enqueue_step_outs(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U, const int* outs, int S,
+                       const EmitPlan* emit = nullptr);
 void launch_cmax_of(amrvac_ctx* c, int buf, int slot, hipStream_t s);
 amrvac_status read_status(amrvac_ctx* c);
 // Shu-Osher table (Sect. 2.3) as used by the stage recipes: alpha[i][k],
