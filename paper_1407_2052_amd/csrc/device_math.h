@@ -184,70 +184,109 @@ __device__ __forceinline__ double fast_speed(const PrimD& w, int d, double gamma
 // ---------------------------------------------------------------------------
 // MP5 (Suresh & Huynh 1997), alpha = 4, eps = 0, median form.
 // ---------------------------------------------------------------------------
+// minmod of four arguments (the one of smallest magnitude when all have
+// the same sign, else zero), as a clamp of zero into [min, max]: the result
+// is one of the arguments exactly, or zero.
 __device__ __forceinline__ double minmod4(double w, double x, double y, double z) {
   const double lo = fmin(fmin(w, x), fmin(y, z));
   const double hi = fmax(fmax(w, x), fmax(y, z));
-  return fmax(lo, 0.0) + fmin(hi, 0.0);
+  return fmax(lo, fmin(hi, 0.0));
 }
 
-__device__ __forceinline__ double mp5(double a, double b, double c, double d, double e) {
-  const double fL = fma(2.0, a, fma(-13.0, b, fma(47.0, c, fma(27.0, d, -3.0 * e)))) * (1.0 / 60.0);
-  const double cb = c - b;
-  const double dm = fma(-2.0, b, a) + c;
-  const double d0 = fma(-2.0, c, b) + d;
-  const double dp = fma(-2.0, d, c) + e;
-  const double m4p = minmod4(fma(4.0, d0, -dp), fma(4.0, dp, -d0), d0, dp);
-  const double m4m = minmod4(fma(4.0, d0, -dm), fma(4.0, dm, -d0), d0, dm);
-  const double fUL = fma(4.0, cb, c);
-  const double fMD = fma(-0.5, m4p, 0.5 * (c + d));
-  const double fLC = fma(4.0 / 3.0, m4m, fma(0.5, cb, c));
-  const double fmn = fmax(fmin(fmin(c, d), fMD), fmin(fmin(c, fUL), fLC));
-  const double fmx = fmin(fmax(fmax(c, d), fMD), fmax(fmax(c, fUL), fLC));
-  return fmin(fmax(fL, fmn), fmx);
+// Curvature limiter of the cell pair (j, j+1) from their curvatures x = d_j
+// and y = d_{j+1}: d^M4_{j+1/2}.  Both limiters of a reconstruction use it
+// with the lower cell first, so neighbouring interfaces of a pencil share
+// one evaluation.
+__device__ __forceinline__ double m4pair(double x, double y) {
+  return minmod4(fma(4.0, x, -y), fma(4.0, y, -x), x, y);
+}
+
+// Index (1..4) of the first of (w, x, y, z) equal to the minmod result m,
+// 0 when m is zero: the argument minmod4 returned.
+__device__ __forceinline__ int minmod4_arg(double m, double w, double x, double y) {
+  return m == 0.0 ? 0 : w == m ? 1 : x == m ? 2 : y == m ? 3 : 4;
+}
+
+// Bounds and clamp of MP5 from the stencil centre c, its right neighbour
+// d, the fifth-order value fL, c - b and the two curvature limiters.
+struct Mp5Parts {
+  double fUL, fMD, fLC, fmn, fmx;
+};
+__device__ __forceinline__ double mp5_tail(double c, double d, double fL, double cb, double m4p, double m4m,
+                                           Mp5Parts& q) {
+  q.fUL = fma(4.0, cb, c);
+  q.fMD = fma(-0.5, m4p, 0.5 * (c + d));
+  q.fLC = fma(4.0 / 3.0, m4m, fma(0.5, cb, c));
+  q.fmn = fmax(fmin(fmin(c, d), q.fMD), fmin(fmin(c, q.fUL), q.fLC));
+  q.fmx = fmin(fmax(fmax(c, d), q.fMD), fmax(fmax(c, q.fUL), q.fLC));
+  return fmin(fmax(fL, q.fmn), q.fmx);
 }
 
 // Linear pieces of MP5.  With eps = 0, mp5 is continuous and piecewise
-// linear in its five inputs; mp5_coded names the piece it evaluates (the
+// linear in its five inputs; mp5_piece names the piece it evaluates (the
 // adjoint multiplies by that piece's constant weights):
 //   0 fL;  1 c;  2 d;  3 fUL;  4 + k fMD and 9 + k fLC, where k (0..4) is
-//   the argument minmod4 returned for the curvature at j+1/2 (fMD) or
-//   j-1/2 (fLC), k = 0 for zero.
-// mp5 together with the code of the linear piece it evaluates (same
-// numbering as above), computed from mp5's own intermediate values with
-// selects only.  The value is bitwise that of mp5.  The piece: fL when fmin
-// <= fL <= fmax; else the candidate that realised fmin (fL < fmin) or fmax
-// (fL > fmax), searched as a minimum over sigma * candidate with sigma = +1
-// or -1 (ties to the earlier candidate, as in the min/max chains); a
-// minmod4 result that is not zero equals its first extremal argument.
-__device__ __forceinline__ double mp5_coded(double a, double b, double c, double d, double e, int& code) {
-  const double fL = fma(2.0, a, fma(-13.0, b, fma(47.0, c, fma(27.0, d, -3.0 * e)))) * (1.0 / 60.0);
-  const double cb = c - b;
-  const double dm = fma(-2.0, b, a) + c;
-  const double d0 = fma(-2.0, c, b) + d;
-  const double dp = fma(-2.0, d, c) + e;
-  const double w1p = fma(4.0, d0, -dp), w2p = fma(4.0, dp, -d0);
-  const double w1m = fma(4.0, d0, -dm), w2m = fma(4.0, dm, -d0);
-  const double m4p = minmod4(w1p, w2p, d0, dp);
-  const double m4m = minmod4(w1m, w2m, d0, dm);
-  const double fUL = fma(4.0, cb, c);
-  const double fMD = fma(-0.5, m4p, 0.5 * (c + d));
-  const double fLC = fma(4.0 / 3.0, m4m, fma(0.5, cb, c));
-  const double fmn = fmax(fmin(fmin(c, d), fMD), fmin(fmin(c, fUL), fLC));
-  const double fmx = fmin(fmax(fmax(c, d), fMD), fmax(fmax(c, fUL), fLC));
-  const double r = fmin(fmax(fL, fmn), fmx);
-  // piece
-  const bool lo = fL < fmn, hi = fL > fmx;
+//   the argument the curvature minmod returned, k = 0 for zero, with the
+//   arguments ordered (4d_j - d_{j+1}, 4d_{j+1} - d_j, d_j, d_{j+1}) for fMD
+//   at j+1/2 and (4d_j - d_{j-1}, 4d_{j-1} - d_j, d_j, d_{j-1}) for fLC at
+//   j-1/2.  The piece is fL when fmin <= fL <= fmax; else the candidate that
+//   realised fmin (fL < fmin) or fmax (fL > fmax), searched as a minimum
+//   over sigma * candidate with sigma = +1 or -1 (ties to the earlier
+//   candidate, as in the min/max chains).
+__device__ __forceinline__ int mp5_piece(double c, double d, double fL, const Mp5Parts& q, int kp, int km) {
+  const bool lo = fL < q.fmn, hi = fL > q.fmx;
   const double sg = hi ? -1.0 : 1.0;
-  const int kp = m4p == 0.0 ? 0 : w1p == m4p ? 1 : w2p == m4p ? 2 : d0 == m4p ? 3 : 4;
-  const int km = m4m == 0.0 ? 0 : w1m == m4m ? 1 : w2m == m4m ? 2 : d0 == m4m ? 3 : 4;
-  const double sc = sg * c, sd = sg * d, sMD = sg * fMD, sUL = sg * fUL, sLC = sg * fLC;
+  const double sc = sg * c, sd = sg * d, sMD = sg * q.fMD, sUL = sg * q.fUL, sLC = sg * q.fLC;
   double t1 = sc, t2 = sc;
   int k1 = 1, k2 = 1;
   if (sd < t1) { t1 = sd; k1 = 2; }
   if (sMD < t1) { t1 = sMD; k1 = 4 + kp; }
   if (sUL < t2) { t2 = sUL; k2 = 3; }
   if (sLC < t2) { t2 = sLC; k2 = 9 + km; }
-  code = (lo || hi) ? (t2 > t1 ? k2 : k1) : 0;
+  return (lo || hi) ? (t2 > t1 ? k2 : k1) : 0;
+}
+
+// MP5 (Suresh & Huynh 1997, alpha = 4, eps = 0, median form) of RUN
+// consecutive interfaces of a pencil: interface kk reconstructs from the
+// stencil f[kk .. kk+4] (f_{j-2} .. f_{j+2}).  Curvatures and curvature
+// limiters are evaluated once and shared by the interfaces that use them;
+// every value is bitwise that of RUN separate evaluations.  With CODES the
+// linear piece of every interface is returned as well.
+template <int RUN, bool CODES>
+__device__ __forceinline__ void mp5_run(const double* f, double* out, int* code) {
+  double dc[RUN + 2];   // curvature at stencil position j + 1
+#pragma unroll
+  for (int j = 0; j < RUN + 2; ++j) dc[j] = fma(-2.0, f[j + 1], f[j]) + f[j + 2];
+  double m4[RUN + 1];   // limiter of the pair (j + 1, j + 2)
+#pragma unroll
+  for (int j = 0; j < RUN + 1; ++j) m4[j] = m4pair(dc[j], dc[j + 1]);
+#pragma unroll
+  for (int kk = 0; kk < RUN; ++kk) {
+    const double a = f[kk], b = f[kk + 1], c = f[kk + 2], d = f[kk + 3], e = f[kk + 4];
+    const double fL = fma(2.0, a, fma(-13.0, b, fma(47.0, c, fma(27.0, d, -3.0 * e)))) * (1.0 / 60.0);
+    const double cb = c - b;
+    Mp5Parts q;
+    out[kk] = mp5_tail(c, d, fL, cb, m4[kk + 1], m4[kk], q);
+    if constexpr (CODES) {
+      const double dm = dc[kk], d0 = dc[kk + 1], dp = dc[kk + 2];
+      const int kp = minmod4_arg(m4[kk + 1], fma(4.0, d0, -dp), fma(4.0, dp, -d0), d0);
+      const int km = minmod4_arg(m4[kk], fma(4.0, d0, -dm), fma(4.0, dm, -d0), d0);
+      code[kk] = mp5_piece(c, d, fL, q, kp, km);
+    }
+  }
+}
+
+__device__ __forceinline__ double mp5(double a, double b, double c, double d, double e) {
+  const double f[5] = {a, b, c, d, e};
+  double r;
+  mp5_run<1, false>(f, &r, nullptr);
+  return r;
+}
+
+__device__ __forceinline__ double mp5_coded(double a, double b, double c, double d, double e, int& code) {
+  const double f[5] = {a, b, c, d, e};
+  double r;
+  mp5_run<1, true>(f, &r, &code);
   return r;
 }
 

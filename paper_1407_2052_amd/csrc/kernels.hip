@@ -43,7 +43,8 @@ namespace amrvac {
 // ---------------------------------------------------------------------------
 // Fused stage kernel.
 // ---------------------------------------------------------------------------
-template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false>
+template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
+          bool RUNS = false>
 __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
   using E = Eq<NDIM, MHD>;
   using S = TileShape<TX, TY, TZ>;
@@ -51,7 +52,9 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
   constexpr int VPG = (NV + NGRP - 1) / NGRP;
   constexpr int TC = S::TC;
   constexpr int CPT = (TC + NT - 1) / NT;
-  constexpr int EXT = cmax_i<cmax_i<S::NEXT(0), NDIM >= 2 ? S::NEXT(1) : 0>::v,
+  // with RUNS the x rows of the extended box get an odd LDS stride
+  constexpr int XP = RUNS ? ((TX + 2 * NG) | 1) : TX + 2 * NG;
+  constexpr int EXT = cmax_i<cmax_i<XP * TY * TZ, NDIM >= 2 ? S::NEXT(1) : 0>::v,
                              NDIM >= 3 ? S::NEXT(2) : 0>::v;
   constexpr int IFC = cmax_i<cmax_i<S::NIFC(0), NDIM >= 2 ? S::NIFC(1) : 0>::v,
                              NDIM >= 3 ? S::NIFC(2) : 0>::v;
@@ -97,13 +100,15 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
 
     static_for<0, NDIM>([&](auto Dc) {
       constexpr int D = decltype(Dc)::value;
+      constexpr int E0 = S::E(D, 0), E1 = S::E(D, 1);
+      constexpr int E0P = (D == 0) ? XP : E0;            // LDS row stride of the extended box
       constexpr int NEXT_D = S::NEXT(D);
+      constexpr int NEXTP = E0P * E1 * S::E(D, 2);       // LDS size of one variable's box
       constexpr int NIFC_D = S::NIFC(D);
       constexpr int NITEM = VPG * NIFC_D;
       constexpr int IPT = (NITEM + NT - 1) / NT;
-      constexpr int E0 = S::E(D, 0), E1 = S::E(D, 1);
       constexpr int I0 = S::I(D, 0), I1 = S::I(D, 1);
-      constexpr int SD = S::SD(D);
+      constexpr int SD = (D == 0) ? 1 : (D == 1) ? E0P : E0P * E1;
       const double c = cin[D];
       const double idx_d = B.inv_dx[D];
 
@@ -134,70 +139,150 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
             ok_all = prim<NDIM, MHD>(u, gamma, w) && ok_all;
             double F[NV];
             phys_flux<NDIM, MHD, D>(u, w, F);
+            const int el = a[0] + E0P * (a[1] + E1 * a[2]);
 #pragma unroll
             for (int vg = 0; vg < VPG; ++vg) {
-              constexpr int dummy = 0;
-              (void)dummy;
               const int v = G * VPG + vg;
               if (v < NV) {
-                lds[vg * NEXT_D + e] = 0.5 * fma(c, u[v], F[v]);
-                lds[(VPG + vg) * NEXT_D + e] = 0.5 * fma(-c, u[v], F[v]);
+                lds[vg * NEXTP + el] = 0.5 * fma(c, u[v], F[v]);
+                lds[(VPG + vg) * NEXTP + el] = 0.5 * fma(-c, u[v], F[v]);
               }
             }
           }
         }
         __syncthreads();
         // B) interface fluxes for every (variable, interface)
-        double res[IPT];
+        if constexpr (RUNS) {
+          // one item per (variable, pencil, run of up to 5 interfaces): the
+          // run shares curvatures and curvature limiters between its
+          // interfaces and reads every split flux once.  The last run of a
+          // pencil is shifted back to end at the pencil's last interface.
+          constexpr int NIF = S::T(D) + 1;
+          constexpr int RUN = NIF < 5 ? NIF : 5;
+          constexpr int NRUN = (NIF + RUN - 1) / RUN;
+          constexpr int NPEN = NIFC_D / NIF;
+          constexpr int NIT = VPG * NPEN * NRUN;
+          constexpr int IPR = (NIT + NT - 1) / NT;
+          double res[IPR][RUN];
 #pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-          const int w = tid + r * NT;
-          res[r] = 0.0;
-          if (w < NITEM) {
-            const int vg = w / NIFC_D;
-            const int q = w - vg * NIFC_D;
+          for (int r = 0; r < IPR; ++r) {
+            const int w = tid + r * NT;
+#pragma unroll
+            for (int kk = 0; kk < RUN; ++kk) res[r][kk] = 0.0;
+            if (w >= NIT) continue;
+            const int pen = w % NPEN;
+            const int run = (w / NPEN) % NRUN;
+            const int vg = w / (NPEN * NRUN);
+            const int k0 = run * RUN < NIF - RUN ? run * RUN : NIF - RUN;
             int a[3];
-            a[0] = q % I0;
-            a[1] = (q / I0) % I1;
-            a[2] = q / (I0 * I1);
+            if constexpr (D == 0) { a[0] = k0; a[1] = pen % TY; a[2] = pen / TY; }
+            if constexpr (D == 1) { a[0] = pen % TX; a[1] = k0; a[2] = pen / TX; }
+            if constexpr (D == 2) { a[0] = pen % TX; a[1] = pen / TX; a[2] = k0; }
             bool valid = (G * VPG + vg) < NV;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) valid = valid && (a[d] < tend[d] + (d == D ? 1 : 0));
-            if (valid) {
-              // interface between cells a_D - 1 and a_D (tile coordinates);
-              // stencil cells a_D - 3 .. a_D + 2 are ext indices a_D .. a_D + 5
-              int eb = 0;
-              {
-                int ea[3] = {a[0], a[1], a[2]};
-                eb = ea[0] + E0 * (ea[1] + E1 * ea[2]);
-              }
-              const double* fp = &lds[vg * NEXT_D + eb];
-              const double* fm = &lds[(VPG + vg) * NEXT_D + eb];
-              if constexpr (EMIT) {
-                // both linear pieces, stored on the lower face of cell a_D
-                int kp, km;
-                res[r] = mp5_coded(fp[0], fp[SD], fp[2 * SD], fp[3 * SD], fp[4 * SD], kp) +
-                         mp5_coded(fm[5 * SD], fm[4 * SD], fm[3 * SD], fm[2 * SD], fm[SD], km);
-                if (a[D] < tend[D]) {
-                  const long long cell =
-                      ((long long)(tl.o[2] + a[2]) * B.n[1] + (tl.o[1] + a[1])) * B.n[0] + (tl.o[0] + a[0]);
+            for (int d = 0; d < 3; ++d)
+              if (d != D) valid = valid && (a[d] < tend[d]);
+            if (!valid) continue;
+            // interface a_D lies between cells a_D - 1 and a_D; its F+
+            // stencil is ext a_D .. a_D + 4, its F- stencil ext a_D + 5 .. a_D + 1
+            const int eb = a[0] + E0P * (a[1] + E1 * a[2]);
+            double fp[RUN + 4], fm[RUN + 4];
+#pragma unroll
+            for (int m = 0; m < RUN + 4; ++m) {
+              fp[m] = lds[vg * NEXTP + eb + m * SD];
+              fm[m] = lds[(VPG + vg) * NEXTP + eb + (RUN + 4 - m) * SD];
+            }
+            double op[RUN], om[RUN];
+            int cp[RUN], cm[RUN];
+            mp5_run<RUN, EMIT>(fp, op, cp);
+            mp5_run<RUN, EMIT>(fm, om, cm);
+#pragma unroll
+            for (int kk = 0; kk < RUN; ++kk) res[r][kk] = op[kk] + om[RUN - 1 - kk];
+            if constexpr (EMIT) {
+              // linear pieces, stored on the lower face of cell a_D
+#pragma unroll
+              for (int kk = 0; kk < RUN; ++kk) {
+                int ci[3] = {tl.o[0] + a[0], tl.o[1] + a[1], tl.o[2] + a[2]};
+                ci[D] += kk;
+                if (k0 + kk < tend[D]) {
+                  const long long cell = ((long long)ci[2] * B.n[1] + ci[1]) * B.n[0] + ci[0];
                   P.codes[D * P.code_plane + (B.coff + cell) * 8 + (G * VPG + vg)] =
-                      (unsigned char)(kp | (km << 4));
+                      (unsigned char)(cp[kk] | (cm[RUN - 1 - kk] << 4));
                 }
-              } else {
-                res[r] = mp5(fp[0], fp[SD], fp[2 * SD], fp[3 * SD], fp[4 * SD]) +
-                         mp5(fm[5 * SD], fm[4 * SD], fm[3 * SD], fm[2 * SD], fm[SD]);
               }
             }
           }
-        }
-        __syncthreads();
+          __syncthreads();
 #pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-          const int w = tid + r * NT;
-          if (w < NITEM) lds[w] = res[r];
+          for (int r = 0; r < IPR; ++r) {
+            const int w = tid + r * NT;
+            if (w >= NIT) continue;
+            const int pen = w % NPEN;
+            const int run = (w / NPEN) % NRUN;
+            const int vg = w / (NPEN * NRUN);
+            const int k0 = run * RUN < NIF - RUN ? run * RUN : NIF - RUN;
+            int a[3];
+            if constexpr (D == 0) { a[0] = k0; a[1] = pen % TY; a[2] = pen / TY; }
+            if constexpr (D == 1) { a[0] = pen % TX; a[1] = k0; a[2] = pen / TX; }
+            if constexpr (D == 2) { a[0] = pen % TX; a[1] = pen / TX; a[2] = k0; }
+            const int q0 = a[0] + I0 * (a[1] + I1 * a[2]);
+            constexpr int SI = S::SI(D);
+#pragma unroll
+            for (int kk = 0; kk < RUN; ++kk) lds[vg * NIFC_D + q0 + kk * SI] = res[r][kk];
+          }
+          __syncthreads();
+        } else {
+          double res[IPT];
+#pragma unroll
+          for (int r = 0; r < IPT; ++r) {
+            const int w = tid + r * NT;
+            res[r] = 0.0;
+            if (w < NITEM) {
+              const int vg = w / NIFC_D;
+              const int q = w - vg * NIFC_D;
+              int a[3];
+              a[0] = q % I0;
+              a[1] = (q / I0) % I1;
+              a[2] = q / (I0 * I1);
+              bool valid = (G * VPG + vg) < NV;
+#pragma unroll
+              for (int d = 0; d < 3; ++d) valid = valid && (a[d] < tend[d] + (d == D ? 1 : 0));
+              if (valid) {
+                // interface between cells a_D - 1 and a_D (tile coordinates);
+                // stencil cells a_D - 3 .. a_D + 2 are ext indices a_D .. a_D + 5
+                int eb = 0;
+                {
+                  int ea[3] = {a[0], a[1], a[2]};
+                  eb = ea[0] + E0P * (ea[1] + E1 * ea[2]);
+                }
+                const double* fp = &lds[vg * NEXTP + eb];
+                const double* fm = &lds[(VPG + vg) * NEXTP + eb];
+                if constexpr (EMIT) {
+                  // both linear pieces, stored on the lower face of cell a_D
+                  int kp, km;
+                  res[r] = mp5_coded(fp[0], fp[SD], fp[2 * SD], fp[3 * SD], fp[4 * SD], kp) +
+                           mp5_coded(fm[5 * SD], fm[4 * SD], fm[3 * SD], fm[2 * SD], fm[SD], km);
+                  if (a[D] < tend[D]) {
+                    const long long cell =
+                        ((long long)(tl.o[2] + a[2]) * B.n[1] + (tl.o[1] + a[1])) * B.n[0] + (tl.o[0] + a[0]);
+                    P.codes[D * P.code_plane + (B.coff + cell) * 8 + (G * VPG + vg)] =
+                        (unsigned char)(kp | (km << 4));
+                  }
+                } else {
+                  res[r] = mp5(fp[0], fp[SD], fp[2 * SD], fp[3 * SD], fp[4 * SD]) +
+                           mp5(fm[5 * SD], fm[4 * SD], fm[3 * SD], fm[2 * SD], fm[SD]);
+                }
+              }
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < IPT; ++r) {
+            const int w = tid + r * NT;
+            if (w < NITEM) lds[w] = res[r];
+          }
+          __syncthreads();
         }
-        __syncthreads();
         // C) conservative difference into the owned cells
 #pragma unroll
         for (int r = 0; r < CPT; ++r) {
@@ -425,15 +510,21 @@ struct StageVariant {
   const char* name;
 };
 
-template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false>
+template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
+          bool RUNS = false>
 static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE, EMIT>), dim3(grid), dim3(NT), 0, s, p);
+  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE, EMIT, RUNS>), dim3(grid), dim3(NT), 0, s, p);
 }
 
 #define AMRVAC_VARIANT(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                       \
   {ND, M, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE>, \
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE>,                                          \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE}
+// the same with interfaces evaluated in runs along each pencil
+#define AMRVAC_VARIANT_R(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                  \
+  {ND, M, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>,                                          \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs"}
 
 // Tile shapes the autotuner chooses from (the first of each (ndim,
 // physics) is the default).  WPE = minimum waves per SIMD requested from
@@ -444,24 +535,34 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT(1, false, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT(1, true, 128, 1, 1, 128, 1, 1),
     AMRVAC_VARIANT(1, true, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT_R(1, true, 64, 1, 1, 64, 1, 1),
     // 2D
     AMRVAC_VARIANT(2, false, 16, 16, 1, 256, 1, 1),
     AMRVAC_VARIANT(2, false, 16, 16, 1, 256, 1, 3),
     AMRVAC_VARIANT(2, false, 32, 8, 1, 256, 1, 1),
+    AMRVAC_VARIANT_R(2, false, 16, 16, 1, 256, 1, 1),
     AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 2, 1),
     AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 1, 1),
     AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 2, 3),
     AMRVAC_VARIANT(2, true, 32, 8, 1, 256, 2, 1),
+    AMRVAC_VARIANT_R(2, true, 16, 16, 1, 256, 1, 1),
+    AMRVAC_VARIANT_R(2, true, 16, 16, 1, 256, 2, 2),
     // 3D
     AMRVAC_VARIANT(3, false, 8, 8, 8, 512, 2, 1),
     AMRVAC_VARIANT(3, false, 8, 8, 4, 256, 1, 1),
     AMRVAC_VARIANT(3, false, 8, 8, 8, 512, 2, 4),
+    AMRVAC_VARIANT_R(3, false, 8, 8, 4, 256, 1, 2),
     AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 2, 1),
     AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 2, 4),
     AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 2, 1),
     AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 2, 3),
     AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 4, 4),
     AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 4, 4),
+    AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 1),
+    AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 2),
+    AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 3),
+    AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 1),
+    AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 2),
 };
 
 const StageVariant* stage_variants(int* count) {
@@ -471,18 +572,18 @@ const StageVariant* stage_variants(int* count) {
 
 // Code-emitting stage kernels (the adjoint's forward recompute), one per
 // (ndim, physics); their tile shapes match the adjoint kernels'.
-#define AMRVAC_EMIT(ND, M, TX, TY, TZ, NT, NGRP)                                       \
-  {ND, M, TX, TY, TZ, NT, NGRP, 1, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, 1, true>, \
-   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, 1, true>,                                \
-   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-emit"}
+#define AMRVAC_EMIT(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                       \
+  {ND, M, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true>,                                          \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-emit"}
 
 static const StageVariant g_emit[] = {
-    AMRVAC_EMIT(1, false, 64, 1, 1, 64, 1),
-    AMRVAC_EMIT(1, true, 64, 1, 1, 64, 1),
-    AMRVAC_EMIT(2, false, 16, 16, 1, 256, 1),
-    AMRVAC_EMIT(2, true, 16, 16, 1, 256, 2),
-    AMRVAC_EMIT(3, false, 8, 8, 4, 256, 1),
-    AMRVAC_EMIT(3, true, 8, 8, 4, 256, 2),
+    AMRVAC_EMIT(1, false, 64, 1, 1, 64, 1, 1),
+    AMRVAC_EMIT(1, true, 64, 1, 1, 64, 1, 1),
+    AMRVAC_EMIT(2, false, 16, 16, 1, 256, 1, 1),
+    AMRVAC_EMIT(2, true, 16, 16, 1, 256, 2, 1),
+    AMRVAC_EMIT(3, false, 8, 8, 4, 256, 1, 2),
+    AMRVAC_EMIT(3, true, 8, 8, 4, 256, 2, 2),
 };
 
 const StageVariant* emit_variant(int ndim, int mhd) {
