@@ -50,15 +50,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(variant):
     """HBM bytes per stage launch from committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs, if taken on the current kernel source."""
+    WRITE_SIZE runs (calibrated against a plain copy), if they were taken on
+    the current kernel source and on the tile shape that is being timed."""
     path = os.path.join(ROOT, "profiles", "stage_kernel_mhd3d_uneven4096_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("variant") != variant:
         return None
     return rec.get("bytes_per_launch")
 
@@ -217,10 +218,10 @@ def main():
 
     flops = FLOPS_PER_CELL_STAGE_MHD3D * cells
     achieved = flops / stage_s / 1e12
-    traffic = measured_traffic()
+    traffic = measured_traffic(variant)
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                "kernel": "k_stage<3,MHD> (fused SSPRK stage)",
+                "kernel": f"k_stage<3,MHD> (fused SSPRK stage), {variant}",
                 "hbm_algorithmic_GBs": BYTES_PER_CELL_STEP_MHD3D * cells / STAGES / stage_s / 1e9,
                 "hbm_frac": BYTES_PER_CELL_STEP_MHD3D * cells / STAGES / stage_s / 1e9 / PEAK_HBM_GBS}
 
