@@ -98,11 +98,13 @@ def cpu_baseline(bs_full, min_seconds=10.0, max_steps=4):
                       f"{steps} SSPRK(5,4) steps, {el:.1f} s wall, OpenMP over blocks"}
 
 
-def adjoint_ratio(nsteps, ckpt):
+def adjoint_ratio(nsteps, ckpt, warm=80, ckpt_also=None):
     """Adjoint / forward wall-time ratio on 3D ideal MHD, 256^3 periodic as
     4096 blocks of 16^3 (16-mode velocity and field perturbations, plasma
-    beta 1): nsteps fixed-dt SSPRK(5,4) steps forward, then the adjoint of
-    the same nsteps (checkpoints every `ckpt` steps, recompute included)."""
+    beta 1), fixed dt from the CFL rule on the initial state: `warm` steps
+    forward (untimed), then `nsteps` timed forward steps, then the adjoint of
+    those nsteps (checkpoints every `ckpt` steps, recompute included) with
+    lambda_N = rho_N - 1 in the density slot."""
     import torch
     from paper_1407_2052_amd import amrvac, inputs
 
@@ -113,31 +115,79 @@ def adjoint_ratio(nsteps, ckpt):
     _, cm = ctx.fd_rhs()
     dt = 0.4 / sum(cm[d] / bs.dx[0, d] for d in range(3))
     stream = torch.cuda.current_stream()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    u0 = flat.clone()
-    ctx.ssprk_step(amrvac.SSPRK54, 1, dt=dt, t=None)      # warm-up (graph capture)
-    flat.copy_(u0)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    print(f"bench: {warm} forward steps to the adjoint window", file=sys.stderr, flush=True)
+    ctx.ssprk_step(amrvac.SSPRK54, warm, dt=dt, t=None)
     torch.cuda.synchronize()
-    e[0].record(stream)
-    ctx.ssprk_step(amrvac.SSPRK54, nsteps, dt=dt, t=None)
-    e[1].record(stream)
-    torch.cuda.synchronize()
+    u_w = flat.clone()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        fn()
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        return e[0].elapsed_time(e[1]) / 1e3
+
+    fwd = timed(lambda: ctx.ssprk_step(amrvac.SSPRK54, nsteps, dt=dt, t=None))
     ctx.sync()
-    fwd = e[0].elapsed_time(e[1]) / 1e3
-    lam = [torch.zeros_like(v) for v in views]
-    for l in lam:
-        l[0, 3:-3, 3:-3, 3:-3] = 1e-3
-    flat.copy_(u0)
-    print(f"bench: adjoint of {nsteps} steps (checkpoints every {ckpt})", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    e[2].record(stream)
-    ctx.ssprk_adjoint(amrvac.SSPRK54, dt, nsteps, ckpt, lam)
-    e[3].record(stream)
-    torch.cuda.synchronize()
-    adj = e[2].elapsed_time(e[3]) / 1e3
+    lam_n = [torch.zeros_like(v) for v in views]
+    for l, v in zip(lam_n, views):
+        l[0, 3:-3, 3:-3, 3:-3] = v[0, 3:-3, 3:-3, 3:-3] - 1.0
+    out = {"workload": "3D ideal MHD 256^3 periodic, 4096 x 16^3, SSPRK(5,4), steps "
+                       f"{warm + 1}-{warm + nsteps} after {warm} forward steps",
+           "steps": nsteps, "forward_s": fwd, "forward_cell_updates_per_s": cells * nsteps / fwd}
+    for k in [ckpt] + ([ckpt_also] if ckpt_also else []):
+        flat.copy_(u_w)
+        lam = [l.clone() for l in lam_n]
+        print(f"bench: adjoint of {nsteps} steps (checkpoints every {k})", file=sys.stderr, flush=True)
+        adj = timed(lambda: ctx.ssprk_adjoint(amrvac.SSPRK54, dt, nsteps, k, lam))
+        key = "" if k == ckpt else f"_ckpt{k}"
+        out["ckpt_every" + key] = k
+        out["adjoint_s" + key] = adj
+        out["ratio" + key] = adj / fwd
     ctx.close()
-    return {"workload": "3D ideal MHD 256^3 periodic, 4096 x 16^3, SSPRK(5,4)", "steps": nsteps,
-            "ckpt_every": ckpt, "forward_s": fwd, "adjoint_s": adj, "ratio": adj / fwd,
+    return out
+
+
+def adjoint_ratio_2d(nsteps=200, ckpt=20):
+    """Adjoint / forward wall-time ratio on 2D Euler 256^2 periodic (256
+    blocks of 16^2, 8-mode density perturbation, v = 0, p = 1), fixed dt from
+    the CFL rule on the initial state, J = 1/2 sum (rho_N - rho*)^2."""
+    import torch
+    from paper_1407_2052_amd import amrvac, inputs
+
+    bs = inputs.hydro_random_2d()
+    target = inputs.hydro_target_density()
+    cells = bs.interior_cells()
+    ctx, flat, views = amrvac.context_for(bs, amrvac.EXEC_BATCHED)
+    _, cm = ctx.fd_rhs()
+    dt = 0.4 / sum(cm[d] / bs.dx[0, d] for d in range(2))
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    u0 = flat.clone()
+    ctx.ssprk_step(amrvac.SSPRK54, 1, dt=dt, t=None)      # graph capture
+    flat.copy_(u0)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        fn()
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        return e[0].elapsed_time(e[1]) / 1e3
+
+    fwd = timed(lambda: ctx.ssprk_step(amrvac.SSPRK54, nsteps, dt=dt, t=None))
+    ctx.sync()
+    lam = [torch.zeros_like(v) for v in views]
+    for b, (l, v) in enumerate(zip(lam, views)):
+        l[0, 0, 3:-3, 3:-3] = v[0, 0, 3:-3, 3:-3] - torch.from_numpy(target[b].reshape(v.shape[2] - 6, v.shape[3] - 6)).to(v.device)
+    flat.copy_(u0)
+    print(f"bench: 2D Euler adjoint of {nsteps} steps (checkpoints every {ckpt})", file=sys.stderr, flush=True)
+    adj = timed(lambda: ctx.ssprk_adjoint(amrvac.SSPRK54, dt, nsteps, ckpt, lam))
+    ctx.close()
+    return {"workload": "2D Euler 256^2 periodic, 256 x 16^2, SSPRK(5,4)", "steps": nsteps, "ckpt_every": ckpt,
+            "forward_s": fwd, "adjoint_s": adj, "ratio": adj / fwd,
             "forward_cell_updates_per_s": cells * nsteps / fwd}
 
 
@@ -152,6 +202,10 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=20)
     ap.add_argument("--ckpt", type=int, default=5)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-warm", type=int, default=80,
+                    help="forward steps before the timed adjoint window (3D MHD 256^3)")
+    ap.add_argument("--ckpt-also", type=int, default=20,
+                    help="also time the adjoint with this checkpoint interval (0: no)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run one plain device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -171,6 +225,9 @@ def main():
     stream = torch.cuda.current_stream()
     print("bench: autotuning the tile shape", file=sys.stderr, flush=True)
     variant, tune_ms = ctx.autotune(amrvac.SSPRK54, 2)
+    for name, ms in zip(ctx.variants(), tune_ms):
+        if ms >= 0:
+            print(f"bench: autotune {name} {ms:.3f} ms/step", file=sys.stderr, flush=True)
 
     def timed(nsteps, warmup):
         if warmup:
@@ -212,9 +269,11 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    adjoint = None
+    adjoint = adjoint_2d = None
     if not args.no_adjoint:
-        adjoint = adjoint_ratio(args.adjoint_steps, args.ckpt)
+        adjoint = adjoint_ratio(args.adjoint_steps, args.ckpt, args.adjoint_warm,
+                                args.ckpt_also if args.ckpt_also > 0 else None)
+        adjoint_2d = adjoint_ratio_2d()
 
     flops = FLOPS_PER_CELL_STAGE_MHD3D * cells
     achieved = flops / stage_s / 1e12
@@ -244,6 +303,7 @@ def main():
         "batched_over_per_block": (value / per_block["value"]) if per_block else None,
         "adjoint_forward_ratio": adjoint["ratio"] if adjoint else None,
         "adjoint": adjoint,
+        "adjoint_2d_euler": adjoint_2d,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
