@@ -75,7 +75,19 @@ CASES = {
     "ragged3d_hd": lambda: strip_blocks(3, False, [10, 6], ny=9, nz=11, seed=4, gamma=1.4),
     "mhd3d": lambda: inputs.mhd_turbulence_3d(N=32, block=16, seed=5),
     "uneven3d": uneven_small,
+    # the smallest blocks allowed (3 cells: a halo is a neighbour's whole
+    # interior, or the block's own interior through the periodic wrap)
+    "min3_1d_mhd": lambda: strip_blocks(1, True, [3, 5, 3, 3, 8, 3], seed=6),
+    "min3_3d_mhd": lambda: strip_blocks(3, True, [3, 4, 3], ny=3, nz=3, seed=7),
+    # one large block, periodic onto itself
+    "big2d_single": lambda: big_single_block(),
 }
+
+
+def big_single_block(N=512):
+    n, dx, xlo, nbr, _ = inputs.uniform_blocks(2, [N, N], [N, N])
+    from helpers import smooth_fields
+    return inputs.sample_blocks(2, True, 5 / 3, n, dx, xlo, nbr, smooth_fields(2, True, 8, amp=0.08))
 
 
 def rhs_scale(bs, cmax):
@@ -119,6 +131,9 @@ STEP_CASES = [
     ("ragged3d_hd", oracle.RK3, 30),
     ("mhd3d", oracle.SSPRK54, 20),
     ("uneven3d", oracle.SSPRK54, 10),
+    ("min3_1d_mhd", oracle.SSPRK54, 50),
+    ("min3_3d_mhd", oracle.RK3, 10),
+    ("big2d_single", oracle.SSPRK54, 2),
 ]
 
 
@@ -331,7 +346,7 @@ def test_full_size_mhd3d_256_conserves_totals():
 
 # ---------------------------------------------------------------- tile shapes
 @pytest.mark.parametrize("case", ["dwave1d_8blk", "ot2d", "hydro2d", "ragged2d_mhd", "mhd3d", "uneven3d",
-                                  "ragged3d_hd", "ragged3d_mhd"])
+                                  "ragged3d_hd", "ragged3d_mhd", "min3_3d_mhd", "min3_1d_mhd"])
 def test_every_tile_shape_is_bitwise_identical(case):
     bs = CASES[case]()
     ref = None
