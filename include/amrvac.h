@@ -190,6 +190,32 @@ amrvac_status amrvac_ssprk_step(amrvac_ctx *ctx, int scheme, double cfl, const d
 amrvac_status amrvac_ssprk_adjoint(amrvac_ctx *ctx, int scheme, double dt, int nsteps,
                                    int ckpt_every, double *const *lam);
 
+/* Dynamic grid activation (the paper's appendix "Dynamic grid
+ * activation"), the host-side list building: a block is active when
+ * want[b] != 0 (the caller's criterion); then, `safety` times, every passive
+ * block with an active face neighbour becomes active (the safety belt; each
+ * pass works on the flags the previous pass produced).  blocks: the block
+ * list (only nbr is read); want, active_out: host arrays of nblocks bytes;
+ * active_out receives 1 (active) or 0 (passive).  Returns the number of
+ * active blocks, or -1 for invalid arguments (a null pointer, nblocks < 1,
+ * safety < 0, a neighbour index outside [-1, nblocks)).  Makes no HIP call
+ * and needs no device. */
+int amrvac_activation_flags(const amrvac_block *blocks, int nblocks, const unsigned char *want,
+                            int safety, unsigned char *active_out);
+
+/* Dynamic grid activation, integration side: later amrvac_fd_rhs and
+ * amrvac_ssprk_step calls evaluate and advance only the blocks with
+ * active[b] != 0 (host array of nblocks bytes; NULL = every block, the
+ * state after amrvac_set_blocks).  c_max and the time step are taken over
+ * the active blocks' cells and cell widths.  Passive blocks are not
+ * written: their current interiors are read at the start of every
+ * amrvac_ssprk_step call and serve, unchanged through all stages, as halo
+ * for active neighbours; amrvac_fd_rhs leaves their rhs arrays untouched.
+ * Rebuilds the work list and drops cached graphs.  amrvac_autotune and
+ * amrvac_ssprk_adjoint return UNSUPPORTED while a block is passive.
+ * Errors: INVALID (no blocks, no active block), NOMEM, DEVICE. */
+amrvac_status amrvac_set_active(amrvac_ctx *ctx, const unsigned char *active);
+
 /* Waits for the context stream and returns (and clears) the sticky device
  * error: OK, NONPHYSICAL or DEVICE. */
 amrvac_status amrvac_sync(amrvac_ctx *ctx);

@@ -54,6 +54,7 @@ def lib():
                                   ctypes.c_int, dpp, dpp]
         L.orc_branch_hash_end.restype = ctypes.c_uint64
         L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_active.argtypes = [ctypes.POINTER(ctypes.c_ubyte), ctypes.c_int]
         _LIB = L
     return _LIB
 
@@ -185,6 +186,18 @@ def num_threads() -> int:
 
 def set_threads(n: int) -> None:
     lib().orc_set_threads(int(n))
+
+
+def set_active(flags: Optional[Sequence[int]]) -> None:
+    """Dynamic grid activation (appendix "Dynamic grid activation"): later
+    calls on a block list of len(flags) blocks advance only the blocks with a
+    nonzero flag; passive blocks keep their state and act as ghost sources.
+    None: every block active."""
+    if flags is None:
+        lib().orc_set_active(None, 0)
+        return
+    arr = (ctypes.c_ubyte * len(flags))(*[1 if f else 0 for f in flags])
+    lib().orc_set_active(arr, len(flags))
 
 
 def run_branch_hash(bs, scheme: int, nsteps: int, dt: float, eps: float = 0.0) -> int:

@@ -325,7 +325,15 @@ struct Geom {
 struct Grid {
   Phys ph;
   std::vector<Geom> g;
+  // dynamic grid activation (appendix "Dynamic grid activation"): only
+  // active blocks are advanced; passive blocks keep their state, which
+  // active neighbours read as ghost values.  Empty: every block is active.
+  std::vector<unsigned char> active;
+  bool is_active(size_t b) const { return active.empty() || active[b] != 0; }
 };
+
+// Active flags for the next calls (set by orc_set_active; test infrastructure).
+static std::vector<unsigned char> g_active;
 
 template <class T> using State = std::vector<std::vector<T>>;   // [block][var*ncell + idx]
 
@@ -349,6 +357,8 @@ static int build_grid(Grid& G, int ndim, int mhd, double gamma, int nb, const in
     for (int f = 0; f < 6; ++f) q.nbr[f] = (f < 2 * ndim) ? nbr[6 * b + f] : -1;
     q.ncell = (size_t)q.P[0] * q.P[1] * q.P[2];
   }
+  G.active.clear();
+  if ((int)g_active.size() == nb) G.active = g_active;
   return ORC_OK;
 }
 
@@ -394,6 +404,7 @@ static int global_cmax(const Grid& G, const State<T>& U, T cmax[3]) {
   uint64_t arg[3] = {0, 0, 0};
   bool first = true;
   for (size_t b = 0; b < G.g.size(); ++b) {
+    if (!G.is_active(b)) continue;
     const Geom& q = G.g[b];
     for (int k = 0; k < q.n[2]; ++k)
       for (int j = 0; j < q.n[1]; ++j)
@@ -428,6 +439,7 @@ static int rhs(const Grid& G, const State<T>& U, const T cmax[3], State<T>& L, d
   for (int b = 0; b < nb; ++b) {
     const Geom& q = G.g[b];
     std::fill(L[b].begin(), L[b].end(), T(0.0));
+    if (!G.is_active(b)) continue;
     for (int d = 0; d < G.ph.ndim; ++d) {
       const int nd = q.n[d];
       const int len = nd + 2 * NG;
@@ -489,7 +501,9 @@ static void alloc_state(const Grid& G, State<T>& S) {
 
 static double dt_rule(const Grid& G, const double cmax[3], double cfl) {
   double worst = 0.0;
-  for (const Geom& q : G.g) {
+  for (size_t b = 0; b < G.g.size(); ++b) {
+    if (!G.is_active(b)) continue;
+    const Geom& q = G.g[b];
     double s = 0.0;
     for (int d = 0; d < G.ph.ndim; ++d) s += cmax[d] / q.dx[d];
     worst = std::max(worst, s);
@@ -522,8 +536,9 @@ static int ssprk_step(const Grid& G, const Scheme& S, State<T>& U, double cfl, d
     alloc_state(G, Ls[k]);
     st = rhs(G, Us[k], cm, Ls[k], eps);
     if (st) return st;
-    Us[i] = Us[0];   // ghost layers: fixed faces keep U^n's values
+    Us[i] = Us[0];   // ghost layers: fixed faces keep U^n's values; passive blocks keep U^n
     for (size_t b = 0; b < G.g.size(); ++b) {
+      if (!G.is_active(b)) continue;
       const Geom& q = G.g[b];
       for (int kk = 0; kk < q.n[2]; ++kk)
         for (int j = 0; j < q.n[1]; ++j)
@@ -718,6 +733,14 @@ void orc_branch_hash_begin(void) {
 uint64_t orc_branch_hash_end(void) {
   g_hash_on = false;
   return g_hash;
+}
+
+// Active flags (one byte per block, nonzero = active) used by the grids of
+// every later call with the same number of blocks; n = 0 or flags = NULL
+// makes every block active again.
+void orc_set_active(const unsigned char* flags, int n) {
+  g_active.clear();
+  if (flags && n > 0) g_active.assign(flags, flags + n);
 }
 
 void orc_set_threads(int n) {

@@ -28,6 +28,7 @@ SYMBOLS = ["amrvac_abi_version", "amrvac_create", "amrvac_set_blocks", "amrvac_v
            "amrvac_set_exec", "amrvac_num_variants", "amrvac_variant_name", "amrvac_set_variant",
            "amrvac_get_variant",
            "amrvac_autotune", "amrvac_fd_rhs", "amrvac_ssprk_step", "amrvac_ssprk_adjoint",
+           "amrvac_activation_flags", "amrvac_set_active",
            "amrvac_sync", "amrvac_last_error", "amrvac_destroy"]
 
 
@@ -76,13 +77,18 @@ def lib():
         L.amrvac_fd_rhs.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p), dp]
         L.amrvac_ssprk_step.argtypes = [vp, ip, ctypes.c_double, dp, ip, dp]
         L.amrvac_ssprk_adjoint.argtypes = [vp, ip, ctypes.c_double, ip, ip, ctypes.POINTER(ctypes.c_void_p)]
+        ub = ctypes.POINTER(ctypes.c_ubyte)
+        L.amrvac_activation_flags.argtypes = [ctypes.POINTER(Block), ip, ub, ip, ub]
+        L.amrvac_activation_flags.restype = ctypes.c_int
+        L.amrvac_set_active.argtypes = [vp, ub]
         L.amrvac_sync.argtypes = [vp]
         L.amrvac_last_error.restype = ctypes.c_char_p
         L.amrvac_last_error.argtypes = [vp]
         L.amrvac_destroy.argtypes = [vp]
         for name in ("amrvac_create", "amrvac_set_blocks", "amrvac_validate_blocks", "amrvac_set_exec",
                      "amrvac_set_variant", "amrvac_autotune",
-                     "amrvac_fd_rhs", "amrvac_ssprk_step", "amrvac_ssprk_adjoint", "amrvac_sync"):
+                     "amrvac_fd_rhs", "amrvac_ssprk_step", "amrvac_ssprk_adjoint", "amrvac_set_active",
+                     "amrvac_sync"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -100,6 +106,17 @@ def make_blocks(ptrs: Sequence[int], n, dx, xlo, nbr) -> ctypes.Array:
         for f in range(6):
             arr[b].nbr[f] = int(nbr[b][f])
     return arr
+
+
+def activation_flags(nbr, want, safety: int) -> Tuple[int, np.ndarray]:
+    """Active/passive flags after the safety belt (host only, no device):
+    returns (number of active blocks or -1, flags)."""
+    nb = len(want)
+    arr = make_blocks([0] * nb, np.ones((nb, 3)), np.ones((nb, 3)), np.zeros((nb, 3)), nbr)
+    w = (ctypes.c_ubyte * nb)(*[1 if x else 0 for x in want])
+    out = (ctypes.c_ubyte * nb)()
+    n = lib().amrvac_activation_flags(arr, nb, w, int(safety), out)
+    return n, np.array(list(out), dtype=np.uint8)
 
 
 def validate_blocks(ndim: int, mhd: bool, gamma: float, ptrs, n, dx, xlo, nbr) -> Tuple[int, str]:
@@ -166,6 +183,14 @@ class Context:
     def variants(self) -> List[str]:
         n = lib().amrvac_num_variants(self._h)
         return [lib().amrvac_variant_name(self._h, i).decode() for i in range(n)]
+
+    def set_active(self, active=None):
+        """Advance only the blocks with active[b] != 0 (None: every block)."""
+        if active is None:
+            self._check(lib().amrvac_set_active(self._h, None))
+            return
+        a = (ctypes.c_ubyte * len(active))(*[1 if x else 0 for x in active])
+        self._check(lib().amrvac_set_active(self._h, a))
 
     def set_variant(self, i: int):
         self._check(lib().amrvac_set_variant(self._h, i))

@@ -54,6 +54,8 @@ static void free_tables(amrvac_ctx* c) {
   if (c->d_scr) (void)hipFree(c->d_scr);
   if (c->d_dxtab) (void)hipFree(c->d_dxtab);
   if (c->d_rhs_ptrs) (void)hipFree(c->d_rhs_ptrs);
+  if (c->d_ptiles) (void)hipFree(c->d_ptiles);
+  c->d_ptiles = nullptr;
   c->d_blocks = nullptr;
   c->d_tiles = nullptr;
   c->d_scr = nullptr;
@@ -128,10 +130,12 @@ static amrvac_status build_tiles(amrvac_ctx* c) {
     return key[a] < key[b];
   });
   c->htiles.clear();
+  c->hptiles.clear();
   c->blk_tile_begin.assign(nb, 0);
   c->blk_tile_count.assign(nb, 0);
   for (int b : order) {
     const amrvac_block& q = c->hb[b];
+    const bool act = c->active.empty() || c->active[b];
     int nt[3];
     for (int d = 0; d < 3; ++d) nt[d] = (q.n[d] + T[d] - 1) / T[d];
     std::vector<std::pair<uint64_t, Tile>> tl;
@@ -149,15 +153,28 @@ static amrvac_status build_tiles(amrvac_ctx* c) {
                      [](const std::pair<uint64_t, Tile>& a, const std::pair<uint64_t, Tile>& b) {
                        return a.first < b.first;
                      });
+    if (!act) {   // passive: no work, its tiles only feed the slot copies
+      c->blk_tile_begin[b] = (int)c->htiles.size();
+      for (auto& p : tl) c->hptiles.push_back(p.second);
+      continue;
+    }
     c->blk_tile_begin[b] = (int)c->htiles.size();
     c->blk_tile_count[b] = (int)tl.size();
     for (auto& p : tl) c->htiles.push_back(p.second);
   }
+  if (c->htiles.empty()) return fail(c, AMRVAC_ERR_INVALID, "no active block");
   if (c->d_tiles) (void)hipFree(c->d_tiles);
   c->d_tiles = nullptr;
   HIP_TRY(c, hipMalloc(&c->d_tiles, sizeof(Tile) * c->htiles.size()));
   HIP_TRY(c, hipMemcpyAsync(c->d_tiles, c->htiles.data(), sizeof(Tile) * c->htiles.size(),
                             hipMemcpyHostToDevice, c->stream));
+  if (c->d_ptiles) (void)hipFree(c->d_ptiles);
+  c->d_ptiles = nullptr;
+  if (!c->hptiles.empty()) {
+    HIP_TRY(c, hipMalloc(&c->d_ptiles, sizeof(Tile) * c->hptiles.size()));
+    HIP_TRY(c, hipMemcpyAsync(c->d_ptiles, c->hptiles.data(), sizeof(Tile) * c->hptiles.size(),
+                              hipMemcpyHostToDevice, c->stream));
+  }
   int per_cu = 0;
   HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V->fn, V->nt, 0));
   if (per_cu < 1) return fail(c, AMRVAC_ERR_DEVICE, "stage kernel cannot be resident");
@@ -355,7 +372,11 @@ static void launch_stage(amrvac_ctx* c, StageParams p, int exec, hipStream_t s) 
     q.ntiles = c->blk_tile_count[b];
     // the slot reset must run once, on the first launch only
     if (b > 0) q.cm_reset = -1;
-    c->var->launch(q, q.ntiles, s);
+    if (q.ntiles > 0) {
+      c->var->launch(q, q.ntiles, s);
+    } else if (b == 0 && p.cm_reset >= 0) {
+      launch_clear_slot(c->d_ctl, p.cm_reset, s);   // block 0 is passive: clear here
+    }
   }
 }
 
@@ -557,6 +578,8 @@ amrvac_status amrvac_set_blocks(amrvac_ctx* c, const amrvac_block* blocks, int n
   free_tables(c);
   c->hb.assign(blocks, blocks + nblocks);
   c->hdev.resize(nblocks);
+  c->active.assign(nblocks, 1);
+  c->n_active = nblocks;
   long long off = 0;
   std::vector<double> dxt;
   for (int b = 0; b < nblocks; ++b) {
@@ -634,6 +657,8 @@ amrvac_status amrvac_autotune(amrvac_ctx* c, int scheme, int nsteps, double* ms_
   if (c->hb.empty()) return fail(c, AMRVAC_ERR_INVALID, "autotune: no blocks set");
   if (scheme < AMRVAC_RK3 || scheme > AMRVAC_SSPRK54 || nsteps < 1)
     return fail(c, AMRVAC_ERR_INVALID, "autotune: invalid scheme or nsteps");
+  if (c->n_active < (int)c->hb.size())
+    return fail(c, AMRVAC_ERR_UNSUPPORTED, "autotune: some blocks are passive");
   const int nv = count_variants(c);
   if (ms_out)
     for (int i = 0; i < nv; ++i) ms_out[i] = -1.0;
@@ -751,6 +776,15 @@ amrvac_status amrvac_ssprk_step(amrvac_ctx* c, int scheme, double cfl, const dou
   }
   amrvac_status st = ensure_slots(c, 3);
   if (st != AMRVAC_OK) return st;
+  if (!c->hptiles.empty() && nsteps > 0) {
+    // passive blocks: their current state in the stage buffers A and B,
+    // which active neighbours read as halo at every stage
+    const StageVariant* V = c->var;
+    const int np = (int)c->hptiles.size();
+    const int grid = std::max(1, std::min(np, c->ncu * 8));
+    launch_copy_interior(state_table(c), c->d_ptiles, np, V->tx, V->ty, V->tz, c->nvar, 0, 1, grid, c->stream);
+    launch_copy_interior(state_table(c), c->d_ptiles, np, V->tx, V->ty, V->tz, c->nvar, 0, 2, grid, c->stream);
+  }
   launch_set_control(c->d_ctl, dt_fixed ? *dt_fixed : 0.0, cfl, t_inout ? *t_inout : 0.0, c->stream);
   if (nsteps > 0) launch_cmax_of(c, 0, 0, c->stream);
   const int exec = c->exec;
@@ -778,6 +812,82 @@ amrvac_status amrvac_ssprk_step(amrvac_ctx* c, int scheme, double cfl, const dou
     *t_inout = t;
     return st;
   }
+  return AMRVAC_OK;
+}
+
+int amrvac_activation_flags(const amrvac_block* blocks, int nblocks, const unsigned char* want, int safety,
+                            unsigned char* active_out) {
+  if (!blocks || nblocks < 1 || !want || safety < 0 || !active_out) return -1;
+  for (int b = 0; b < nblocks; ++b)
+    for (int f = 0; f < 6; ++f)
+      if (blocks[b].nbr[f] < -1 || blocks[b].nbr[f] >= nblocks) return -1;
+  // step 1: the caller's criterion; step 2, `safety` times: a passive block
+  // with an active face neighbour becomes active
+  std::vector<unsigned char> cur(nblocks), next;
+  for (int b = 0; b < nblocks; ++b) cur[b] = want[b] ? 1 : 0;
+  for (int pass = 0; pass < safety; ++pass) {
+    next = cur;
+    for (int b = 0; b < nblocks; ++b) {
+      if (cur[b]) continue;
+      for (int f = 0; f < 6; ++f) {
+        const int nb = blocks[b].nbr[f];
+        if (nb >= 0 && cur[nb]) next[b] = 1;
+      }
+    }
+    cur.swap(next);
+  }
+  int n = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    active_out[b] = cur[b];
+    n += cur[b];
+  }
+  return n;
+}
+
+amrvac_status amrvac_set_active(amrvac_ctx* c, const unsigned char* active) {
+  if (!c) return AMRVAC_ERR_INVALID;
+  if (c->hb.empty()) return fail(c, AMRVAC_ERR_INVALID, "set_active: no blocks set");
+  const int nb = (int)c->hb.size();
+  std::vector<unsigned char> a(nb, 1);
+  int n = nb;
+  if (active) {
+    n = 0;
+    for (int b = 0; b < nb; ++b) {
+      a[b] = active[b] ? 1 : 0;
+      n += a[b];
+    }
+  }
+  if (n == 0) return fail(c, AMRVAC_ERR_INVALID, "set_active: no active block");
+  drop_graphs(c);
+  c->active = a;
+  c->n_active = n;
+  amrvac_status st = build_tiles(c);
+  if (st != AMRVAC_OK) return st;
+  // dt rule over the active blocks' cell widths
+  std::vector<double> dxt;
+  for (int b = 0; b < nb; ++b) {
+    if (!a[b]) continue;
+    const BlockDev& D = c->hdev[b];
+    bool seen = false;
+    for (size_t k = 0; k < dxt.size(); k += 3)
+      if (dxt[k] == D.dx[0] && dxt[k + 1] == D.dx[1] && dxt[k + 2] == D.dx[2]) seen = true;
+    if (!seen) {
+      dxt.push_back(D.dx[0]);
+      dxt.push_back(D.dx[1]);
+      dxt.push_back(D.dx[2]);
+    }
+  }
+  if (c->d_dxtab) (void)hipFree(c->d_dxtab);
+  c->d_dxtab = nullptr;
+  HIP_TRY(c, hipMalloc(&c->d_dxtab, sizeof(double) * dxt.size()));
+  HIP_TRY(c, hipMemcpyAsync(c->d_dxtab, dxt.data(), sizeof(double) * dxt.size(), hipMemcpyHostToDevice,
+                            c->stream));
+  c->ndx = (int)(dxt.size() / 3);
+  Control h{};
+  HIP_TRY(c, hipMemcpyAsync(&h, c->d_ctl, sizeof(Control), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  h.ndx = c->ndx;
+  HIP_TRY(c, hipMemcpy(c->d_ctl, &h, sizeof(Control), hipMemcpyHostToDevice));
   return AMRVAC_OK;
 }
 

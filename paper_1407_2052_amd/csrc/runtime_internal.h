@@ -64,6 +64,12 @@ struct amrvac_ctx {
   std::vector<Tile> htiles;
   Tile* d_tiles = nullptr;
   std::vector<int> blk_tile_begin, blk_tile_count;
+
+  // dynamic grid activation: 1 = advanced, 0 = passive (kept, read as halo)
+  std::vector<unsigned char> active;
+  int n_active = 0;
+  std::vector<Tile> hptiles;   // tiles of the passive blocks
+  Tile* d_ptiles = nullptr;
   int grid_batched = 0;
 
   // scratch
