@@ -104,7 +104,10 @@ def adjoint_ratio(nsteps, ckpt, warm=80, ckpt_also=None):
     beta 1), fixed dt from the CFL rule on the initial state: `warm` steps
     forward (untimed), then `nsteps` timed forward steps, then the adjoint of
     those nsteps (checkpoints every `ckpt` steps, recompute included) with
-    lambda_N = rho_N - 1 in the density slot."""
+    lambda_N = rho_N - 1 in the density slot.  Then the same forward steps
+    with only the blocks near the box centre active (dynamic grid
+    activation, safety belt of one block)."""
+    import numpy as np
     import torch
     from paper_1407_2052_amd import amrvac, inputs
 
@@ -146,6 +149,19 @@ def adjoint_ratio(nsteps, ckpt, warm=80, ckpt_also=None):
         out["ckpt_every" + key] = k
         out["adjoint_s" + key] = adj
         out["ratio" + key] = adj / fwd
+    # dynamic grid activation: blocks whose centre lies within 0.25 of the
+    # box centre are active, plus a safety belt of one block
+    centres = bs.xlo + 0.5 * bs.n * bs.dx
+    want = (np.sqrt(((centres - 0.5) ** 2).sum(axis=1)) < 0.25).astype(np.uint8)
+    n_act, flags = amrvac.activation_flags(bs.nbr, want, 1)
+    flat.copy_(u_w)
+    ctx.set_active(flags)
+    ctx.ssprk_step(amrvac.SSPRK54, 1, dt=dt, t=None)      # graph capture
+    masked = timed(lambda: ctx.ssprk_step(amrvac.SSPRK54, nsteps, dt=dt, t=None))
+    ctx.sync()
+    out["activation"] = {"active_blocks": int(n_act), "blocks": bs.nb, "active_fraction": n_act / bs.nb,
+                         "step_time_fraction": masked / fwd,
+                         "active_cell_updates_per_s": n_act * 16 ** 3 * nsteps / masked}
     ctx.close()
     return out
 
