@@ -16,6 +16,7 @@ _LIB = None
 
 RK3, SSPRK43, SSPRK54 = 0, 1, 2
 STAGES = {RK3: 3, SSPRK43: 4, SSPRK54: 5}
+MP5, LIM03 = 0, 1
 
 
 class OracleError(RuntimeError):
@@ -37,6 +38,12 @@ def lib():
         L.orc_mp5.argtypes = [dp, ctypes.c_double]
         L.orc_mp5_grad.restype = ctypes.c_double
         L.orc_mp5_grad.argtypes = [dp, ctypes.c_double, dp]
+        L.orc_lim03.restype = ctypes.c_double
+        L.orc_lim03.argtypes = [dp, ctypes.c_double]
+        L.orc_lim03_grad.restype = ctypes.c_double
+        L.orc_lim03_grad.argtypes = [dp, ctypes.c_double, dp]
+        L.orc_set_lim03_radius.argtypes = [ctypes.c_double]
+        L.orc_set_recon.argtypes = [ctypes.c_int]
         L.orc_prim.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
         L.orc_flux.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp]
         L.orc_fast_speed.restype = ctypes.c_double
@@ -99,6 +106,47 @@ def mp5_grad(f: Sequence[float], eps: float = 0.0) -> Tuple[float, np.ndarray]:
     g = np.zeros(5)
     v = lib().orc_mp5_grad(_dp(a), eps, _dp(g))
     return v, g
+
+
+def lim03(f: Sequence[float], dx: float = 1.0) -> float:
+    """LIM03 left-biased interface value at j+1/2 from f_{j-1}, f_j, f_{j+1}
+    on cells of width dx (dx scales the asymptotic-region test)."""
+    a = np.ascontiguousarray(f, np.float64)
+    assert a.size == 3
+    return lib().orc_lim03(_dp(a), dx)
+
+
+def lim03_grad(f: Sequence[float], dx: float = 1.0) -> Tuple[float, np.ndarray]:
+    a = np.ascontiguousarray(f, np.float64)
+    g = np.zeros(3)
+    v = lib().orc_lim03_grad(_dp(a), dx, _dp(g))
+    return v, g
+
+
+def set_lim03_radius(r: float) -> None:
+    """Radius of LIM03's asymptotic region (test hook; default 1)."""
+    lib().orc_set_lim03_radius(float(r))
+
+
+def set_recon(recon: int) -> None:
+    """Reconstruction of the later rhs / run / run_jvp calls: MP5 (the
+    default) or LIM03 (both offered in Sect. 2.2)."""
+    _check(lib().orc_set_recon(int(recon)), "set_recon")
+
+
+class use_recon:
+    """Context manager: `with use_recon(LIM03): ...` restores MP5 on exit."""
+
+    def __init__(self, recon: int):
+        self.recon = recon
+
+    def __enter__(self):
+        set_recon(self.recon)
+        return self
+
+    def __exit__(self, *exc):
+        set_recon(MP5)
+        return False
 
 
 def prim(ndim: int, mhd: bool, gamma: float, u: Sequence[float]) -> Tuple[int, np.ndarray]:

@@ -36,6 +36,22 @@
 //       Ties: minmod / min / max take the first argument, the median takes
 //       f^L when it equals a bound, the global max keeps the lowest
 //       (block, cell) index.
+//   R7  LIM03 (Cada & Torrilhon 2009, offered beside MP5 in Sect. 2.2) is
+//       their compact third-order function with the asymptotic-region
+//       switch: with dm = f_j - f_{j-1}, dp = f_{j+1} - f_j, theta = dm/dp
+//       and eta = (dm^2 + dp^2) / (r dx)^2, the interface value is
+//       f_j + H/2 with
+//         H = (2 dp + dm)/3                       if eta <= 1 (unlimited),
+//         H = phi(theta) dp                       otherwise, where
+//         phi(theta) = max(0, min(phi3, max(-theta/2, min(2 theta, phi3, 1.6)))),
+//         phi3 = (2 + theta)/3,
+//       and H = 0 when eta > 1 and dp = 0 (the limit of both one-sided
+//       branches).  The radius is r = 1; the switch is sharp (the published
+//       smoothing band of width 2 epsilon around eta = 1 is taken with
+//       epsilon -> 0).  Sect. 5.1 reports third order in both norms for
+//       RK3 + LIM03 on the Alfven wave: the limited function alone does not
+//       reach it at smooth extrema, and r = 1 does at the resolutions of
+//       that test (smaller radii only asymptotically).
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -182,6 +198,45 @@ template <class T> static T mp5(T a, T b, T c, T d, T e, double eps) {
   }
   return r;
 }
+
+// ---------------------------------------------------------------------------
+// LIM03 reconstruction (Cada & Torrilhon 2009; reading R7).
+// ---------------------------------------------------------------------------
+static const double LIM03_ALPHA = 0.5;   // slope bound at extrema (theta < 0)
+static const double LIM03_BETA = 2.0;    // TVD bound phi <= 2 theta
+static const double LIM03_GAMMA = 1.6;   // cap below the TVD bound phi <= 2
+static double LIM03_RADIUS = 1.0;        // r of the asymptotic region
+
+// Interface value at j+1/2 from f_{j-1}, f_j, f_{j+1}, biased to the left;
+// dx is the cell width along the reconstruction direction.
+template <class T> static T lim03(T a, T b, T c, double dx) {
+  T dm = b - a;   // f_j - f_{j-1}
+  T dp = c - b;   // f_{j+1} - f_j
+  const double rdx = LIM03_RADIUS * dx;
+  T eta = (dm * dm + dp * dp) / T(rdx * rdx);
+  if (val(eta) <= 1.0) {   // asymptotic region: third-order formula
+    hash_mix(0x45);
+    return b + T(0.5) * ((T(2.0) * dp + dm) / T(3.0));
+  }
+  if (val(dp) == 0.0) {
+    hash_mix(0x40);
+    return b;
+  }
+  T theta = dm / dp;
+  T phi3 = (T(2.0) + theta) / T(3.0);
+  T lo = T(-LIM03_ALPHA) * theta;
+  T tvd = T(LIM03_BETA) * theta;
+  T phi = max2(T(0.0), min2(phi3, max2(lo, min3(tvd, phi3, T(LIM03_GAMMA)))));
+  if (g_hash_on) {
+    uint64_t code = val(phi) == 0.0 ? 0x40 : val(phi) == val(phi3) ? 0x41 : val(phi) == val(lo) ? 0x42
+                  : val(phi) == val(tvd) ? 0x43 : 0x44;
+    hash_mix(code);
+  }
+  return b + T(0.5) * phi * dp;
+}
+
+// Reconstruction selected for the following calls (0: MP5, 1: LIM03).
+static int g_recon = 0;
 
 // ---------------------------------------------------------------------------
 // Physics (Sect. 3 hydro with an ideal-gas energy equation; Sect. 4.1 and 4.3
@@ -472,8 +527,14 @@ static int rhs(const Grid& G, const State<T>& U, const T cmax[3], State<T>& L, d
               const T* p = &Fp[v * len + NG];
               const T* mneg = &Fm[v * len + NG];
               for (int s = -1; s < nd; ++s) {
-                T plus = mp5(p[s - 2], p[s - 1], p[s], p[s + 1], p[s + 2], eps);
-                T minus = mp5(mneg[s + 3], mneg[s + 2], mneg[s + 1], mneg[s], mneg[s - 1], eps);
+                T plus, minus;
+                if (g_recon == 1) {
+                  plus = lim03(p[s - 1], p[s], p[s + 1], q.dx[d]);
+                  minus = lim03(mneg[s + 2], mneg[s + 1], mneg[s], q.dx[d]);
+                } else {
+                  plus = mp5(p[s - 2], p[s - 1], p[s], p[s + 1], p[s + 2], eps);
+                  minus = mp5(mneg[s + 3], mneg[s + 2], mneg[s + 1], mneg[s], mneg[s - 1], eps);
+                }
                 Fh[v * (nd + 1) + (s + 1)] = plus + minus;
               }
             }
@@ -593,6 +654,33 @@ double orc_mp5_grad(const double* f, double eps, double* grad) {
     out = r.v;
   }
   return out;
+}
+
+// LIM03 left-biased interface value from f[0..2] = f_{j-1}..f_{j+1} on
+// cells of width dx.
+double orc_lim03(const double* f, double dx) { return lim03<double>(f[0], f[1], f[2], dx); }
+
+// LIM03 and its three partial derivatives.
+double orc_lim03_grad(const double* f, double dx, double* grad) {
+  double out = 0.0;
+  for (int s = 0; s < 3; ++s) {
+    Dual x[3];
+    for (int t = 0; t < 3; ++t) x[t] = Dual(f[t], t == s ? 1.0 : 0.0);
+    Dual r = lim03<Dual>(x[0], x[1], x[2], dx);
+    grad[s] = r.d;
+    out = r.v;
+  }
+  return out;
+}
+
+// Reconstruction of the following rhs / run / jvp calls: 0 MP5, 1 LIM03.
+// Test hook: radius r of LIM03's asymptotic region (default 1).
+void orc_set_lim03_radius(double r) { LIM03_RADIUS = r; }
+
+int orc_set_recon(int recon) {
+  if (recon != 0 && recon != 1) return ORC_ERR_INVALID;
+  g_recon = recon;
+  return ORC_OK;
 }
 
 // Primitive variables (rho, vx, vy, vz, p, Bx, By, Bz) of one cell.

@@ -52,8 +52,26 @@ def random_mhd(ndim, N, block, seed):
     return inputs.sample_blocks(ndim, True, 5 / 3, n, dx, xlo, nbr, f)
 
 
-@pytest.mark.parametrize("case", ["hydro2d", "hydro2d_rest_density", "mhd2d", "mhd1d"])
+@pytest.mark.parametrize("case", ["hydro2d", "hydro2d_rest_density", "mhd2d", "mhd1d",
+                                  "lim03_hydro2d", "lim03_mhd2d", "lim03_limited_mhd1d"])
 def test_jvp_matches_central_differences(case):
+    # LIM03 cases: the default radius mixes the asymptotic and the limited
+    # branches; a tiny radius sends every reconstruction through the
+    # limited function.
+    if case.startswith("lim03_limited_"):
+        oracle.set_lim03_radius(1e-6)
+        try:
+            with oracle.use_recon(oracle.LIM03):
+                return _jvp_case(case[14:], oracle.SSPRK43)
+        finally:
+            oracle.set_lim03_radius(1.0)
+    if case.startswith("lim03_"):
+        with oracle.use_recon(oracle.LIM03):
+            return _jvp_case(case[6:], oracle.RK3 if case.endswith("hydro2d") else oracle.SSPRK43)
+    return _jvp_case(case, None)
+
+
+def _jvp_case(case, scheme_override):
     # Central differences are exact only where the forward map is smooth
     # ("non-kinked"): a state at rest makes the momentum and energy split
     # fluxes exactly flat, a kink of MP5, so there only density directions
@@ -74,6 +92,8 @@ def test_jvp_matches_central_differences(case):
         bs = random_mhd(1, 32, 8, seed=2)
         tang = inputs.random_tangent(bs, 9)
         scheme, nsteps = oracle.RK3, 4
+    if scheme_override is not None:
+        scheme = scheme_override
     _, cm = oracle.rhs(bs)
     dt = 0.3 / sum(cm[d] / bs.dx[0, d] for d in range(bs.ndim))
     _, du = oracle.run_jvp(bs, tang, scheme, nsteps, dt)
