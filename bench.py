@@ -222,6 +222,8 @@ def main():
                     help="forward steps before the timed adjoint window (3D MHD 256^3)")
     ap.add_argument("--ckpt-also", type=int, default=20,
                     help="also time the adjoint with this checkpoint interval (0: no)")
+    ap.add_argument("--no-lim03", action="store_true",
+                    help="skip the RK3 + LIM03 leg on the same block list")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run one plain device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -273,6 +275,29 @@ def main():
                      "steps": args.per_block_steps}
         ctx.set_exec(amrvac.EXEC_BATCHED)
     ctx.close()
+    del flat, views
+
+    lim03 = None
+    if not args.no_lim03:
+        # the paper's other FD combination (RK3 + LIM03) on the same list
+        print("bench: RK3 + LIM03 on the same block list", file=sys.stderr, flush=True)
+        ctx, flat, views = amrvac.context_for(bs, amrvac.EXEC_BATCHED, recon=amrvac.LIM03)
+        lvar, _ = ctx.autotune(amrvac.RK3, 2)
+        ctx.ssprk_step(amrvac.RK3, args.warmup, cfl=0.4, t=None)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.ssprk_step(amrvac.RK3, args.steps, cfl=0.4, t=None)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ctx.sync()
+        ell = e0.elapsed_time(e1) / 1e3
+        ctx.close()
+        del flat, views
+        lim03 = {"scheme": "RK3 + LIM03", "tile_shape": lvar, "steps": args.steps,
+                 "ms_per_step": 1e3 * ell / args.steps, "cell_updates_per_s": cells * args.steps / ell,
+                 "ssprk54_mp5_over_rk3_lim03_step_time": ms_per_step / (1e3 * ell / args.steps)}
 
     if args.copy_probe > 0:
         # a plain copy kernel of known size: FETCH_SIZE / WRITE_SIZE of this
@@ -320,6 +345,7 @@ def main():
         "adjoint_forward_ratio": adjoint["ratio"] if adjoint else None,
         "adjoint": adjoint,
         "adjoint_2d_euler": adjoint_2d,
+        "lim03": lim03,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

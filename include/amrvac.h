@@ -7,7 +7,8 @@
  *     (Sect. 2.1, eqs. fdcons, reconstruct, timeoperator; no source terms),
  *   Fhat = R_[L](F^+) + R_[R](F^-),  F^+- = (F +- c_max U) / 2
  *     (Sect. 2.2, global Lax-Friedrichs flux-vector splitting),
- *   R = MP5 (Suresh & Huynh 1997, selected in Sect. 2.2),
+ *   R = MP5 (Suresh & Huynh 1997) or LIM03 (Cada & Torrilhon 2009), the two
+ *     reconstructions Sect. 2.2 offers for the FD scheme,
  *   U^(i) = sum_k alpha_ik U^(k) + dt beta_ik L(U^(k))
  *     (Sect. 2.3, Shu-Osher form; RK3, SSPRK(4,3), SSPRK(5,4)),
  *
@@ -55,7 +56,7 @@
 extern "C" {
 #endif
 
-#define AMRVAC_ABI_VERSION 1
+#define AMRVAC_ABI_VERSION 2
 #define AMRVAC_NGHOST 3
 
 typedef enum {
@@ -76,11 +77,25 @@ typedef enum { AMRVAC_RK3 = 0, AMRVAC_SSPRK43 = 1, AMRVAC_SSPRK54 = 2 } amrvac_s
  * launch over the whole block list replayed from a HIP graph. */
 typedef enum { AMRVAC_EXEC_PER_BLOCK = 0, AMRVAC_EXEC_BATCHED = 1 } amrvac_exec;
 
+/* Reconstruction of the split fluxes (Sect. 2.2).
+ *  MP5:   Suresh & Huynh (1997) with alpha = 4 and eps = 0; 5-cell stencils,
+ *         reads all 3 ghost layers.
+ *  LIM03: Cada & Torrilhon (2009) compact third-order function with the
+ *         asymptotic-region switch: from f_{j-1}, f_j, f_{j+1}, with
+ *         dm = f_j - f_{j-1} and dp = f_{j+1} - f_j, the interface value is
+ *         f_j + H/2 with H = (2 dp + dm)/3 where (dm^2 + dp^2) <= (r dx)^2,
+ *         else H = phi(dm/dp) dp, phi(t) = max(0, min(phi3, max(-t/2,
+ *         min(2t, phi3, 1.6)))), phi3 = (2 + t)/3 (H = 0 for dp = 0); radius
+ *         r = 1 (data units per cell width dx along the pencil).  3-cell
+ *         stencils: only the 2 inner ghost layers are read. */
+typedef enum { AMRVAC_MP5 = 0, AMRVAC_LIM03 = 1 } amrvac_recon;
+
 typedef struct {
   int ndim;        /* 1, 2 or 3                                     */
   int physics;     /* amrvac_physics                                */
   double gamma;    /* ratio of specific heats, finite and > 1       */
   int exec;        /* amrvac_exec                                   */
+  int recon;       /* amrvac_recon (added in ABI version 2)         */
 } amrvac_config;
 
 typedef struct {

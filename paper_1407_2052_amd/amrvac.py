@@ -20,7 +20,9 @@ OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_NONPHYSICAL, ERR_UNSUPPORTED = range
 HD, MHD = 0, 1
 RK3, SSPRK43, SSPRK54 = 0, 1, 2
 EXEC_PER_BLOCK, EXEC_BATCHED = 0, 1
+MP5, LIM03 = 0, 1
 NGHOST = 3
+ABI_VERSION = 2
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NONPHYSICAL", 5: "UNSUPPORTED"}
 
 # Entry points declared in include/amrvac.h.
@@ -40,7 +42,7 @@ class AmrvacError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("physics", ctypes.c_int), ("gamma", ctypes.c_double),
-                ("exec", ctypes.c_int)]
+                ("exec", ctypes.c_int), ("recon", ctypes.c_int)]
 
 
 class Block(ctypes.Structure):
@@ -119,9 +121,10 @@ def activation_flags(nbr, want, safety: int) -> Tuple[int, np.ndarray]:
     return n, np.array(list(out), dtype=np.uint8)
 
 
-def validate_blocks(ndim: int, mhd: bool, gamma: float, ptrs, n, dx, xlo, nbr) -> Tuple[int, str]:
+def validate_blocks(ndim: int, mhd: bool, gamma: float, ptrs, n, dx, xlo, nbr,
+                    recon: int = MP5) -> Tuple[int, str]:
     """Host-only validation (no device needed)."""
-    cfg = Config(ndim, MHD if mhd else HD, gamma, EXEC_BATCHED)
+    cfg = Config(ndim, MHD if mhd else HD, gamma, EXEC_BATCHED, recon)
     arr = make_blocks(ptrs, n, dx, xlo, nbr) if len(ptrs) else None
     buf = ctypes.create_string_buffer(256)
     st = lib().amrvac_validate_blocks(ctypes.byref(cfg), arr, len(ptrs), buf, 256)
@@ -131,15 +134,16 @@ def validate_blocks(ndim: int, mhd: bool, gamma: float, ptrs, n, dx, xlo, nbr) -
 class Context:
     """One amrvac context bound to torch's current HIP stream."""
 
-    def __init__(self, ndim: int, mhd: bool, gamma: float, exec: int = EXEC_BATCHED, stream=None):
+    def __init__(self, ndim: int, mhd: bool, gamma: float, exec: int = EXEC_BATCHED, stream=None,
+                 recon: int = MP5):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("amrvac.Context needs a HIP device")
         self._torch = torch
-        self.ndim, self.mhd, self.gamma = ndim, bool(mhd), float(gamma)
+        self.ndim, self.mhd, self.gamma, self.recon = ndim, bool(mhd), float(gamma), int(recon)
         self.nvar = 8 if mhd else 2 + ndim
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        cfg = Config(ndim, MHD if mhd else HD, gamma, exec)
+        cfg = Config(ndim, MHD if mhd else HD, gamma, exec, recon)
         h = ctypes.c_void_p()
         st = lib().amrvac_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
                                  ctypes.byref(h))
@@ -247,9 +251,9 @@ def device_blocks(bs, device="cuda"):
     return flat, views
 
 
-def context_for(bs, exec: int = EXEC_BATCHED, device="cuda"):
+def context_for(bs, exec: int = EXEC_BATCHED, device="cuda", recon: int = MP5):
     """Context + device copy of a BlockSet (returns ctx, flat, views)."""
     flat, views = device_blocks(bs, device)
-    ctx = Context(bs.ndim, bs.mhd, bs.gamma, exec)
+    ctx = Context(bs.ndim, bs.mhd, bs.gamma, exec, recon=recon)
     ctx.set_blocks(views, bs.n, bs.dx, bs.xlo, bs.nbr)
     return ctx, flat, views

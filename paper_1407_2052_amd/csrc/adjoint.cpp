@@ -59,7 +59,7 @@ struct Adj {
   long long* d_targ = nullptr;
   double* d_cpart = nullptr;
   double** d_ptrs = nullptr;
-  unsigned char* d_codes = nullptr;   // MP5 piece codes of every stage state of a segment
+  unsigned char* d_codes = nullptr;   // reconstruction piece codes of every stage state of a segment
   long long code_plane = 0;           // bytes per direction: 8 per cell
   int grid_vjp = 0;
   int grid_emit = 0;
@@ -108,7 +108,7 @@ struct Adj {
   }
 
   // dst = sum lam_t + dt * J_L(state)^T (sum mu_t), including the c_max
-  // term; `codes` are the MP5 pieces of L(state) from the recompute
+  // term; `codes` are the reconstruction pieces of L(state) from the recompute
   void vjp(int state, const unsigned char* codes, const std::vector<std::pair<int, double>>& mu_t,
            const std::vector<std::pair<int, double>>& lam_t, int dst, double dt) {
     StateTable st = state_table(c);
@@ -124,6 +124,7 @@ struct Adj {
     p.in = state;
     p.codes = codes;
     p.code_plane = code_plane;
+    p.recon = c->cfg.recon;
     p.nmu = (int)mu_t.size();
     for (int q = 0; q < p.nmu; ++q) {
       p.mu_src[q] = mu_t[q].first;
@@ -190,7 +191,7 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
   Adj adj;
   adj.c = c;
   adj.V = vjp_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD);
-  const StageVariant* EV = emit_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD);
+  const StageVariant* EV = emit_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD, c->cfg.recon);
   if (!adj.V || !EV) return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: no kernel for this ndim/physics");
   if (EV->tx != adj.V->tx || EV->ty != adj.V->ty || EV->tz != adj.V->tz)
     return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: recompute and adjoint tile shapes differ");

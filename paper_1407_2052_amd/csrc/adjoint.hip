@@ -6,10 +6,12 @@
 // dependence of L on U (everything but the global c_max), as a gather per
 // cell so that no atomics are needed and the result is deterministic.  MP5
 // with eps = 0 is continuous and piecewise linear, so its derivative at U is
-// one of 14 constant weight vectors per reconstruction; the forward
-// recompute of U's stage records which one as a 4-bit code per (interface,
-// variable, sign), and k_vjp reads those codes instead of re-evaluating the
-// split fluxes and the limiter.  Per cell j and direction d:
+// one of 14 constant weight vectors per reconstruction; LIM03 is piecewise
+// linear too (5 pieces; its asymptotic-region switch is a jump on a set of
+// measure zero, where the derivative of the branch taken is used).  The
+// forward recompute of U's stage records the piece as a 4-bit code per
+// (interface, variable, sign), and k_vjp reads those codes instead of
+// re-evaluating the split fluxes and the limiter.  Per cell j and direction d:
 //   lamFhat_{i+1/2} = (mu_{i+1} - mu_i) / dx_d,
 //   lamF+_j = sum over interfaces i = j-2 .. j+2 of lamFhat w+_i,
 //   lamF-_j = sum over interfaces i = j-3 .. j+1 of lamFhat w-_i,
@@ -41,6 +43,18 @@ __constant__ double c_mp5w[14][5] = {
     {16.0 / 3.0, -12.5, 9.5, -4.0 / 3.0, 0.0},
     {0.0, 5.0 / 6.0, -7.0 / 6.0, 4.0 / 3.0, 0.0},
     {4.0 / 3.0, -19.0 / 6.0, 17.0 / 6.0, 0.0, 0.0},
+};
+
+// Weights of the LIM03 inputs for each of its linear pieces, placed on the
+// same five stencil positions (f_{j-2} .. f_{j+2}; LIM03 reads f_{j-1} ..
+// f_{j+1}): 0 f_j; 1 the third-order formula (-f_{j-1} + 5 f_j + 2
+// f_{j+1})/6; 2 phi = -theta/2; 3 phi = 2 theta; 4 phi = 1.6.
+__constant__ double c_lim3w[5][5] = {
+    {0.0, 0.0, 1.0, 0.0, 0.0},
+    {0.0, -1.0 / 6.0, 5.0 / 6.0, 1.0 / 3.0, 0.0},
+    {0.0, 0.25, 0.75, 0.0, 0.0},
+    {0.0, -1.0, 2.0, 0.0, 0.0},
+    {0.0, 0.0, 1.0 - 0.5 * 1.6, 0.5 * 1.6, 0.0},
 };
 
 // Reverse of the primitive recovery: adjoints of the primitives (lv, lp,
@@ -244,7 +258,11 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
   const int tid = threadIdx.x;
   const StateTable& st = P.st;
   const double gamma = P.gamma;
-  for (int q = tid; q < 16 * 5; q += NT) sW[q] = q < 14 * 5 ? c_mp5w[q / 5][q % 5] : 0.0;
+  if (P.recon == 1) {
+    for (int q = tid; q < 16 * 5; q += NT) sW[q] = q < 5 * 5 ? c_lim3w[q / 5][q % 5] : 0.0;
+  } else {
+    for (int q = tid; q < 16 * 5; q += NT) sW[q] = q < 14 * 5 ? c_mp5w[q / 5][q % 5] : 0.0;
+  }
   double cin[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) cin[d] = __longlong_as_double((long long)P.ctl->cm[P.cm_slot][d]);

@@ -83,8 +83,9 @@ struct StageParams {
   double sb;
   int sdst;
   double* const* rhs_out;
-  // Optional (only the code-emitting kernels write it): MP5 linear-piece
-  // codes of L(in), one byte per (direction, cell, variable) for the
+  // Optional (only the code-emitting kernels write it): linear-piece codes
+  // of the reconstructions (MP5 or LIM03) of L(in), one byte per
+  // (direction, cell, variable) for the
   // interface on the cell's lower face, low nibble for the F+ stencil and
   // high nibble for the F- stencil, at
   //   codes + D * code_plane + (block.coff + cell) * 8 + v.
@@ -122,6 +123,7 @@ struct VjpParams {
   int in;
   const unsigned char* codes;
   long long code_plane;
+  int recon;   // reconstruction the codes refer to: 0 MP5, 1 LIM03
   int nmu;
   int mu_src[MAX_TERMS];
   double mu_a[MAX_TERMS];

@@ -291,14 +291,61 @@ __device__ __forceinline__ double mp5_coded(double a, double b, double c, double
 }
 
 // ---------------------------------------------------------------------------
+// LIM03 (Cada & Torrilhon 2009): compact third-order reconstruction with the
+// asymptotic-region switch.
+// ---------------------------------------------------------------------------
+// Radius r of the asymptotic region, in units of the data per cell width.
+constexpr double LIM03_RADIUS = 1.0;
+
+// Interface value at j+1/2 from a = f_{j-1}, b = f_j, c = f_{j+1}; kr =
+// 1 / (r dx)^2 for the cell width dx along the pencil.  With dm = b - a and
+// dp = c - b the value is b + H/2, where
+//   H = (2 dp + dm)/3                      if (dm^2 + dp^2) kr <= 1,
+//   H = phi(dm/dp) dp                      otherwise,
+//   phi(t) = max(0, min(phi3, max(-t/2, min(2t, phi3, 1.6)))), phi3 = (2+t)/3.
+// The limited branch is evaluated without a division: with s = sign(dp)
+// and p3 = (2 dp + dm)/3,
+//   phi(dm/dp) dp = s max(0, min(s p3, max(-s dm/2, min(2 s dm, s p3, 1.6 |dp|)))),
+// which is 0 for dp = 0 (the limit of both one-sided branches).
+// The function is piecewise linear in (a, b, c); with CODES the piece is
+// returned for the adjoint: 0 H = 0; 1 the third-order formula (either
+// branch); 2 -theta/2; 3 2 theta; 4 the 1.6 cap.
+template <bool CODES>
+__device__ __forceinline__ double lim03_eval(double a, double b, double c, double kr, int& code) {
+  const double dm = b - a, dp = c - b;
+  const double p3 = fma(2.0, dp, dm) * (1.0 / 3.0);
+  const double eta = fma(dm, dm, dp * dp) * kr;
+  const double s = dp > 0.0 ? 1.0 : (dp < 0.0 ? -1.0 : 0.0);
+  const double sp3 = s * p3, sdm = s * dm, adp = s * dp;
+  const double q = -0.5 * sdm, t = 2.0 * sdm, g = 1.6 * adp;
+  const double lo = fmin(sp3, fmax(q, fmin(fmin(t, sp3), g)));
+  const bool asym = eta <= 1.0;
+  const double h = asym ? p3 : s * fmax(0.0, lo);
+  if constexpr (CODES) {
+    code = asym ? 1 : (!(lo > 0.0) || s == 0.0) ? 0 : lo == sp3 ? 1 : lo == q ? 2 : lo == t ? 3 : 4;
+  }
+  return fma(0.5, h, b);
+}
+
+__device__ __forceinline__ double lim03(double a, double b, double c, double kr) {
+  int unused;
+  return lim03_eval<false>(a, b, c, kr, unused);
+}
+
+__device__ __forceinline__ double lim03_coded(double a, double b, double c, double kr, int& code) {
+  return lim03_eval<true>(a, b, c, kr, code);
+}
+
+// ---------------------------------------------------------------------------
 // Tile geometry helpers (compile time).
 // ---------------------------------------------------------------------------
-template <int TX, int TY, int TZ>
+template <int TX, int TY, int TZ, int HG = NG>
 struct TileShape {
   static constexpr int T(int d) { return d == 0 ? TX : d == 1 ? TY : TZ; }
   static constexpr int TC = TX * TY * TZ;
-  // extended box along D (halo of 3 on both sides)
-  static constexpr int E(int D, int d) { return T(d) + (d == D ? 2 * NG : 0); }
+  // extended box along D (halo of HG cells on both sides: 3 for MP5, 2 for
+  // LIM03)
+  static constexpr int E(int D, int d) { return T(d) + (d == D ? 2 * HG : 0); }
   static constexpr int NEXT(int D) { return E(D, 0) * E(D, 1) * E(D, 2); }
   static constexpr int SD(int D) { return D == 0 ? 1 : D == 1 ? E(D, 0) : E(D, 0) * E(D, 1); }
   // interface box along D

@@ -44,16 +44,19 @@ namespace amrvac {
 // Fused stage kernel.
 // ---------------------------------------------------------------------------
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
-          bool RUNS = false>
+          bool RUNS = false, bool LIM = false>
 __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
+  static_assert(!(LIM && RUNS), "runs share MP5 curvatures; LIM03 has none");
+  // halo of the extended box: MP5 reaches 3 cells, LIM03 2
+  constexpr int HG = LIM ? 2 : NG;
   using E = Eq<NDIM, MHD>;
-  using S = TileShape<TX, TY, TZ>;
+  using S = TileShape<TX, TY, TZ, HG>;
   constexpr int NV = E::NV;
   constexpr int VPG = (NV + NGRP - 1) / NGRP;
   constexpr int TC = S::TC;
   constexpr int CPT = (TC + NT - 1) / NT;
   // with RUNS the x rows of the extended box get an odd LDS stride
-  constexpr int XP = RUNS ? ((TX + 2 * NG) | 1) : TX + 2 * NG;
+  constexpr int XP = RUNS ? ((TX + 2 * HG) | 1) : TX + 2 * HG;
   constexpr int EXT = cmax_i<cmax_i<XP * TY * TZ, NDIM >= 2 ? S::NEXT(1) : 0>::v,
                              NDIM >= 3 ? S::NEXT(2) : 0>::v;
   constexpr int IFC = cmax_i<cmax_i<S::NIFC(0), NDIM >= 2 ? S::NIFC(1) : 0>::v,
@@ -111,6 +114,8 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
       constexpr int SD = (D == 0) ? 1 : (D == 1) ? E0P : E0P * E1;
       const double c = cin[D];
       const double idx_d = B.inv_dx[D];
+      // LIM03's asymptotic-region scale 1 / (r dx_d)^2
+      const double kr = (idx_d * (1.0 / LIM03_RADIUS)) * (idx_d * (1.0 / LIM03_RADIUS));
 
       static_for<0, NGRP>([&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
@@ -125,8 +130,8 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
             if (d == D) {
-              valid = valid && (a[d] < tend[d] + 2 * NG);
-              cc[d] = tl.o[d] + a[d] - NG;
+              valid = valid && (a[d] < tend[d] + 2 * HG);
+              cc[d] = tl.o[d] + a[d] - HG;
             } else {
               valid = valid && (a[d] < tend[d]);
               cc[d] = tl.o[d] + a[d];
@@ -249,7 +254,8 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
               for (int d = 0; d < 3; ++d) valid = valid && (a[d] < tend[d] + (d == D ? 1 : 0));
               if (valid) {
                 // interface between cells a_D - 1 and a_D (tile coordinates);
-                // stencil cells a_D - 3 .. a_D + 2 are ext indices a_D .. a_D + 5
+                // stencil cells a_D - HG .. a_D + HG - 1 are ext indices
+                // a_D .. a_D + 2 HG - 1
                 int eb = 0;
                 {
                   int ea[3] = {a[0], a[1], a[2]};
@@ -257,7 +263,22 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
                 }
                 const double* fp = &lds[vg * NEXTP + eb];
                 const double* fm = &lds[(VPG + vg) * NEXTP + eb];
-                if constexpr (EMIT) {
+                if constexpr (LIM) {
+                  // F+ from cells a_D - 2 .. a_D, F- mirrored from a_D + 1 .. a_D - 1
+                  if constexpr (EMIT) {
+                    int kp, km;
+                    res[r] = lim03_coded(fp[0], fp[SD], fp[2 * SD], kr, kp) +
+                             lim03_coded(fm[3 * SD], fm[2 * SD], fm[SD], kr, km);
+                    if (a[D] < tend[D]) {
+                      const long long cell =
+                          ((long long)(tl.o[2] + a[2]) * B.n[1] + (tl.o[1] + a[1])) * B.n[0] + (tl.o[0] + a[0]);
+                      P.codes[D * P.code_plane + (B.coff + cell) * 8 + (G * VPG + vg)] =
+                          (unsigned char)(kp | (km << 4));
+                    }
+                  } else {
+                    res[r] = lim03(fp[0], fp[SD], fp[2 * SD], kr) + lim03(fm[3 * SD], fm[2 * SD], fm[SD], kr);
+                  }
+                } else if constexpr (EMIT) {
                   // both linear pieces, stored on the lower face of cell a_D
                   int kp, km;
                   res[r] = mp5_coded(fp[0], fp[SD], fp[2 * SD], fp[3 * SD], fp[4 * SD], kp) +
@@ -504,27 +525,34 @@ __global__ void k_clear_slot(Control* ctl, int slot) {
 // Variant table.
 // ---------------------------------------------------------------------------
 struct StageVariant {
-  int ndim, mhd, tx, ty, tz, nt, ngrp, wpe;
+  int ndim, mhd, rec, tx, ty, tz, nt, ngrp, wpe;
   const void* fn;
   void (*launch)(const StageParams&, int grid, hipStream_t);
   const char* name;
 };
 
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
-          bool RUNS = false>
+          bool RUNS = false, bool LIM = false>
 static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE, EMIT, RUNS>), dim3(grid), dim3(NT), 0, s, p);
+  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE, EMIT, RUNS, LIM>), dim3(grid), dim3(NT), 0,
+                     s, p);
 }
 
-#define AMRVAC_VARIANT(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                       \
-  {ND, M, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE>, \
-   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE>,                                          \
+// rec: the reconstruction (0 MP5, 1 LIM03)
+#define AMRVAC_VARIANT(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                          \
+  {ND, M, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE}
 // the same with interfaces evaluated in runs along each pencil
-#define AMRVAC_VARIANT_R(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                  \
-  {ND, M, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>, \
-   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>,                                          \
+#define AMRVAC_VARIANT_R(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                     \
+  {ND, M, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs"}
+// LIM03 reconstruction
+#define AMRVAC_VARIANT_L(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                            \
+  {ND, M, 1, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, false, true>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, false, true>,                                             \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-lim03"}
 
 // Tile shapes the autotuner chooses from (the first of each (ndim,
 // physics) is the default).  WPE = minimum waves per SIMD requested from
@@ -563,6 +591,22 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 3),
     AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 1),
     AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 2),
+    // LIM03
+    AMRVAC_VARIANT_L(1, false, 128, 1, 1, 128, 1, 1),
+    AMRVAC_VARIANT_L(1, false, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT_L(1, true, 128, 1, 1, 128, 1, 1),
+    AMRVAC_VARIANT_L(1, true, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT_L(2, false, 16, 16, 1, 256, 1, 1),
+    AMRVAC_VARIANT_L(2, false, 32, 8, 1, 256, 1, 1),
+    AMRVAC_VARIANT_L(2, true, 16, 16, 1, 256, 2, 1),
+    AMRVAC_VARIANT_L(2, true, 16, 16, 1, 256, 1, 1),
+    AMRVAC_VARIANT_L(2, true, 32, 8, 1, 256, 2, 1),
+    AMRVAC_VARIANT_L(3, false, 8, 8, 4, 256, 1, 1),
+    AMRVAC_VARIANT_L(3, false, 8, 8, 8, 512, 2, 1),
+    AMRVAC_VARIANT_L(3, true, 8, 8, 4, 256, 2, 1),
+    AMRVAC_VARIANT_L(3, true, 8, 8, 4, 256, 2, 3),
+    AMRVAC_VARIANT_L(3, true, 8, 8, 8, 512, 2, 1),
+    AMRVAC_VARIANT_L(3, true, 8, 8, 4, 256, 4, 4),
 };
 
 const StageVariant* stage_variants(int* count) {
@@ -572,10 +616,14 @@ const StageVariant* stage_variants(int* count) {
 
 // Code-emitting stage kernels (the adjoint's forward recompute), one per
 // (ndim, physics); their tile shapes match the adjoint kernels'.
-#define AMRVAC_EMIT(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                       \
-  {ND, M, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true>, \
-   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true>,                                          \
+#define AMRVAC_EMIT(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                          \
+  {ND, M, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-emit"}
+#define AMRVAC_EMIT_L(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                              \
+  {ND, M, 1, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, false, true>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, false, true>,                                             \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-lim03-emit"}
 
 static const StageVariant g_emit[] = {
     AMRVAC_EMIT(1, false, 64, 1, 1, 64, 1, 1),
@@ -584,11 +632,17 @@ static const StageVariant g_emit[] = {
     AMRVAC_EMIT(2, true, 16, 16, 1, 256, 2, 1),
     AMRVAC_EMIT(3, false, 8, 8, 4, 256, 1, 2),
     AMRVAC_EMIT(3, true, 8, 8, 4, 256, 2, 2),
+    AMRVAC_EMIT_L(1, false, 64, 1, 1, 64, 1, 1),
+    AMRVAC_EMIT_L(1, true, 64, 1, 1, 64, 1, 1),
+    AMRVAC_EMIT_L(2, false, 16, 16, 1, 256, 1, 1),
+    AMRVAC_EMIT_L(2, true, 16, 16, 1, 256, 2, 1),
+    AMRVAC_EMIT_L(3, false, 8, 8, 4, 256, 1, 1),
+    AMRVAC_EMIT_L(3, true, 8, 8, 4, 256, 2, 1),
 };
 
-const StageVariant* emit_variant(int ndim, int mhd) {
+const StageVariant* emit_variant(int ndim, int mhd, int rec) {
   for (const StageVariant& v : g_emit)
-    if (v.ndim == ndim && v.mhd == mhd) return &v;
+    if (v.ndim == ndim && v.mhd == mhd && v.rec == rec) return &v;
   return nullptr;
 }
 

@@ -84,7 +84,7 @@ static int count_variants(const amrvac_ctx* c) {
   int nv = 0, k = 0;
   const StageVariant* v = stage_variants(&nv);
   for (int i = 0; i < nv; ++i)
-    if (v[i].ndim == c->cfg.ndim && v[i].mhd == (c->cfg.physics == AMRVAC_MHD)) ++k;
+    if (v[i].ndim == c->cfg.ndim && v[i].mhd == (c->cfg.physics == AMRVAC_MHD) && v[i].rec == c->cfg.recon) ++k;
   return k;
 }
 
@@ -93,7 +93,7 @@ static const StageVariant* pick_variant(const amrvac_ctx* c, int want) {
   const StageVariant* v = stage_variants(&nv);
   int k = 0;
   for (int i = 0; i < nv; ++i) {
-    if (v[i].ndim == c->cfg.ndim && v[i].mhd == (c->cfg.physics == AMRVAC_MHD)) {
+    if (v[i].ndim == c->cfg.ndim && v[i].mhd == (c->cfg.physics == AMRVAC_MHD) && v[i].rec == c->cfg.recon) {
       if (k == want) return &v[i];
       ++k;
     }
@@ -468,6 +468,7 @@ static bool config_ok(const amrvac_config* cfg) {
   return cfg && cfg->ndim >= 1 && cfg->ndim <= 3 &&
          (cfg->physics == AMRVAC_HD || cfg->physics == AMRVAC_MHD) &&
          (cfg->exec == AMRVAC_EXEC_PER_BLOCK || cfg->exec == AMRVAC_EXEC_BATCHED) &&
+         (cfg->recon == AMRVAC_MP5 || cfg->recon == AMRVAC_LIM03) &&
          std::isfinite(cfg->gamma) && cfg->gamma > 1.0;
 }
 
@@ -526,7 +527,7 @@ amrvac_status amrvac_create(const amrvac_config* cfg, void* hip_stream, amrvac_c
     return AMRVAC_ERR_INVALID;
   }
   if (!config_ok(cfg)) {
-    g_noctx_error = "amrvac_create: invalid config (ndim 1..3, physics HD/MHD, exec, gamma > 1)";
+    g_noctx_error = "amrvac_create: invalid config (ndim 1..3, physics HD/MHD, exec, recon, gamma > 1)";
     return AMRVAC_ERR_INVALID;
   }
   amrvac_ctx* c = new amrvac_ctx();
@@ -556,7 +557,7 @@ amrvac_status amrvac_validate_blocks(const amrvac_config* cfg, const amrvac_bloc
   std::string m;
   amrvac_status st = AMRVAC_OK;
   if (!config_ok(cfg)) {
-    m = "invalid config (ndim 1..3, physics HD/MHD, exec, gamma > 1)";
+    m = "invalid config (ndim 1..3, physics HD/MHD, exec, recon, gamma > 1)";
     st = AMRVAC_ERR_INVALID;
   } else if (!blocks_ok(cfg->ndim, blocks, nblocks, m)) {
     st = AMRVAC_ERR_INVALID;
@@ -666,8 +667,8 @@ amrvac_status amrvac_autotune(amrvac_ctx* c, int scheme, int nsteps, double* ms_
   char key[256];
   hipDeviceProp_t prop;
   HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
-  snprintf(key, sizeof(key), "%s|%d|%d|%zu|%lld|%d", prop.gcnArchName, c->cfg.ndim, c->cfg.physics, c->hb.size(),
-           c->total_cells, scheme);
+  snprintf(key, sizeof(key), "%s|%d|%d|%d|%zu|%lld|%d", prop.gcnArchName, c->cfg.ndim, c->cfg.physics,
+           c->cfg.recon, c->hb.size(), c->total_cells, scheme);
   const char* cache = std::getenv("AMRVAC_TUNE_CACHE");
   if (cache && *cache) {
     std::ifstream in(cache);

@@ -11,14 +11,14 @@
 namespace amrvac {
 
 struct StageVariant {
-  int ndim, mhd, tx, ty, tz, nt, ngrp, wpe;
+  int ndim, mhd, rec, tx, ty, tz, nt, ngrp, wpe;   // rec: 0 MP5, 1 LIM03
   const void* fn;
   void (*launch)(const StageParams&, int grid, hipStream_t);
   const char* name;
 };
 const StageVariant* stage_variants(int* count);
 // Code-emitting stage kernel for (ndim, physics), or nullptr.
-const StageVariant* emit_variant(int ndim, int mhd);
+const StageVariant* emit_variant(int ndim, int mhd, int rec);
 void launch_cmax(int ndim, int mhd, const CmaxParams& p, int grid, hipStream_t s);
 void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo, int clear_hi,
                        hipStream_t s);

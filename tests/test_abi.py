@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_matches_header():
     m = re.search(r"#define AMRVAC_ABI_VERSION (\d+)", open(HEADER).read())
-    assert A.lib().amrvac_abi_version() == int(m.group(1))
+    assert A.lib().amrvac_abi_version() == int(m.group(1)) == A.ABI_VERSION
 
 
 def test_header_constants_match_binding():
@@ -39,7 +39,8 @@ def test_header_constants_match_binding():
     assert re.search(r"#define AMRVAC_NGHOST (\d+)", src).group(1) == str(A.NGHOST)
     for name, val in [("AMRVAC_ERR_INVALID", A.ERR_INVALID), ("AMRVAC_ERR_NONPHYSICAL", A.ERR_NONPHYSICAL),
                       ("AMRVAC_ERR_UNSUPPORTED", A.ERR_UNSUPPORTED), ("AMRVAC_SSPRK54", A.SSPRK54),
-                      ("AMRVAC_EXEC_BATCHED", A.EXEC_BATCHED), ("AMRVAC_MHD", A.MHD)]:
+                      ("AMRVAC_EXEC_BATCHED", A.EXEC_BATCHED), ("AMRVAC_MHD", A.MHD),
+                      ("AMRVAC_MP5", A.MP5), ("AMRVAC_LIM03", A.LIM03)]:
         assert re.search(rf"{name} = (\d+)", src).group(1) == str(val)
 
 
@@ -50,7 +51,8 @@ def test_create_rejects_invalid_config_without_device():
     assert L.amrvac_create(None, None, ctypes.byref(h)) == A.ERR_INVALID
     for cfg in (A.Config(0, A.HD, 1.4, A.EXEC_BATCHED), A.Config(4, A.HD, 1.4, A.EXEC_BATCHED),
                 A.Config(2, 7, 1.4, A.EXEC_BATCHED), A.Config(2, A.HD, 1.0, A.EXEC_BATCHED),
-                A.Config(2, A.HD, float("nan"), A.EXEC_BATCHED), A.Config(2, A.HD, 1.4, 9)):
+                A.Config(2, A.HD, float("nan"), A.EXEC_BATCHED), A.Config(2, A.HD, 1.4, 9),
+                A.Config(2, A.HD, 1.4, A.EXEC_BATCHED, 2), A.Config(2, A.HD, 1.4, A.EXEC_BATCHED, -1)):
         assert L.amrvac_create(ctypes.byref(cfg), None, ctypes.byref(h)) == A.ERR_INVALID
         assert h.value is None
     assert b"invalid config" in L.amrvac_last_error(None)
@@ -114,3 +116,15 @@ def test_product_path_has_no_cpu_fallback():
     for f in os.listdir(os.path.join(ROOT, "paper_1407_2052_amd")):
         if f.endswith(".py"):
             assert "import oracle" not in open(os.path.join(ROOT, "paper_1407_2052_amd", f)).read()
+
+
+def test_config_struct_layout_matches_header():
+    # the binding's Config mirrors amrvac_config field by field
+    import ctypes
+    src = open(HEADER).read()
+    body = re.search(r"typedef struct \{(.*?)\} amrvac_config;", src, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"(int|double)\s+(\w+);", body)
+    assert [f[1] for f in fields] == [f[0] for f in A.Config._fields_]
+    ct = {"int": ctypes.c_int, "double": ctypes.c_double}
+    assert [ct[f[0]] for f in fields] == [f[1] for f in A.Config._fields_]

@@ -1,0 +1,218 @@
+"""GPU parity of the LIM03 reconstruction (Cada & Torrilhon 2009, offered
+beside MP5 in Sect. 2.2) through the C ABI against the oracle: right-hand
+sides element by element, states after RK3 / SSPRK(4,3) (the paper's
+combinations with LIM03) and SSPRK(5,4) steps, bitwise equality of every
+tile shape and of both execution forms, the full-size 3D lists on sampled
+blocks, and the adjoint against the oracle's JVP.  Bars as for MP5."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1407_2052_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1407_2052_amd import amrvac as A  # noqa: E402
+from test_gpu_parity import (CASES, assert_state_parity, compare_rhs, host_blocks,  # noqa: E402
+                             sample_blocks_with_true_ghosts)
+from test_gpu_adjoint import (fixed_dt, interior_dot, periodic_state,  # noqa: E402
+                              random_cotangent)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def lim03_oracle():
+    oracle.set_recon(oracle.LIM03)
+    yield
+    oracle.set_recon(oracle.MP5)
+
+
+def gpu_rhs(bs, exec=A.EXEC_BATCHED):
+    ctx, flat, views = A.context_for(bs, exec, recon=A.LIM03)
+    out, cm = ctx.fd_rhs()
+    res = [o.cpu().numpy() for o in out]
+    ctx.close()
+    return res, cm
+
+
+def gpu_run(bs, scheme, nsteps, cfl=0.4, dt=None, exec=A.EXEC_BATCHED, variant=None):
+    ctx, flat, views = A.context_for(bs, exec, recon=A.LIM03)
+    if variant is not None:
+        ctx.set_variant(variant)
+    t = ctx.ssprk_step(scheme, nsteps, cfl=cfl, dt=dt, t=0.0)
+    out = bs.copy()
+    out.u = host_blocks(views)
+    ctx.close()
+    return out, t
+
+
+RHS_CASES = ["dwave1d", "dwave1d_8blk", "sod1d_fixed", "briowu1d_fixed", "ot2d", "hydro2d", "ragged2d_hd",
+             "ragged2d_mhd", "ragged3d_mhd", "ragged3d_hd", "mhd3d", "uneven3d", "min3_1d_mhd", "min3_3d_mhd",
+             "big2d_single"]
+
+
+@pytest.mark.parametrize("case", RHS_CASES)
+def test_rhs_matches_oracle(case):
+    say(f"[lim03 rhs] {case}")
+    bs = CASES[case]()
+    Lo, cmo = oracle.rhs(bs)
+    Lg, cmg = gpu_rhs(bs)
+    np.testing.assert_allclose(cmg, cmo, rtol=1e-14, atol=0)
+    compare_rhs(bs, Lg, Lo, cmo)
+
+
+STEP_CASES = [
+    ("dwave1d", oracle.RK3, 200),
+    ("dwave1d_8blk", oracle.SSPRK43, 100),
+    ("sod1d_fixed", oracle.RK3, 100),
+    ("briowu1d_fixed", oracle.RK3, 60),
+    ("briowu1d_fixed", oracle.SSPRK43, 40),
+    ("ot2d", oracle.RK3, 100),
+    ("hydro2d", oracle.SSPRK43, 100),
+    ("ragged2d_hd", oracle.RK3, 60),
+    ("ragged2d_mhd", oracle.SSPRK43, 60),
+    ("ragged3d_mhd", oracle.RK3, 30),
+    ("ragged3d_hd", oracle.SSPRK54, 30),
+    ("mhd3d", oracle.RK3, 20),
+    ("uneven3d", oracle.RK3, 10),
+    ("min3_1d_mhd", oracle.SSPRK43, 50),
+    ("min3_3d_mhd", oracle.RK3, 10),
+]
+
+
+@pytest.mark.parametrize("case,scheme,nsteps", STEP_CASES, ids=[f"{c}-s{s}-n{n}" for c, s, n in STEP_CASES])
+def test_steps_match_oracle(case, scheme, nsteps):
+    say(f"[lim03 steps] {case} scheme={scheme} n={nsteps}")
+    bs = CASES[case]()
+    out_o, dts = oracle.run(bs, scheme, nsteps, cfl=0.4)
+    out_g, t = gpu_run(bs, scheme, nsteps, cfl=0.4)
+    assert abs(t - dts.sum()) <= 1e-12 * dts.sum()
+    assert_state_parity(bs, out_g, out_o)
+
+
+@pytest.mark.parametrize("case", ["dwave1d_8blk", "ot2d", "ragged2d_mhd", "uneven3d", "ragged3d_hd",
+                                  "min3_3d_mhd", "min3_1d_mhd"])
+def test_every_tile_shape_and_both_exec_forms_are_bitwise_identical(case):
+    bs = CASES[case]()
+    ctx0, _, _ = A.context_for(bs, recon=A.LIM03)
+    names = ctx0.variants()
+    ctx0.close()
+    assert names and all("lim03" in n for n in names)
+    ref = None
+    for i, name in enumerate(names):
+        say(f"[lim03 variant] {case} {name}")
+        got = gpu_run(bs, oracle.RK3, 3, variant=i)
+        if ref is None:
+            ref = got
+            continue
+        assert got[1] == ref[1], name
+        for x, y in zip(got[0].u, ref[0].u):
+            assert np.array_equal(x, y), name
+    say(f"[lim03 per-block] {case}")
+    pb = gpu_run(bs, oracle.RK3, 3, exec=A.EXEC_PER_BLOCK)
+    assert pb[1] == ref[1]
+    for x, y in zip(pb[0].u, ref[0].u):
+        assert np.array_equal(x, y)
+
+
+def test_lim03_reads_two_ghost_layers_and_mp5_three():
+    # Smooth fixed faces (uneven 3D list): a perturbation of the outermost
+    # ghost layer of every fixed x face leaves LIM03's L bitwise unchanged
+    # (3-cell stencils reach 2 layers) and changes MP5's (5-cell stencils).
+    bs = CASES["uneven3d"]()
+    bad = bs.copy()
+    bad.u = [u.copy() for u in bs.u]
+    touched = 0
+    for b in range(bs.nb):
+        if bs.nbr[b, 0] < 0:
+            bad.u[b][..., 0] *= 1.0 + 1e-3
+            touched += 1
+        if bs.nbr[b, 1] < 0:
+            bad.u[b][..., -1] *= 1.0 - 1e-3
+            touched += 1
+    assert touched > 0
+    L0, _ = gpu_rhs(bs)
+    L1, _ = gpu_rhs(bad)
+    assert all(np.array_equal(x, y) for x, y in zip(L0, L1))
+
+    def mp5_rhs(blocks):
+        ctx, flat, views = A.context_for(blocks, recon=A.MP5)
+        out, _ = ctx.fd_rhs()
+        res = [o.cpu().numpy() for o in out]
+        ctx.close()
+        return res
+    M0, M1 = mp5_rhs(bs), mp5_rhs(bad)
+    assert not all(np.array_equal(x, y) for x, y in zip(M0, M1))
+
+
+@pytest.mark.parametrize("which", ["uneven3d_4096", "mhd3d_256"])
+def test_full_size_3d_rhs_on_sampled_blocks(which):
+    say(f"[lim03 full] {which} rhs, sampled blocks")
+    bs = inputs.uneven_3d() if which == "uneven3d_4096" else inputs.mhd_turbulence_3d()
+    Lg, cmg = gpu_rhs(bs)
+    cmo = oracle.cmax(bs)
+    np.testing.assert_allclose(cmg, cmo, rtol=1e-14)
+    rng = np.random.default_rng(2)
+    idx = np.unique(np.concatenate([rng.choice(bs.nb, 24, replace=False), [0, bs.nb - 1]]))
+    sub = sample_blocks_with_true_ghosts(bs, idx)
+    Lo, _ = oracle.rhs(sub, cmax=cmo)
+    compare_rhs(sub, [Lg[i] for i in idx], Lo, cmo)
+
+
+def test_full_size_uneven3d_rk3_batched_equals_per_block():
+    say("[lim03 full] uneven3d 4096 blocks: 5 RK3 steps batched vs per-block")
+    bs = inputs.uneven_3d()
+    a, ta = gpu_run(bs, oracle.RK3, 5)
+    b, tb = gpu_run(bs, oracle.RK3, 5, exec=A.EXEC_PER_BLOCK)
+    assert ta == tb
+    for x, y in zip(a.u, b.u):
+        assert np.array_equal(x, y)
+    tot0 = [math.fsum(float(bs.interior(i)[v].sum()) for i in range(bs.nb)) for v in range(bs.nvar)]
+    assert all(np.isfinite(t) for t in tot0)
+
+
+ADJ_CASES = [
+    ("hydro1d", 1, False, 64, 16, oracle.RK3, 6, 2),
+    ("mhd1d", 1, True, 64, 32, oracle.SSPRK43, 6, 4),
+    ("hydro2d", 2, False, 32, 16, oracle.RK3, 4, 3),
+    ("mhd2d", 2, True, 32, 16, oracle.SSPRK43, 3, 2),
+    ("mhd2d_54", 2, True, 32, 16, oracle.SSPRK54, 3, 1),
+    ("hydro3d", 3, False, 16, 8, oracle.RK3, 2, 1),
+    ("mhd3d", 3, True, 16, 8, oracle.RK3, 2, 2),
+]
+
+
+@pytest.mark.parametrize("case,ndim,mhd,N,block,scheme,nsteps,ckpt", ADJ_CASES, ids=[c[0] for c in ADJ_CASES])
+def test_adjoint_dot_product_against_oracle_jvp(case, ndim, mhd, N, block, scheme, nsteps, ckpt):
+    say(f"[lim03 adjoint dot] {case}")
+    # the seeds of the MP5 cases: along these runs no two cells come within
+    # rounding of each other as the c_max argmax (a seed whose fields all
+    # have period 1/2 does, and the derivative of c_max then goes to a cell
+    # chosen by rounding, differently in the two implementations)
+    bs = periodic_state(ndim, mhd, N, block, seed=ndim * 10 + mhd)
+    dt = fixed_dt(bs)
+    tang = inputs.random_tangent(bs, 3)
+    lam_n = random_cotangent(bs, 4)
+    _, du = oracle.run_jvp(bs, tang, scheme, nsteps, dt)
+    ctx, flat, views = A.context_for(bs, recon=A.LIM03)
+    before = flat.clone()
+    lam = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in lam_n]
+    ctx.ssprk_adjoint(scheme, dt, nsteps, ckpt, lam)
+    torch.cuda.synchronize()
+    assert torch.equal(before, flat)
+    lam0 = [x.cpu().numpy() for x in lam]
+    ctx.close()
+    lhs = interior_dot(bs, lam0, tang)
+    rhs = interior_dot(bs, lam_n, du)
+    assert abs(lhs - rhs) <= 1e-10 * max(abs(rhs), 1e-300), (lhs, rhs)
