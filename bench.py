@@ -222,6 +222,8 @@ def main():
                     help="forward steps before the timed adjoint window (3D MHD 256^3)")
     ap.add_argument("--ckpt-also", type=int, default=20,
                     help="also time the adjoint with this checkpoint interval (0: no)")
+    ap.add_argument("--adjoint-2d-steps", type=int, default=200,
+                    help="steps of the 2D Euler adjoint leg")
     ap.add_argument("--no-lim03", action="store_true",
                     help="skip the RK3 + LIM03 leg on the same block list")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -314,7 +316,7 @@ def main():
     if not args.no_adjoint:
         adjoint = adjoint_ratio(args.adjoint_steps, args.ckpt, args.adjoint_warm,
                                 args.ckpt_also if args.ckpt_also > 0 else None)
-        adjoint_2d = adjoint_ratio_2d()
+        adjoint_2d = adjoint_ratio_2d(args.adjoint_2d_steps)
 
     flops = FLOPS_PER_CELL_STAGE_MHD3D * cells
     achieved = flops / stage_s / 1e12
