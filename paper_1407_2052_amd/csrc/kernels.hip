@@ -46,7 +46,6 @@ namespace amrvac {
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
           bool RUNS = false, bool LIM = false>
 __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
-  static_assert(!(LIM && RUNS), "runs share MP5 curvatures; LIM03 has none");
   // halo of the extended box: MP5 reaches 3 cells, LIM03 2
   constexpr int HG = LIM ? 2 : NG;
   using E = Eq<NDIM, MHD>;
@@ -159,9 +158,10 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
         // B) interface fluxes for every (variable, interface)
         if constexpr (RUNS) {
           // one item per (variable, pencil, run of up to 5 interfaces): the
-          // run shares curvatures and curvature limiters between its
-          // interfaces and reads every split flux once.  The last run of a
-          // pencil is shifted back to end at the pencil's last interface.
+          // run reads every split flux of its window once and, for MP5,
+          // shares curvatures and curvature limiters between its
+          // interfaces.  The last run of a pencil is shifted back to end at
+          // the pencil's last interface.
           constexpr int NIF = S::T(D) + 1;
           constexpr int RUN = NIF < 5 ? NIF : 5;
           constexpr int NRUN = (NIF + RUN - 1) / RUN;
@@ -189,18 +189,30 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
               if (d != D) valid = valid && (a[d] < tend[d]);
             if (!valid) continue;
             // interface a_D lies between cells a_D - 1 and a_D; its F+
-            // stencil is ext a_D .. a_D + 4, its F- stencil ext a_D + 5 .. a_D + 1
+            // stencil is ext a_D .. a_D + 2 HG - 2, its F- stencil ext
+            // a_D + 2 HG - 1 .. a_D + 1 (mirrored).  fp and fm hold the run's
+            // windows, so that interface kk of the run reconstructs F+ from
+            // fp[kk ..] and F- from fm[RUN - 1 - kk ..].
+            constexpr int W = RUN + 2 * HG - 2;
             const int eb = a[0] + E0P * (a[1] + E1 * a[2]);
-            double fp[RUN + 4], fm[RUN + 4];
+            double fp[W], fm[W];
 #pragma unroll
-            for (int m = 0; m < RUN + 4; ++m) {
+            for (int m = 0; m < W; ++m) {
               fp[m] = lds[vg * NEXTP + eb + m * SD];
-              fm[m] = lds[(VPG + vg) * NEXTP + eb + (RUN + 4 - m) * SD];
+              fm[m] = lds[(VPG + vg) * NEXTP + eb + (W - m) * SD];
             }
             double op[RUN], om[RUN];
             int cp[RUN], cm[RUN];
-            mp5_run<RUN, EMIT>(fp, op, cp);
-            mp5_run<RUN, EMIT>(fm, om, cm);
+            if constexpr (LIM) {
+#pragma unroll
+              for (int kk = 0; kk < RUN; ++kk) {
+                op[kk] = lim03_eval<EMIT>(fp[kk], fp[kk + 1], fp[kk + 2], kr, cp[kk]);
+                om[kk] = lim03_eval<EMIT>(fm[kk], fm[kk + 1], fm[kk + 2], kr, cm[kk]);
+              }
+            } else {
+              mp5_run<RUN, EMIT>(fp, op, cp);
+              mp5_run<RUN, EMIT>(fm, om, cm);
+            }
 #pragma unroll
             for (int kk = 0; kk < RUN; ++kk) res[r][kk] = op[kk] + om[RUN - 1 - kk];
             if constexpr (EMIT) {
@@ -548,6 +560,11 @@ static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
   {ND, M, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>, \
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs"}
+// LIM03 reconstruction in runs along each pencil
+#define AMRVAC_VARIANT_LR(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                         \
+  {ND, M, 1, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true, true>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true, true>,                                             \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-lim03"}
 // LIM03 reconstruction
 #define AMRVAC_VARIANT_L(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                            \
   {ND, M, 1, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, false, true>, \
@@ -591,7 +608,17 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 3),
     AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 1),
     AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 2),
-    // LIM03
+    // LIM03 (pencil runs first: the defaults)
+    AMRVAC_VARIANT_LR(1, true, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT_LR(2, false, 16, 16, 1, 256, 1, 1),
+    AMRVAC_VARIANT_LR(2, true, 16, 16, 1, 256, 1, 1),
+    AMRVAC_VARIANT_LR(2, true, 16, 16, 1, 256, 2, 2),
+    AMRVAC_VARIANT_LR(3, false, 8, 8, 4, 256, 1, 2),
+    AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 1),
+    AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 2),
+    AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 3),
+    AMRVAC_VARIANT_LR(3, true, 8, 8, 8, 512, 2, 1),
+    AMRVAC_VARIANT_LR(3, true, 8, 8, 8, 512, 2, 2),
     AMRVAC_VARIANT_L(1, false, 128, 1, 1, 128, 1, 1),
     AMRVAC_VARIANT_L(1, false, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_L(1, true, 128, 1, 1, 128, 1, 1),
@@ -620,10 +647,10 @@ const StageVariant* stage_variants(int* count) {
   {ND, M, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true>, \
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-emit"}
-#define AMRVAC_EMIT_L(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                              \
-  {ND, M, 1, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, false, true>, \
-   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, false, true>,                                             \
-   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-lim03-emit"}
+#define AMRVAC_EMIT_L(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                             \
+  {ND, M, 1, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true, true>, \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true, true>,                                             \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-lim03-emit"}
 
 static const StageVariant g_emit[] = {
     AMRVAC_EMIT(1, false, 64, 1, 1, 64, 1, 1),
@@ -636,8 +663,8 @@ static const StageVariant g_emit[] = {
     AMRVAC_EMIT_L(1, true, 64, 1, 1, 64, 1, 1),
     AMRVAC_EMIT_L(2, false, 16, 16, 1, 256, 1, 1),
     AMRVAC_EMIT_L(2, true, 16, 16, 1, 256, 2, 1),
-    AMRVAC_EMIT_L(3, false, 8, 8, 4, 256, 1, 1),
-    AMRVAC_EMIT_L(3, true, 8, 8, 4, 256, 2, 1),
+    AMRVAC_EMIT_L(3, false, 8, 8, 4, 256, 1, 2),
+    AMRVAC_EMIT_L(3, true, 8, 8, 4, 256, 2, 2),
 };
 
 const StageVariant* emit_variant(int ndim, int mhd, int rec) {
