@@ -46,6 +46,9 @@ def lib():
         L.orc_set_recon.argtypes = [ctypes.c_int]
         L.orc_prim.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
         L.orc_flux.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp]
+        L.orc_flux_glm.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, dp, dp]
+        L.orc_glm_cr.restype = ctypes.c_double
+        L.orc_set_glm_cr.argtypes = [ctypes.c_double]
         L.orc_fast_speed.restype = ctypes.c_double
         L.orc_fast_speed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp]
         L.orc_scheme_table.argtypes = [ctypes.c_int, dp, dp]
@@ -150,21 +153,38 @@ class use_recon:
 
 
 def prim(ndim: int, mhd: bool, gamma: float, u: Sequence[float]) -> Tuple[int, np.ndarray]:
-    a = np.zeros(8); a[:len(u)] = u
+    a = np.zeros(9); a[:len(u)] = u
     w = np.zeros(8)
     st = lib().orc_prim(ndim, int(mhd), gamma, _dp(a), _dp(w))
     return st, w
 
 
 def flux(ndim: int, mhd: bool, gamma: float, d: int, u: Sequence[float]) -> np.ndarray:
-    a = np.zeros(8); a[:len(u)] = u
-    f = np.zeros(8)
+    a = np.zeros(9); a[:len(u)] = u
+    f = np.zeros(9)
     lib().orc_flux(ndim, int(mhd), gamma, d, _dp(a), _dp(f))
     return f[:len(u)]
 
 
+def flux_glm(ndim: int, gamma: float, d: int, ch: float, u: Sequence[float]) -> np.ndarray:
+    """GLM flux (Sect. 4.2, glm3) of the 9-variable state u along d."""
+    a = np.zeros(9); a[:len(u)] = u
+    f = np.zeros(9)
+    lib().orc_flux_glm(ndim, gamma, d, ch, _dp(a), _dp(f))
+    return f
+
+
+def glm_cr() -> float:
+    return lib().orc_glm_cr()
+
+
+def set_glm_cr(cr: float) -> None:
+    """Test hook: c_r of the GLM psi decay (default 0.18)."""
+    lib().orc_set_glm_cr(float(cr))
+
+
 def fast_speed(ndim: int, mhd: bool, gamma: float, d: int, u: Sequence[float]) -> float:
-    a = np.zeros(8); a[:len(u)] = u
+    a = np.zeros(9); a[:len(u)] = u
     return lib().orc_fast_speed(ndim, int(mhd), gamma, d, _dp(a))
 
 

@@ -52,6 +52,15 @@
 //       RK3 + LIM03 on the Alfven wave: the limited function alone does not
 //       reach it at smooth extrema, and r = 1 does at the resolutions of
 //       that test (smaller radii only asymptotically).
+//   R8  GLM (Sect. 4.2, the glm3 variant: psi as a ninth variable with flux
+//       psi on B_d and c_h^2 B_d on psi, no other psi or div B source terms):
+//       the cleaning speed c_h is the largest per-direction c_max of the
+//       state L is applied to, and every direction then uses c_h as its
+//       c_max, both in the Lax-Friedrichs split (it must bound the +-c_h
+//       waves of the psi-B_d subsystem) and in the time step.  The psi decay
+//       is operator split after each step: psi *= exp(-dt c_h / c_r) with
+//       c_h of the step's initial state and c_r = c_p^2 / c_h = 0.18
+//       (the second of the two ways the section names).
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -98,6 +107,11 @@ static inline Dual sqrt_(Dual a) {
   return Dual(s, s > 0.0 ? a.d / (2.0 * s) : 0.0);
 }
 static inline double sqrt_(double a) { return std::sqrt(a); }
+static inline Dual exp_(Dual a) {
+  const double e = std::exp(a.v);
+  return Dual(e, e * a.d);
+}
+static inline double exp_(double a) { return std::exp(a); }
 static inline double val(double a) { return a; }
 static inline double val(Dual a) { return a.v; }
 static inline bool finite_(double a) { return std::isfinite(a); }
@@ -240,16 +254,18 @@ static int g_recon = 0;
 
 // ---------------------------------------------------------------------------
 // Physics (Sect. 3 hydro with an ideal-gas energy equation; Sect. 4.1 and 4.3
-// ideal MHD with B0 = 0, eta = eta_h = 0, no psi).  Units with magnetic
-// pressure B^2/2.
+// ideal MHD with B0 = 0, eta = eta_h = 0; Sect. 4.2 glm3 for GLM).  Units
+// with magnetic pressure B^2/2.
 // Variable order: hydro (rho, m_1..m_ndim, E); MHD (rho, m_x, m_y, m_z, E,
-// B_x, B_y, B_z).
+// B_x, B_y, B_z); GLM as MHD, then psi.  Phys::mhd is 0 (hydro), 1 (MHD)
+// or 2 (GLM).
 // ---------------------------------------------------------------------------
 struct Phys {
   int ndim;
   int mhd;
   double gamma;
-  int nvar() const { return mhd ? 8 : 2 + ndim; }
+  int nvar() const { return mhd == 2 ? 9 : mhd ? 8 : 2 + ndim; }
+  bool glm() const { return mhd == 2; }
   int ncomp() const { return mhd ? 3 : ndim; }   // momentum components
   int iE() const { return 1 + ncomp(); }
 };
@@ -280,9 +296,10 @@ static bool cons_to_prim(const Phys& ph, const T* u, Prim<T>& w) {
   return ok;
 }
 
-// Physical flux along direction d.
+// Physical flux along direction d (ch: the GLM cleaning speed, unused
+// otherwise).
 template <class T>
-static void phys_flux(const Phys& ph, int d, const T* u, const Prim<T>& w, T* f) {
+static void phys_flux(const Phys& ph, int d, const T* u, const Prim<T>& w, T* f, T ch = T(0.0)) {
   const int nc = ph.ncomp();
   const T vd = w.v[d];
   f[0] = u[1 + d];                                           // m_d
@@ -300,7 +317,14 @@ static void phys_flux(const Phys& ph, int d, const T* u, const Prim<T>& w, T* f)
   f[1 + d] = f[1 + d] + ptot;
   f[4] = vd * (u[4] + ptot) - Bd * bv;
   for (int k = 0; k < 3; ++k) f[5 + k] = vd * w.B[k] - Bd * w.v[k];
+  if (ph.glm()) {
+    f[5 + d] = f[5 + d] + u[8];   // + psi delta_kd (the k = d term above is 0)
+    f[8] = ch * ch * Bd;          // c_h^2 B_d
+  }
 }
+
+// GLM: c_r = c_p^2 / c_h of the psi decay (reading R8).
+static double GLM_CR = 0.18;
 
 // Fast speed along d (sound speed for hydro).
 template <class T>
@@ -396,7 +420,7 @@ enum { ORC_OK = 0, ORC_ERR_INVALID = 1, ORC_ERR_NONPHYSICAL = 4 };
 
 static int build_grid(Grid& G, int ndim, int mhd, double gamma, int nb, const int* n,
                       const double* dx, const int* nbr) {
-  if (ndim < 1 || ndim > 3 || nb <= 0) return ORC_ERR_INVALID;
+  if (ndim < 1 || ndim > 3 || nb <= 0 || mhd < 0 || mhd > 2) return ORC_ERR_INVALID;
   G.ph.ndim = ndim; G.ph.mhd = mhd; G.ph.gamma = gamma;
   G.g.resize(nb);
   for (int b = 0; b < nb; ++b) {
@@ -464,7 +488,7 @@ static int global_cmax(const Grid& G, const State<T>& U, T cmax[3]) {
     for (int k = 0; k < q.n[2]; ++k)
       for (int j = 0; j < q.n[1]; ++j)
         for (int i = 0; i < q.n[0]; ++i) {
-          T u[8];
+          T u[9];
           size_t c = q.idx(i, j, k);
           for (int v = 0; v < nv; ++v) u[v] = U[b][v * q.ncell + c];
           Prim<T> w;
@@ -477,6 +501,12 @@ static int global_cmax(const Grid& G, const State<T>& U, T cmax[3]) {
         }
   }
   for (int d = 0; d < G.ph.ndim; ++d) hash_mix(arg[d] * 3 + d);
+  if (G.ph.glm()) {   // reading R8: c_h = max_d c_max,d for every direction
+    T ch = cmax[0];
+    for (int d = 1; d < G.ph.ndim; ++d)
+      if (val(cmax[d]) > val(ch)) ch = cmax[d];
+    for (int d = 0; d < G.ph.ndim; ++d) cmax[d] = ch;
+  }
   return ORC_OK;
 }
 
@@ -509,14 +539,14 @@ static int rhs(const Grid& G, const State<T>& U, const T cmax[3], State<T>& L, d
               int c3[3] = {i, j, k};
               c3[d] = m;
               size_t c = q.idx(c3[0], c3[1], c3[2]);
-              T u[8], f[8];
+              T u[9], f[9];
               for (int v = 0; v < nv; ++v) u[v] = U[b][v * q.ncell + c];
               Prim<T> w;
               if (!cons_to_prim(G.ph, u, w)) {
 #pragma omp atomic write
                 status = ORC_ERR_NONPHYSICAL;
               }
-              phys_flux(G.ph, d, u, w, f);
+              phys_flux(G.ph, d, u, w, f, cmax[d]);
               for (int v = 0; v < nv; ++v) {
                 Fp[v * len + (m + NG)] = T(0.5) * (f[v] + cmax[d] * u[v]);
                 Fm[v * len + (m + NG)] = T(0.5) * (f[v] - cmax[d] * u[v]);
@@ -583,6 +613,7 @@ static int ssprk_step(const Grid& G, const Scheme& S, State<T>& U, double cfl, d
   std::vector<State<T>> Us(S.s + 1), Ls(S.s);
   Us[0] = U;
   double dt = dt_in;
+  T ch0(0.0);   // GLM cleaning speed of U^n
   for (int i = 1; i <= S.s; ++i) {
     // L(U(i-1)) is the only new right-hand side this stage needs.
     int k = i - 1;
@@ -590,6 +621,7 @@ static int ssprk_step(const Grid& G, const Scheme& S, State<T>& U, double cfl, d
     T cm[3];
     int st = global_cmax(G, Us[k], cm);
     if (st) return st;
+    if (k == 0) ch0 = cm[0];
     if (k == 0 && dt_in < 0.0) {
       double cv[3] = {val(cm[0]), val(cm[1]), val(cm[2])};
       dt = dt_rule(G, cv, cfl);
@@ -618,6 +650,20 @@ static int ssprk_step(const Grid& G, const Scheme& S, State<T>& U, double cfl, d
     }
   }
   U = Us[S.s];
+  if (G.ph.glm()) {
+    // operator-split decay of psi (reading R8), interior cells of active blocks
+    T decay = exp_(T(-dt / GLM_CR) * ch0);
+    for (size_t b = 0; b < G.g.size(); ++b) {
+      if (!G.is_active(b)) continue;
+      const Geom& q = G.g[b];
+      for (int kk = 0; kk < q.n[2]; ++kk)
+        for (int j = 0; j < q.n[1]; ++j)
+          for (int ii = 0; ii < q.n[0]; ++ii) {
+            size_t o = 8 * q.ncell + q.idx(ii, j, kk);
+            U[b][o] = U[b][o] * decay;
+          }
+    }
+  }
   if (dt_used) *dt_used = dt;
   return ORC_OK;
 }
@@ -700,6 +746,19 @@ int orc_flux(int ndim, int mhd, double gamma, int d, const double* u, double* f)
   phys_flux(ph, d, u, w, f);
   return ok ? ORC_OK : ORC_ERR_NONPHYSICAL;
 }
+
+// GLM flux (reading R8) along d with cleaning speed ch; u and f hold 9 values.
+int orc_flux_glm(int ndim, double gamma, int d, double ch, const double* u, double* f) {
+  Phys ph; ph.ndim = ndim; ph.mhd = 2; ph.gamma = gamma;
+  Prim<double> w;
+  bool ok = cons_to_prim(ph, u, w);
+  phys_flux(ph, d, u, w, f, ch);
+  return ok ? ORC_OK : ORC_ERR_NONPHYSICAL;
+}
+
+// c_r of the GLM psi decay (reading R8), and a test hook to change it.
+double orc_glm_cr(void) { return GLM_CR; }
+void orc_set_glm_cr(double cr) { GLM_CR = cr; }
 
 double orc_fast_speed(int ndim, int mhd, double gamma, int d, const double* u) {
   Phys ph; ph.ndim = ndim; ph.mhd = mhd; ph.gamma = gamma;

@@ -35,8 +35,9 @@ import numpy as np
 NG = 3
 
 
-def nvar_of(ndim: int, mhd: bool) -> int:
-    return 8 if mhd else 2 + ndim
+def nvar_of(ndim: int, mhd) -> int:
+    """mhd: False/0 hydro, True/1 ideal MHD, 2 GLM-MHD (MHD + psi)."""
+    return 9 if mhd == 2 else 8 if mhd else 2 + ndim
 
 
 @dataclasses.dataclass
@@ -82,7 +83,7 @@ class BlockSet:
 # Conserved state from primitive fields (definition of the initial data:
 # m = rho v, E = p/(gamma-1) + rho v^2/2 [+ B^2/2], Sect. 3.2 and eq. frace).
 # ---------------------------------------------------------------------------
-PrimFields = Dict[str, np.ndarray]   # keys rho, vx, vy, vz, p, Bx, By, Bz
+PrimFields = Dict[str, np.ndarray]   # keys rho, vx, vy, vz, p, Bx, By, Bz[, psi]
 
 
 def conserved_from_prims(ndim: int, mhd: bool, gamma: float, w: PrimFields) -> np.ndarray:
@@ -101,6 +102,8 @@ def conserved_from_prims(ndim: int, mhd: bool, gamma: float, w: PrimFields) -> n
         E = E + 0.5 * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2])
         out.append(E)
         out.extend(B)
+        if mhd == 2:   # GLM: the divergence-cleaning potential psi
+            out.append(w.get("psi", 0.0 * rho))
     else:
         out.append(E)
     return np.ascontiguousarray(np.stack([np.broadcast_to(x, rho.shape) for x in out]))
@@ -358,7 +361,7 @@ def mhd_turbulence_3d(N: int = 256, block: int = 16, seed: int = 5, gamma: float
 def circular_alfven(ndim: int, N: int, block: Optional[int] = None, amp: float = 0.1,
                     rho0: float = 1.0, p0: float = 0.1, gamma: float = 5.0 / 3.0,
                     kvec: Tuple[int, int, int] = (1, 0, 0), t: float = 0.0,
-                    direction: int = +1) -> BlockSet:
+                    direction: int = +1, glm: bool = False) -> BlockSet:
     """Circularly polarised Alfven wave (Sect. 4.5.1, eq. alfven) on the
     periodic unit box, wave vector 2 pi kvec, v_A = 1 along k, amplitude
     `amp`, propagating along +k (direction=+1) or -k."""
@@ -388,7 +391,19 @@ def circular_alfven(ndim: int, N: int, block: Optional[int] = None, amp: float =
         one = np.ones(shape)
         return {"rho": rho0 * one, "p": p0 * one, "vx": v[0] * one, "vy": v[1] * one,
                 "vz": v[2] * one, "Bx": B[0] * one, "By": B[1] * one, "Bz": B[2] * one}
-    return sample_blocks(ndim, True, gamma, n, dx, xlo, nbr, f)
+    return sample_blocks(ndim, 2 if glm else True, gamma, n, dx, xlo, nbr, f)
+
+
+def as_glm(bs: BlockSet, psi: float = 0.0) -> BlockSet:
+    """The MHD block list `bs` as a GLM-MHD list (Sect. 4.2): the same eight
+    variables and a ninth, psi, set to `psi` everywhere (ghosts included)."""
+    if bs.mhd is not True and bs.mhd != 1:
+        raise ValueError("as_glm needs an MHD block list")
+    out = bs.copy()
+    out.mhd = 2
+    out.u = [np.ascontiguousarray(np.concatenate([u, np.full((1,) + u.shape[1:], psi)], axis=0))
+             for u in bs.u]
+    return out
 
 
 def riemann_1d(left: Dict[str, float], right: Dict[str, float], N: int, mhd: bool,
