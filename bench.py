@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -224,6 +226,8 @@ def main():
                     help="also time the adjoint with this checkpoint interval (0: no)")
     ap.add_argument("--adjoint-2d-steps", type=int, default=200,
                     help="steps of the 2D Euler adjoint leg")
+    ap.add_argument("--no-glm", action="store_true",
+                    help="skip the GLM-MHD leg on the same block list")
     ap.add_argument("--no-lim03", action="store_true",
                     help="skip the RK3 + LIM03 leg on the same block list")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -301,6 +305,33 @@ def main():
                  "ms_per_step": 1e3 * ell / args.steps, "cell_updates_per_s": cells * args.steps / ell,
                  "ssprk54_mp5_over_rk3_lim03_step_time": ms_per_step / (1e3 * ell / args.steps)}
 
+    glm = None
+    if not args.no_glm:
+        # GLM-MHD (psi as a ninth variable) on the same list, psi = 0.01 sin(...)
+        print("bench: GLM-MHD SSPRK(5,4) + MP5 on the same block list", file=sys.stderr, flush=True)
+        gbs = inputs.as_glm(bs)
+        for b in range(gbs.nb):
+            P = gbs.u[b].shape[1:]
+            x = gbs.xlo[b, 0] + (np.arange(P[2]) - 2.5) * gbs.dx[b, 0]
+            gbs.u[b][8] = 0.01 * np.sin(2 * np.pi * x)[None, None, :]
+        ctx, flat, views = amrvac.context_for(gbs, amrvac.EXEC_BATCHED)
+        gvar, _ = ctx.autotune(amrvac.SSPRK54, 2)
+        ctx.ssprk_step(amrvac.SSPRK54, args.warmup, cfl=0.4, t=None)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.ssprk_step(amrvac.SSPRK54, args.steps, cfl=0.4, t=None)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ctx.sync()
+        elg = e0.elapsed_time(e1) / 1e3
+        ctx.close()
+        del flat, views, gbs
+        glm = {"scheme": "SSPRK(5,4) + MP5, GLM-MHD (9 variables)", "tile_shape": gvar, "steps": args.steps,
+               "ms_per_step": 1e3 * elg / args.steps, "cell_updates_per_s": cells * args.steps / elg,
+               "step_time_over_mhd": (1e3 * elg / args.steps) / ms_per_step}
+
     if args.copy_probe > 0:
         # a plain copy kernel of known size: FETCH_SIZE / WRITE_SIZE of this
         # dispatch calibrate the counters against bytes really moved
@@ -348,6 +379,7 @@ def main():
         "adjoint": adjoint,
         "adjoint_2d_euler": adjoint_2d,
         "lim03": lim03,
+        "glm": glm,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

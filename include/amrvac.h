@@ -12,8 +12,9 @@
  *   U^(i) = sum_k alpha_ik U^(k) + dt beta_ik L(U^(k))
  *     (Sect. 2.3, Shu-Osher form; RK3, SSPRK(4,3), SSPRK(5,4)),
  *
- * for ideal hydrodynamics (Sect. 3, ideal-gas energy equation) and ideal MHD
- * (Sects. 4.1 and 4.3 with B0 = 0, eta = eta_h = 0).
+ * for ideal hydrodynamics (Sect. 3, ideal-gas energy equation), ideal MHD
+ * (Sects. 4.1 and 4.3 with B0 = 0, eta = eta_h = 0) and GLM-MHD (Sect. 4.2,
+ * the glm3 variant).
  *
  * Conventions shared by every call
  * --------------------------------
@@ -23,8 +24,9 @@
  *    both sides of every active direction: nvar arrays of
  *    P0 * P1 * P2 doubles (P_d = n[d] + 6 if d < ndim, else 1), variable
  *    major, x fastest.  Variables: hydro (rho, m_1..m_ndim, E), nvar =
- *    2 + ndim; MHD (rho, m_x, m_y, m_z, E, B_x, B_y, B_z), nvar = 8.  Values
- *    are point values at cell centres (Sect. 2.1).
+ *    2 + ndim; MHD (rho, m_x, m_y, m_z, E, B_x, B_y, B_z), nvar = 8; GLM as
+ *    MHD followed by psi, nvar = 9.  Values are point values at cell centres
+ *    (Sect. 2.1).
  *  * Faces: nbr[2d] (low side) and nbr[2d+1] (high side) of direction d are
  *    either the index of the neighbouring block in the list (its interior
  *    supplies the 3 ghost layers; periodic wrap is expressed by the caller
@@ -68,7 +70,16 @@ typedef enum {
   AMRVAC_ERR_UNSUPPORTED = 5   /* valid request this build does not implement  */
 } amrvac_status;
 
-typedef enum { AMRVAC_HD = 0, AMRVAC_MHD = 1 } amrvac_physics;
+/* GLM (Sect. 4.2, glm3): psi is added to the flux of B_d and c_h^2 B_d is
+ * the flux of psi along d; no other psi or div B terms.  The cleaning speed
+ * c_h is the largest per-direction c_max of the state a right-hand side is
+ * evaluated on, and every direction then uses c_h in place of its c_max (in
+ * the Lax-Friedrichs split, the time step, and the cmax_out of
+ * amrvac_fd_rhs).  After each time step psi is multiplied by
+ * exp(-dt c_h / c_r), c_h of the step's initial state, c_r = c_p^2 / c_h =
+ * 0.18 (operator split).  amrvac_ssprk_adjoint does not support GLM
+ * (AMRVAC_ERR_UNSUPPORTED). */
+typedef enum { AMRVAC_HD = 0, AMRVAC_MHD = 1, AMRVAC_GLM = 2 } amrvac_physics;
 
 /* Sect. 2.3: RK3 (Gottlieb & Shu 1998), SSPRK(4,3) and SSPRK(5,4) tables. */
 typedef enum { AMRVAC_RK3 = 0, AMRVAC_SSPRK43 = 1, AMRVAC_SSPRK54 = 2 } amrvac_scheme;

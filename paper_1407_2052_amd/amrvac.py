@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libamrvac.so")
 
 OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_NONPHYSICAL, ERR_UNSUPPORTED = range(6)
-HD, MHD = 0, 1
+HD, MHD, GLM = 0, 1, 2
 RK3, SSPRK43, SSPRK54 = 0, 1, 2
 EXEC_PER_BLOCK, EXEC_BATCHED = 0, 1
 MP5, LIM03 = 0, 1
@@ -32,6 +32,12 @@ SYMBOLS = ["amrvac_abi_version", "amrvac_create", "amrvac_set_blocks", "amrvac_v
            "amrvac_autotune", "amrvac_fd_rhs", "amrvac_ssprk_step", "amrvac_ssprk_adjoint",
            "amrvac_activation_flags", "amrvac_set_active",
            "amrvac_sync", "amrvac_last_error", "amrvac_destroy"]
+
+
+def physics_of(mhd) -> int:
+    """Physics code from a BlockSet's `mhd` field: False/0 hydro, True/1
+    MHD, 2 GLM-MHD."""
+    return GLM if (mhd == 2) else (MHD if mhd else HD)
 
 
 class AmrvacError(RuntimeError):
@@ -124,7 +130,7 @@ def activation_flags(nbr, want, safety: int) -> Tuple[int, np.ndarray]:
 def validate_blocks(ndim: int, mhd: bool, gamma: float, ptrs, n, dx, xlo, nbr,
                     recon: int = MP5) -> Tuple[int, str]:
     """Host-only validation (no device needed)."""
-    cfg = Config(ndim, MHD if mhd else HD, gamma, EXEC_BATCHED, recon)
+    cfg = Config(ndim, physics_of(mhd), gamma, EXEC_BATCHED, recon)
     arr = make_blocks(ptrs, n, dx, xlo, nbr) if len(ptrs) else None
     buf = ctypes.create_string_buffer(256)
     st = lib().amrvac_validate_blocks(ctypes.byref(cfg), arr, len(ptrs), buf, 256)
@@ -141,9 +147,10 @@ class Context:
             raise RuntimeError("amrvac.Context needs a HIP device")
         self._torch = torch
         self.ndim, self.mhd, self.gamma, self.recon = ndim, bool(mhd), float(gamma), int(recon)
-        self.nvar = 8 if mhd else 2 + ndim
+        self.physics = physics_of(mhd)
+        self.nvar = {HD: 2 + ndim, MHD: 8, GLM: 9}[self.physics]
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        cfg = Config(ndim, MHD if mhd else HD, gamma, exec, recon)
+        cfg = Config(ndim, self.physics, gamma, exec, recon)
         h = ctypes.c_void_p()
         st = lib().amrvac_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
                                  ctypes.byref(h))

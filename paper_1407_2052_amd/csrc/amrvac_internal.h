@@ -42,7 +42,12 @@ struct Control {
   // c_max maximiser per direction ((block << 32) | interior linear index),
   // filled by the adjoint's argmax reduction
   long long arg[3];
+  // GLM: factor exp(-dt c_h / c_r) of this step's psi decay
+  double psi_decay;
 };
+
+// GLM: c_r = c_p^2 / c_h of the operator-split psi decay.
+constexpr double GLM_CR = 0.18;
 
 // Buffers: id 0 = caller's padded u; id k >= 1 = scratch slot k-1 with the
 // interior-only layout, at scr + (k-1)*slot_stride + block.off.
@@ -83,6 +88,8 @@ struct StageParams {
   double sb;
   int sdst;
   double* const* rhs_out;
+  // GLM: multiply psi by the step's decay factor (last stage of a step)
+  int decay_psi;
   // Optional (only the code-emitting kernels write it): linear-piece codes
   // of the reconstructions (MP5 or LIM03) of L(in), one byte per
   // (direction, cell, variable) for the

@@ -11,9 +11,12 @@
 
 namespace amrvac {
 
-template <int NDIM, bool MHD>
+// Variables: hydro (rho, m_1..m_NDIM, E); MHD (rho, m_x, m_y, m_z, E, B_x,
+// B_y, B_z); GLM as MHD, then psi.
+template <int NDIM, bool MHD, bool GLM = false>
 struct Eq {
-  static constexpr int NV = MHD ? 8 : 2 + NDIM;
+  static_assert(MHD || !GLM, "GLM extends MHD");
+  static constexpr int NV = GLM ? 9 : MHD ? 8 : 2 + NDIM;
   static constexpr int NC = MHD ? 3 : NDIM;
   static constexpr int IE = 1 + NC;
 };

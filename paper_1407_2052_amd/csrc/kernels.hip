@@ -44,11 +44,11 @@ namespace amrvac {
 // Fused stage kernel.
 // ---------------------------------------------------------------------------
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
-          bool RUNS = false, bool LIM = false>
+          bool RUNS = false, bool LIM = false, bool GLM = false>
 __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
   // halo of the extended box: MP5 reaches 3 cells, LIM03 2
   constexpr int HG = LIM ? 2 : NG;
-  using E = Eq<NDIM, MHD>;
+  using E = Eq<NDIM, MHD, GLM>;
   using S = TileShape<TX, TY, TZ, HG>;
   constexpr int NV = E::NV;
   constexpr int VPG = (NV + NGRP - 1) / NGRP;
@@ -72,7 +72,16 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
   double cin[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) cin[d] = __longlong_as_double((long long)ctl->cm[P.cm_in][d]);
+  if constexpr (GLM) {
+    // the cleaning speed c_h = max_d c_max,d serves every direction
+    double ch = cin[0];
+#pragma unroll
+    for (int d = 1; d < NDIM; ++d) ch = fmax(ch, cin[d]);
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) cin[d] = ch;
+  }
   const double dt = (P.mode == 0) ? ctl->dt : 0.0;
+  const double psi_decay = (GLM && P.decay_psi) ? ctl->psi_decay : 1.0;
   const double dtb = dt * P.b;
   const double dtsb = dt * P.sb;
   if (P.cm_reset >= 0 && blockIdx.x == 0 && tid == 0) {
@@ -143,6 +152,10 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
             ok_all = prim<NDIM, MHD>(u, gamma, w) && ok_all;
             double F[NV];
             phys_flux<NDIM, MHD, D>(u, w, F);
+            if constexpr (GLM) {
+              F[5 + D] += u[8];             // psi on the flux of B_D
+              F[8] = (c * c) * u[5 + D];    // c_h^2 B_D
+            }
             const int el = a[0] + E0P * (a[1] + E1 * a[2]);
 #pragma unroll
             for (int vg = 0; vg < VPG; ++vg) {
@@ -375,6 +388,9 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
             if (q < P.nsrc) acc = fma(P.a[q], sp[q][v * vs[q]], acc);
           un[v] = fma(dtb, L[r][v], acc);
         }
+        if constexpr (GLM) {
+          if (P.decay_psi) un[8] = un[8] * psi_decay;   // operator-split decay of psi
+        }
       }
       if (P.sdst >= 0) {
         long long vs[MAX_SRC];
@@ -479,14 +495,20 @@ __global__ void __launch_bounds__(256) k_cmax(CmaxParams P) {
 
 // dt from c_max (or the fixed step), t += dt, and clearing of the c_max
 // slots the coming stages accumulate into.  One thread.
-__global__ void k_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo, int clear_hi) {
+__global__ void k_step_begin(Control* ctl, const double* dxtab, int ndim, int glm, int clear_lo,
+                             int clear_hi) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double cm[3];
+  for (int d = 0; d < 3; ++d) cm[d] = __longlong_as_double((long long)ctl->cm[0][d]);
+  double ch = cm[0];
+  if (glm) {   // every direction moves at the cleaning speed c_h = max_d c_max,d
+    for (int d = 1; d < ndim; ++d) ch = fmax(ch, cm[d]);
+    for (int d = 0; d < ndim; ++d) cm[d] = ch;
+  }
   double dt;
   if (ctl->dt_fixed > 0.0) {
     dt = ctl->dt_fixed;
   } else {
-    double cm[3];
-    for (int d = 0; d < 3; ++d) cm[d] = __longlong_as_double((long long)ctl->cm[0][d]);
     double worst = 0.0;
     for (int q = 0; q < ctl->ndx; ++q) {
       double s = 0.0;
@@ -496,6 +518,7 @@ __global__ void k_step_begin(Control* ctl, const double* dxtab, int ndim, int cl
     dt = ctl->cfl / worst;
   }
   ctl->dt = dt;
+  ctl->psi_decay = glm ? exp((-dt / GLM_CR) * ch) : 1.0;
   ctl->t += dt;
   for (int s = clear_lo; s <= clear_hi; ++s)
     for (int d = 0; d < 3; ++d) ctl->cm[s][d] = 0ull;
@@ -544,10 +567,10 @@ struct StageVariant {
 };
 
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
-          bool RUNS = false, bool LIM = false>
+          bool RUNS = false, bool LIM = false, bool GLM = false>
 static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE, EMIT, RUNS, LIM>), dim3(grid), dim3(NT), 0,
-                     s, p);
+  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE, EMIT, RUNS, LIM, GLM>), dim3(grid), dim3(NT),
+                     0, s, p);
 }
 
 // rec: the reconstruction (0 MP5, 1 LIM03)
@@ -560,6 +583,12 @@ static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
   {ND, M, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>, \
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs"}
+// GLM-MHD (physics code 2), MP5 or LIM03 (REC), in runs along each pencil
+#define AMRVAC_VARIANT_G(ND, REC, TX, TY, TZ, NT, NGRP, WPE)                                                    \
+  {ND, 2, REC, TX, TY, TZ, NT, NGRP, WPE,                                                                       \
+   (const void*)&k_stage<ND, true, TX, TY, TZ, NT, NGRP, WPE, false, true, (REC == 1), true>,                  \
+   &launch_stage<ND, true, TX, TY, TZ, NT, NGRP, WPE, false, true, (REC == 1), true>,                          \
+   #ND "d-glm-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-rec" #REC}
 // LIM03 reconstruction in runs along each pencil
 #define AMRVAC_VARIANT_LR(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                         \
   {ND, M, 1, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true, true>, \
@@ -634,6 +663,17 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT_L(3, true, 8, 8, 4, 256, 2, 3),
     AMRVAC_VARIANT_L(3, true, 8, 8, 8, 512, 2, 1),
     AMRVAC_VARIANT_L(3, true, 8, 8, 4, 256, 4, 4),
+    // GLM-MHD
+    AMRVAC_VARIANT_G(1, 0, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT_G(2, 0, 16, 16, 1, 256, 2, 2),
+    AMRVAC_VARIANT_G(2, 0, 16, 16, 1, 256, 1, 1),
+    AMRVAC_VARIANT_G(3, 0, 8, 8, 4, 256, 2, 3),
+    AMRVAC_VARIANT_G(3, 0, 8, 8, 4, 256, 2, 1),
+    AMRVAC_VARIANT_G(3, 0, 8, 8, 4, 256, 3, 3),
+    AMRVAC_VARIANT_G(1, 1, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT_G(2, 1, 16, 16, 1, 256, 2, 2),
+    AMRVAC_VARIANT_G(3, 1, 8, 8, 4, 256, 2, 1),
+    AMRVAC_VARIANT_G(3, 1, 8, 8, 4, 256, 2, 3),
 };
 
 const StageVariant* stage_variants(int* count) {
@@ -684,9 +724,9 @@ void launch_cmax(int ndim, int mhd, const CmaxParams& p, int grid, hipStream_t s
   if (ndim == 3) mhd ? launch_cmax_t<3, true>(p, grid, s) : launch_cmax_t<3, false>(p, grid, s);
 }
 
-void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo, int clear_hi,
+void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int glm, int clear_lo, int clear_hi,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, s, ctl, dxtab, ndim, clear_lo, clear_hi);
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, s, ctl, dxtab, ndim, glm, clear_lo, clear_hi);
 }
 
 void launch_set_control(Control* ctl, double dt_fixed, double cfl, double t, hipStream_t s) {

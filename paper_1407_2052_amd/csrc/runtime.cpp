@@ -84,7 +84,7 @@ static int count_variants(const amrvac_ctx* c) {
   int nv = 0, k = 0;
   const StageVariant* v = stage_variants(&nv);
   for (int i = 0; i < nv; ++i)
-    if (v[i].ndim == c->cfg.ndim && v[i].mhd == (c->cfg.physics == AMRVAC_MHD) && v[i].rec == c->cfg.recon) ++k;
+    if (v[i].ndim == c->cfg.ndim && v[i].mhd == c->cfg.physics && v[i].rec == c->cfg.recon) ++k;
   return k;
 }
 
@@ -93,7 +93,7 @@ static const StageVariant* pick_variant(const amrvac_ctx* c, int want) {
   const StageVariant* v = stage_variants(&nv);
   int k = 0;
   for (int i = 0; i < nv; ++i) {
-    if (v[i].ndim == c->cfg.ndim && v[i].mhd == (c->cfg.physics == AMRVAC_MHD) && v[i].rec == c->cfg.recon) {
+    if (v[i].ndim == c->cfg.ndim && v[i].mhd == c->cfg.physics && v[i].rec == c->cfg.recon) {
       if (k == want) return &v[i];
       ++k;
     }
@@ -395,7 +395,8 @@ void launch_cmax_of(amrvac_ctx* c, int buf, int slot, hipStream_t s) {
   q.slot = slot;
   launch_clear_slot(c->d_ctl, slot, s);
   int grid = (int)std::min<long long>((long long)c->ncu * 8, (long long)c->htiles.size());
-  launch_cmax(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD, q, grid, s);
+  // psi enters no wave speed: GLM uses the MHD reduction
+  launch_cmax(c->cfg.ndim, c->cfg.physics != AMRVAC_HD, q, grid, s);
 }
 }  // namespace amrvac
 
@@ -407,13 +408,14 @@ namespace amrvac {
 void enqueue_step_outs(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U, const int* outs, int S,
                        const EmitPlan* emit) {
   const int ns = scheme_stages(scheme);
-  launch_step_begin(c->d_ctl, c->d_dxtab, c->cfg.ndim, 1, ns - 1, s);
+  launch_step_begin(c->d_ctl, c->d_dxtab, c->cfg.ndim, c->cfg.physics == AMRVAC_GLM, 1, ns - 1, s);
   std::vector<Recipe> r = recipes(scheme, U, outs, S);
   for (int i = 1; i <= ns; ++i) {
     const int cm_in = i - 1;
     const int cm_out = (i == ns) ? 0 : i;
     const int cm_reset = (i == 2) ? 0 : -1;
     StageParams p = make_params(c, r[i - 1], cm_in, cm_out, cm_reset);
+    p.decay_psi = (i == ns && c->cfg.physics == AMRVAC_GLM) ? 1 : 0;
     if (emit) {
       p.tiles = emit->tiles;
       p.tile_begin = 0;
@@ -466,7 +468,7 @@ amrvac_status ctx_fail(amrvac_ctx* c, amrvac_status st, const char* fmt, ...) {
 // ---------------------------------------------------------------------------
 static bool config_ok(const amrvac_config* cfg) {
   return cfg && cfg->ndim >= 1 && cfg->ndim <= 3 &&
-         (cfg->physics == AMRVAC_HD || cfg->physics == AMRVAC_MHD) &&
+         (cfg->physics == AMRVAC_HD || cfg->physics == AMRVAC_MHD || cfg->physics == AMRVAC_GLM) &&
          (cfg->exec == AMRVAC_EXEC_PER_BLOCK || cfg->exec == AMRVAC_EXEC_BATCHED) &&
          (cfg->recon == AMRVAC_MP5 || cfg->recon == AMRVAC_LIM03) &&
          std::isfinite(cfg->gamma) && cfg->gamma > 1.0;
@@ -527,13 +529,13 @@ amrvac_status amrvac_create(const amrvac_config* cfg, void* hip_stream, amrvac_c
     return AMRVAC_ERR_INVALID;
   }
   if (!config_ok(cfg)) {
-    g_noctx_error = "amrvac_create: invalid config (ndim 1..3, physics HD/MHD, exec, recon, gamma > 1)";
+    g_noctx_error = "amrvac_create: invalid config (ndim 1..3, physics HD/MHD/GLM, exec, recon, gamma > 1)";
     return AMRVAC_ERR_INVALID;
   }
   amrvac_ctx* c = new amrvac_ctx();
   c->cfg = *cfg;
   c->exec = cfg->exec;
-  c->nvar = cfg->physics == AMRVAC_MHD ? 8 : 2 + cfg->ndim;
+  c->nvar = cfg->physics == AMRVAC_GLM ? 9 : cfg->physics == AMRVAC_MHD ? 8 : 2 + cfg->ndim;
   c->stream = (hipStream_t)hip_stream;
   c->var = pick_variant(c, 0);
   hipError_t e = hipGetDevice(&c->device);
@@ -557,7 +559,7 @@ amrvac_status amrvac_validate_blocks(const amrvac_config* cfg, const amrvac_bloc
   std::string m;
   amrvac_status st = AMRVAC_OK;
   if (!config_ok(cfg)) {
-    m = "invalid config (ndim 1..3, physics HD/MHD, exec, recon, gamma > 1)";
+    m = "invalid config (ndim 1..3, physics HD/MHD/GLM, exec, recon, gamma > 1)";
     st = AMRVAC_ERR_INVALID;
   } else if (!blocks_ok(cfg->ndim, blocks, nblocks, m)) {
     st = AMRVAC_ERR_INVALID;
@@ -756,6 +758,11 @@ amrvac_status amrvac_fd_rhs(amrvac_ctx* c, double* const* rhs, double* cmax_out)
       double v;
       std::memcpy(&v, &cm[d], sizeof(double));
       cmax_out[d] = v;
+    }
+    if (c->cfg.physics == AMRVAC_GLM) {   // c_h in every direction
+      double ch = cmax_out[0];
+      for (int d = 1; d < c->cfg.ndim; ++d) ch = std::max(ch, cmax_out[d]);
+      for (int d = 0; d < c->cfg.ndim; ++d) cmax_out[d] = ch;
     }
     return read_status(c);
   }

@@ -20,7 +20,7 @@ const StageVariant* stage_variants(int* count);
 // Code-emitting stage kernel for (ndim, physics), or nullptr.
 const StageVariant* emit_variant(int ndim, int mhd, int rec);
 void launch_cmax(int ndim, int mhd, const CmaxParams& p, int grid, hipStream_t s);
-void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int clear_lo, int clear_hi,
+void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int glm, int clear_lo, int clear_hi,
                        hipStream_t s);
 void launch_clear_slot(Control* ctl, int slot, hipStream_t s);
 void launch_set_control(Control* ctl, double dt_fixed, double cfl, double t, hipStream_t s);

@@ -40,7 +40,7 @@ def test_header_constants_match_binding():
     for name, val in [("AMRVAC_ERR_INVALID", A.ERR_INVALID), ("AMRVAC_ERR_NONPHYSICAL", A.ERR_NONPHYSICAL),
                       ("AMRVAC_ERR_UNSUPPORTED", A.ERR_UNSUPPORTED), ("AMRVAC_SSPRK54", A.SSPRK54),
                       ("AMRVAC_EXEC_BATCHED", A.EXEC_BATCHED), ("AMRVAC_MHD", A.MHD),
-                      ("AMRVAC_MP5", A.MP5), ("AMRVAC_LIM03", A.LIM03)]:
+                      ("AMRVAC_MP5", A.MP5), ("AMRVAC_LIM03", A.LIM03), ("AMRVAC_GLM", A.GLM)]:
         assert re.search(rf"{name} = (\d+)", src).group(1) == str(val)
 
 
@@ -52,7 +52,8 @@ def test_create_rejects_invalid_config_without_device():
     for cfg in (A.Config(0, A.HD, 1.4, A.EXEC_BATCHED), A.Config(4, A.HD, 1.4, A.EXEC_BATCHED),
                 A.Config(2, 7, 1.4, A.EXEC_BATCHED), A.Config(2, A.HD, 1.0, A.EXEC_BATCHED),
                 A.Config(2, A.HD, float("nan"), A.EXEC_BATCHED), A.Config(2, A.HD, 1.4, 9),
-                A.Config(2, A.HD, 1.4, A.EXEC_BATCHED, 2), A.Config(2, A.HD, 1.4, A.EXEC_BATCHED, -1)):
+                A.Config(2, A.HD, 1.4, A.EXEC_BATCHED, 2), A.Config(2, A.HD, 1.4, A.EXEC_BATCHED, -1),
+                A.Config(2, 3, 1.4, A.EXEC_BATCHED)):
         assert L.amrvac_create(ctypes.byref(cfg), None, ctypes.byref(h)) == A.ERR_INVALID
         assert h.value is None
     assert b"invalid config" in L.amrvac_last_error(None)

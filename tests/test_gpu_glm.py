@@ -1,0 +1,190 @@
+"""GPU parity of GLM-MHD (Sect. 4.2, glm3: psi as a ninth variable, cleaning
+speed c_h, operator-split decay of psi) through the C ABI against the oracle:
+right-hand sides and c_max, states after SSPRK(5,4) + MP5 and RK3 + LIM03
+steps, the exact decay of a uniform psi, bitwise equality of every tile
+shape and of both execution forms, and the adjoint's refusal.
+
+psi is compared on the scale of its flux, c_h |B| (a divergence-free field
+leaves psi at rounding level, where a relative measure means nothing);
+the eight MHD variables as in the MHD parity tests."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_l1, strip_blocks
+from paper_1407_2052_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1407_2052_amd import amrvac as A  # noqa: E402
+from test_gpu_parity import compare_rhs, host_blocks  # noqa: E402
+
+RTOL_STATE = 1e-11
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def with_psi(bs, seed, amp=0.02):
+    """GLM copy of an MHD list with a seeded smooth psi (ghosts included)."""
+    g = inputs.as_glm(bs)
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, 3, size=3)
+    ph = rng.uniform(0, 2 * math.pi)
+    for b in range(g.nb):
+        P = g.u[b].shape[1:]
+        idx = np.meshgrid(*[np.arange(p) for p in P], indexing="ij")
+        # cell-centre coordinates of the padded array (axes z, y, x)
+        c = [g.xlo[b, d] + (idx[2 - d] - (3 if d < g.ndim else 0) + 0.5) * g.dx[b, d] for d in range(3)]
+        arg = k[0] * c[0] + k[1] * c[1] + k[2] * c[2]
+        g.u[b][8] = amp * np.sin(2 * math.pi * arg + ph)
+    return g
+
+
+G = inputs.as_glm
+CASES = {
+    "briowu1d_fixed": lambda: G(inputs.brio_wu(128)),
+    "psiwave1d": lambda: with_psi(strip_blocks(1, True, [32, 40, 24], seed=1), 11),
+    "ot2d": lambda: G(inputs.orszag_tang_2d(64, 16)),
+    "ragged2d": lambda: with_psi(strip_blocks(2, True, [13, 19, 7], ny=21, seed=2), 12),
+    "ragged3d": lambda: with_psi(strip_blocks(3, True, [9, 12], ny=7, nz=5, seed=3), 13),
+    "mhd3d": lambda: with_psi(inputs.mhd_turbulence_3d(N=32, block=16, seed=5), 14),
+    "uneven3d": lambda: with_psi(inputs.uneven_3d(nblocks=14, seed=3, N=64), 15),
+    "min3_3d": lambda: with_psi(strip_blocks(3, True, [3, 4, 3], ny=3, nz=3, seed=7), 16),
+    "min3_1d": lambda: with_psi(strip_blocks(1, True, [3, 5, 3, 3, 8, 3], seed=6), 17),
+}
+
+
+@pytest.fixture(params=[oracle.MP5, oracle.LIM03], ids=["mp5", "lim03"])
+def recon(request):
+    oracle.set_recon(request.param)
+    yield request.param
+    oracle.set_recon(oracle.MP5)
+
+
+def gpu_rhs(bs, recon):
+    ctx, flat, views = A.context_for(bs, recon=recon)
+    out, cm = ctx.fd_rhs()
+    res = [o.cpu().numpy() for o in out]
+    ctx.close()
+    return res, cm
+
+
+def gpu_run(bs, scheme, nsteps, recon, cfl=0.4, exec=A.EXEC_BATCHED, variant=None):
+    ctx, flat, views = A.context_for(bs, exec, recon=recon)
+    if variant is not None:
+        ctx.set_variant(variant)
+    t = ctx.ssprk_step(scheme, nsteps, cfl=cfl, t=0.0)
+    out = bs.copy()
+    out.u = host_blocks(views)
+    ctx.close()
+    return out, t
+
+
+def assert_glm_state_parity(bs, out_g, out_o, ch):
+    for v in range(8):
+        num, den = rel_l1(out_g.u, out_o.u, bs, v)
+        if den == 0.0:
+            assert num == 0.0, f"var {v} must stay exactly zero"
+        else:
+            assert num / den <= RTOL_STATE, (v, num / den)
+    num, den_psi = rel_l1(out_g.u, out_o.u, bs, 8)
+    den_b = sum(rel_l1(out_o.u, out_o.u, bs, v)[1] for v in (5, 6, 7))
+    assert num <= RTOL_STATE * (ch * den_b + den_psi), ("psi", num, ch * den_b, den_psi)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_rhs_matches_oracle(case, recon):
+    say(f"[glm rhs] {case} recon={recon}")
+    bs = CASES[case]()
+    Lo, cmo = oracle.rhs(bs)
+    Lg, cmg = gpu_rhs(bs, recon)
+    np.testing.assert_allclose(cmg[:bs.ndim], cmo[:bs.ndim], rtol=1e-14, atol=0)
+    assert all(cmg[d] == cmg[0] for d in range(bs.ndim))   # c_h in every direction
+    compare_rhs(bs, Lg, Lo, cmo)
+
+
+STEP_CASES = [("briowu1d_fixed", 60), ("psiwave1d", 80), ("ot2d", 40), ("ragged2d", 40), ("ragged3d", 20),
+              ("mhd3d", 10), ("uneven3d", 8), ("min3_3d", 10), ("min3_1d", 40)]
+
+
+@pytest.mark.parametrize("case,nsteps", STEP_CASES, ids=[c for c, _ in STEP_CASES])
+def test_steps_match_oracle(case, nsteps, recon):
+    scheme = oracle.SSPRK54 if recon == oracle.MP5 else oracle.RK3
+    say(f"[glm steps] {case} recon={recon} n={nsteps}")
+    bs = CASES[case]()
+    ch = oracle.cmax(bs).max()
+    out_o, dts = oracle.run(bs, scheme, nsteps, cfl=0.4)
+    out_g, t = gpu_run(bs, scheme, nsteps, recon)
+    assert abs(t - dts.sum()) <= 1e-12 * dts.sum()
+    assert_glm_state_parity(bs, out_g, out_o, ch)
+
+
+def test_uniform_psi_decays_exactly_on_gpu():
+    n, dx, xlo, nbr, _ = inputs.uniform_blocks(3, [16, 16, 16], [8, 8, 8])
+    bs = inputs.sample_blocks(3, 2, 5 / 3, n, dx, xlo, nbr, lambda X, Y, Z: {
+        "rho": 1.0 + 0 * X, "p": 0.5 + 0 * X, "vx": 0.3 + 0 * X, "vz": -0.2 + 0 * X, "Bx": 0.7 + 0 * X,
+        "By": 0.2 + 0 * X, "Bz": 0.1 + 0 * X, "psi": 0.25 + 0 * X})
+    ch = oracle.cmax(bs).max()
+    out, t = gpu_run(bs, oracle.SSPRK54, 9, oracle.MP5)
+    # the step sizes are all equal (uniform state): t = 9 dt
+    expect = 0.25 * math.exp(-t * ch / oracle.glm_cr())
+    for b in range(out.nb):
+        np.testing.assert_allclose(out.interior(b)[8], expect, rtol=1e-13)
+
+
+@pytest.mark.parametrize("case", ["ragged2d", "ragged3d", "min3_3d", "uneven3d", "min3_1d"])
+def test_every_tile_shape_and_both_exec_forms_are_bitwise_identical(case, recon):
+    bs = CASES[case]()
+    scheme = oracle.SSPRK54 if recon == oracle.MP5 else oracle.RK3
+    ctx0, _, _ = A.context_for(bs, recon=recon)
+    names = ctx0.variants()
+    ctx0.close()
+    assert names and all("glm" in n for n in names)
+    ref = None
+    for i, name in enumerate(names):
+        say(f"[glm variant] {case} {name}")
+        got = gpu_run(bs, scheme, 3, recon, variant=i)
+        if ref is None:
+            ref = got
+            continue
+        assert got[1] == ref[1], name
+        for x, y in zip(got[0].u, ref[0].u):
+            assert np.array_equal(x, y), name
+    pb = gpu_run(bs, scheme, 3, recon, exec=A.EXEC_PER_BLOCK)
+    assert pb[1] == ref[1]
+    for x, y in zip(pb[0].u, ref[0].u):
+        assert np.array_equal(x, y)
+
+
+def test_full_size_uneven3d_glm_rhs_on_sampled_blocks():
+    say("[glm full] uneven3d 4096 blocks, rhs on sampled blocks")
+    from test_gpu_parity import sample_blocks_with_true_ghosts
+    bs = with_psi(inputs.uneven_3d(), 21)
+    Lg, cmg = gpu_rhs(bs, oracle.MP5)
+    cmo = oracle.cmax(bs)
+    np.testing.assert_allclose(cmg, cmo, rtol=1e-14)
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([rng.choice(bs.nb, 16, replace=False), [0, bs.nb - 1]]))
+    sub = sample_blocks_with_true_ghosts(bs, idx)
+    Lo, _ = oracle.rhs(sub, cmax=cmo)
+    compare_rhs(sub, [Lg[i] for i in idx], Lo, cmo)
+
+
+def test_adjoint_refuses_glm():
+    bs = CASES["ot2d"]()
+    ctx, flat, views = A.context_for(bs)
+    lam = [torch.zeros_like(v) for v in views]
+    with pytest.raises(A.AmrvacError) as e:
+        ctx.ssprk_adjoint(oracle.SSPRK54, 1e-3, 1, 1, lam)
+    assert e.value.status == A.ERR_UNSUPPORTED
+    ctx.close()
