@@ -56,6 +56,7 @@ def lib():
                               ctypes.c_int, ip, dp, ip, dpp, dpp, dp, dp]
         L.orc_cmax.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ip, dp, ip,
                                dpp, dp]
+        L.orc_divb.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ip, dp, ip, dpp, dpp]
         L.orc_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                               ctypes.c_int, ip, dp, ip, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, ctypes.c_int, dpp, dp]
@@ -219,6 +220,18 @@ def cmax(bs) -> np.ndarray:
                         _dp(cm))
     _check(st, "cmax")
     return cm
+
+
+def divb(bs) -> List[np.ndarray]:
+    """div B by fourth-order central differences at every interior cell
+    (Sect. 4.5.1 monitor); per block an array of the interior shape
+    (nz, ny, nx)."""
+    n, dx, nbr = _geom(bs)
+    u = [np.ascontiguousarray(x, np.float64) for x in bs.u]
+    out = [np.zeros(int(np.prod(bs.n[b]))) for b in range(bs.nb)]
+    st = lib().orc_divb(bs.ndim, int(bs.mhd), bs.gamma, bs.nb, _ip(n), _dp(dx), _ip(nbr), _ptrs(u), _ptrs(out))
+    _check(st, "divb")
+    return [o.reshape(int(bs.n[b, 2]), int(bs.n[b, 1]), int(bs.n[b, 0])) for b, o in enumerate(out)]
 
 
 def run(bs, scheme: int, nsteps: int, cfl: float = 0.4, dt: Optional[float] = None,

@@ -816,6 +816,41 @@ int orc_cmax(int ndim, int mhd, double gamma, int nb, const int* n, const double
   return st;
 }
 
+// Divergence of B at every interior cell by fourth-order central
+// differences along each active direction (the monitor of Sect. 4.5.1):
+//   div B = sum_d (8 (B_d[i+1] - B_d[i-1]) - (B_d[i+2] - B_d[i-2])) / (12 dx_d),
+// halo from the face neighbours (periodic) or the fixed ghost layers.
+// out: per block, interior-only layout (one double per cell, x fastest).
+int orc_divb(int ndim, int mhd, double gamma, int nb, const int* n, const double* dx, const int* nbr,
+             const double* const* u, double* const* out) {
+  if (mhd == 0) return ORC_ERR_INVALID;
+  Grid G;
+  int st = build_grid(G, ndim, mhd, gamma, nb, n, dx, nbr);
+  if (st) return st;
+  State<double> U;
+  load_state(G, U, u);
+  fill_ghosts(G, U);
+  for (int b = 0; b < nb; ++b) {
+    const Geom& q = G.g[b];
+    size_t o = 0;
+    for (int k = 0; k < q.n[2]; ++k)
+      for (int j = 0; j < q.n[1]; ++j)
+        for (int i = 0; i < q.n[0]; ++i, ++o) {
+          double div = 0.0;
+          for (int d = 0; d < ndim; ++d) {
+            auto B = [&](int s) {
+              int c[3] = {i, j, k};
+              c[d] += s;
+              return U[b][(5 + d) * q.ncell + q.idx(c[0], c[1], c[2])];
+            };
+            div = div + (8.0 * (B(1) - B(-1)) - (B(2) - B(-2))) / (12.0 * q.dx[d]);
+          }
+          out[b][o] = div;
+        }
+  }
+  return ORC_OK;
+}
+
 // nsteps SSPRK steps.  dt_fixed <= 0 selects the CFL rule.  u: in/out
 // padded blocks (interiors updated; ghosts on output are those of the last
 // stage: periodic ones refreshed, fixed ones unchanged).  dts: optional

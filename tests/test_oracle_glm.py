@@ -158,3 +158,52 @@ def test_glm_alfven_wave_fifth_order():
     E = np.array(E)
     for v in (2, 6, 7):
         assert math.log2(E[0, v] / E[1, v]) > 4.5, (v, E[:, v])
+
+
+# --------------------------------------------------------------- div B monitor
+def test_divb_exact_for_quartic_fields_with_fixed_ghosts():
+    # fourth-order central differences are exact for polynomials of degree <= 4
+    n, dx, xlo, nbr, _ = inputs.uniform_blocks(3, [12, 10, 8], [6, 5, 8], periodic=False)
+    f = lambda X, Y, Z: {"rho": 1.0 + 0 * X, "p": 1.0 + 0 * X, "Bx": X ** 4 - 2 * X * Y + Z,
+                         "By": Y ** 3 * Z + X ** 2, "Bz": Z ** 2 * X - Y}
+    bs = inputs.sample_blocks(3, True, GAMMA, n, dx, xlo, nbr, f)
+    div = oracle.divb(bs)
+    for b in range(bs.nb):
+        X, Y, Z = inputs.cell_centres(3, bs.n[b], bs.dx[b], bs.xlo[b])
+        exact = 4 * X ** 3 - 2 * Y + 3 * Y ** 2 * Z + 2 * Z * X
+        np.testing.assert_allclose(div[b], exact[3:-3, 3:-3, 3:-3], rtol=0, atol=1e-11)
+
+
+def test_divb_zero_for_fields_constant_along_their_own_direction():
+    n, dx, xlo, nbr, _ = inputs.uniform_blocks(3, [16, 16, 16], [8, 8, 8])
+    tp = 2 * math.pi
+    bs = inputs.sample_blocks(3, 2, GAMMA, n, dx, xlo, nbr, lambda X, Y, Z: {
+        "rho": 1.0 + 0 * X, "p": 1.0 + 0 * X, "Bx": np.sin(tp * Y) + np.cos(tp * Z),
+        "By": np.sin(tp * Z) * np.cos(tp * X), "Bz": np.sin(tp * X + tp * Y)})
+    for d in oracle.divb(bs):
+        assert np.all(d == 0.0)
+
+
+def test_divb_fourth_order_and_block_invariance():
+    tp = 2 * math.pi
+    errs = []
+    for N in (16, 32, 64):
+        n, dx, xlo, nbr, _ = inputs.uniform_blocks(2, [N, N], [N // 4, N // 2])
+        bs = inputs.sample_blocks(2, True, GAMMA, n, dx, xlo, nbr, lambda X, Y, Z: {
+            "rho": 1.0 + 0 * X, "p": 1.0 + 0 * X, "Bx": np.sin(tp * X), "By": np.cos(tp * Y)})
+        div = oracle.divb(bs)
+        err = 0.0
+        for b in range(bs.nb):
+            X, Y, Z = inputs.cell_centres(2, bs.n[b], bs.dx[b], bs.xlo[b])
+            exact = (tp * np.cos(tp * X) - tp * np.sin(tp * Y))[:, 3:-3, 3:-3]
+            err = max(err, np.abs(div[b] - exact).max())
+        errs.append(err)
+        one = inputs.sample_blocks(2, True, GAMMA, *inputs.uniform_blocks(2, [N, N], [N, N])[:4],
+                                   lambda X, Y, Z: {"rho": 1.0 + 0 * X, "p": 1.0 + 0 * X,
+                                                    "Bx": np.sin(tp * X), "By": np.cos(tp * Y)})
+        whole = oracle.divb(one)[0]
+        for b in range(bs.nb):
+            ox = int(round(bs.xlo[b, 0] * N)); oy = int(round(bs.xlo[b, 1] * N))
+            assert np.array_equal(div[b], whole[:, oy:oy + bs.n[b, 1], ox:ox + bs.n[b, 0]])
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(3.9 < o < 4.1 for o in orders), orders
