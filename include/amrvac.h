@@ -185,6 +185,21 @@ amrvac_status amrvac_autotune(amrvac_ctx *ctx, int scheme, int nsteps, double *m
  * NONPHYSICAL (only when synchronising), DEVICE. */
 amrvac_status amrvac_fd_rhs(amrvac_ctx *ctx, double *const *rhs, double *cmax_out);
 
+/* Divergence of B, the monitor of Sect. 4.5.1 (MHD and GLM contexts only):
+ * at every interior cell of the active blocks,
+ *   div B = sum over active d of (8 (B_d[i+1] - B_d[i-1]) - (B_d[i+2] -
+ *           B_d[i-2])) / (12 dx_d),
+ * fourth-order central differences of the blocks' state u, with the face
+ * neighbours' interiors (or the fixed ghost layers) as halo.
+ *  out:          NULL, or per block a device pointer to n[0]*n[1]*n[2]
+ *                doubles (interior-only layout, x fastest), caller-owned;
+ *  mean_abs_out: NULL, or host: the mean of |div B| over those cells, summed
+ *                in a fixed order (the same bits on every call for the same
+ *                state and tile shape); when non-NULL the call synchronises.
+ * Errors: INVALID (no blocks, hydro context, null entry in out), NOMEM,
+ * DEVICE. */
+amrvac_status amrvac_divb(amrvac_ctx *ctx, double *const *out, double *mean_abs_out);
+
 /* Advances every block by nsteps steps of `scheme` (Sect. 2.3).  The
  * interiors of the u buffers are overwritten with U^{n+nsteps}; ghost layers
  * are not written.  dt_fixed: host pointer to a fixed step > 0, or NULL to

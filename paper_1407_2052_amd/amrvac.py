@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NONPHYSICAL"
 SYMBOLS = ["amrvac_abi_version", "amrvac_create", "amrvac_set_blocks", "amrvac_validate_blocks",
            "amrvac_set_exec", "amrvac_num_variants", "amrvac_variant_name", "amrvac_set_variant",
            "amrvac_get_variant",
-           "amrvac_autotune", "amrvac_fd_rhs", "amrvac_ssprk_step", "amrvac_ssprk_adjoint",
+           "amrvac_autotune", "amrvac_fd_rhs", "amrvac_divb", "amrvac_ssprk_step", "amrvac_ssprk_adjoint",
            "amrvac_activation_flags", "amrvac_set_active",
            "amrvac_sync", "amrvac_last_error", "amrvac_destroy"]
 
@@ -83,6 +83,7 @@ def lib():
         L.amrvac_get_variant.restype = ctypes.c_int
         L.amrvac_autotune.argtypes = [vp, ip, ip, dp]
         L.amrvac_fd_rhs.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p), dp]
+        L.amrvac_divb.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p), dp]
         L.amrvac_ssprk_step.argtypes = [vp, ip, ctypes.c_double, dp, ip, dp]
         L.amrvac_ssprk_adjoint.argtypes = [vp, ip, ctypes.c_double, ip, ip, ctypes.POINTER(ctypes.c_void_p)]
         ub = ctypes.POINTER(ctypes.c_ubyte)
@@ -224,6 +225,20 @@ class Context:
         cm = (ctypes.c_double * 3)()
         self._check(lib().amrvac_fd_rhs(self._h, ptrs, cm if want_cmax else None))
         return out, (np.array(cm[:]) if want_cmax else None)
+
+    def divb(self, want_field: bool = True):
+        """div B (fourth-order central differences) per block as device
+        tensors (nz, ny, nx), and the mean of |div B| (synchronising)."""
+        t = self._torch
+        out = None
+        ptrs = None
+        if want_field:
+            out = [t.empty((int(nn[2]), int(nn[1]), int(nn[0])), dtype=t.float64, device=self.blocks[0].device)
+                   for nn in self.n]
+            ptrs = (ctypes.c_void_p * len(out))(*[o.data_ptr() for o in out])
+        mean = ctypes.c_double(0.0)
+        self._check(lib().amrvac_divb(self._h, ptrs, ctypes.byref(mean)))
+        return out, mean.value
 
     def ssprk_step(self, scheme: int, nsteps: int, cfl: float = 0.4, dt: Optional[float] = None,
                    t: Optional[float] = 0.0) -> Optional[float]:

@@ -391,4 +391,11 @@ __device__ __forceinline__ double wave_max(double x) {
   return x;
 }
 
+// Sum over the 64 lanes of a wave in a fixed butterfly order (deterministic).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x = x + __shfl_xor(x, m, 64);
+  return x;
+}
+
 }  // namespace amrvac

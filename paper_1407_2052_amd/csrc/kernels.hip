@@ -551,6 +551,60 @@ __global__ void __launch_bounds__(256) k_copy_interior(StateTable st, const Tile
   }
 }
 
+// Divergence of B by fourth-order central differences along each active
+// direction (the monitor of Sect. 4.5.1), at every interior cell of the tile
+// list, from buffer `in` with face neighbours' interiors (or fixed ghost
+// layers) as halo.  Writes out[block] (interior layout) when out is set, and
+// per tile the sum of |div B| over its cells, reduced in a fixed order.
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_divb(StateTable st, const Tile* tiles, int ntiles, int tx, int ty, int tz,
+                                            int in, double* const* out, double* tsum) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int tcells = tx * ty * tz;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Tile tl = tiles[t];
+    const BlockDev& B = st.blocks[tl.block];
+    double acc = 0.0;
+    for (int c = tid; c < tcells; c += 256) {
+      const int i = tl.o[0] + c % tx, j = tl.o[1] + (c / tx) % ty, k = tl.o[2] + c / (tx * ty);
+      if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
+      double div = 0.0;
+      static_for<0, NDIM>([&](auto Dc) {
+        constexpr int D = decltype(Dc)::value;
+        double b[5];
+#pragma unroll
+        for (int s = -2; s <= 2; ++s) {
+          if (s == 0) continue;
+          int cc[3] = {i, j, k};
+          cc[D] += s;
+          load_cell_vars<5 + D, 1, D>(st, tl.block, in, cc[0], cc[1], cc[2], &b[s + 2]);
+        }
+        div = div + (8.0 * (b[3] - b[1]) - (b[4] - b[0])) / (12.0 * B.dx[D]);
+      });
+      if (out) out[tl.block][((long long)k * B.n[1] + j) * B.n[0] + i] = div;
+      acc = acc + fabs(div);
+    }
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) tsum[t] = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+  }
+}
+
+// Sum of n values in a fixed order (one work-group of 256 threads).
+__global__ void __launch_bounds__(256) k_sum_fixed(const double* x, int n, double* result) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  for (int q = tid; q < n; q += 256) acc = acc + x[q];
+  acc = wave_sum(acc);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) *result = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // Clears one c_max slot (used before a standalone c_max reduction).
 __global__ void k_clear_slot(Control* ctl, int slot) {
   if (threadIdx.x < 3 && blockIdx.x == 0) ctl->cm[slot][threadIdx.x] = 0ull;
@@ -737,6 +791,14 @@ void launch_copy_interior(const StateTable& st, const Tile* tiles, int ntiles, i
                           int src, int dst, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_interior, dim3(grid), dim3(256), 0, s, st, tiles, ntiles, tx, ty, tz, nv, src,
                      dst);
+}
+
+void launch_divb(int ndim, const StateTable& st, const Tile* tiles, int ntiles, int tx, int ty, int tz, int in,
+                 double* const* out, double* tsum, double* total, int grid, hipStream_t s) {
+  if (ndim == 1) hipLaunchKernelGGL(k_divb<1>, dim3(grid), dim3(256), 0, s, st, tiles, ntiles, tx, ty, tz, in, out, tsum);
+  if (ndim == 2) hipLaunchKernelGGL(k_divb<2>, dim3(grid), dim3(256), 0, s, st, tiles, ntiles, tx, ty, tz, in, out, tsum);
+  if (ndim == 3) hipLaunchKernelGGL(k_divb<3>, dim3(grid), dim3(256), 0, s, st, tiles, ntiles, tx, ty, tz, in, out, tsum);
+  hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, s, tsum, ntiles, total);
 }
 
 void launch_clear_slot(Control* ctl, int slot, hipStream_t s) {

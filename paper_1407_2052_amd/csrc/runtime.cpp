@@ -55,6 +55,11 @@ static void free_tables(amrvac_ctx* c) {
   if (c->d_dxtab) (void)hipFree(c->d_dxtab);
   if (c->d_rhs_ptrs) (void)hipFree(c->d_rhs_ptrs);
   if (c->d_ptiles) (void)hipFree(c->d_ptiles);
+  if (c->d_divb_ptrs) (void)hipFree(c->d_divb_ptrs);
+  if (c->d_divb_sum) (void)hipFree(c->d_divb_sum);
+  c->d_divb_ptrs = nullptr;
+  c->d_divb_sum = nullptr;
+  c->divb_cap = 0;
   c->d_ptiles = nullptr;
   c->d_blocks = nullptr;
   c->d_tiles = nullptr;
@@ -169,6 +174,11 @@ static amrvac_status build_tiles(amrvac_ctx* c) {
   HIP_TRY(c, hipMemcpyAsync(c->d_tiles, c->htiles.data(), sizeof(Tile) * c->htiles.size(),
                             hipMemcpyHostToDevice, c->stream));
   if (c->d_ptiles) (void)hipFree(c->d_ptiles);
+  if (c->d_divb_ptrs) (void)hipFree(c->d_divb_ptrs);
+  if (c->d_divb_sum) (void)hipFree(c->d_divb_sum);
+  c->d_divb_ptrs = nullptr;
+  c->d_divb_sum = nullptr;
+  c->divb_cap = 0;
   c->d_ptiles = nullptr;
   if (!c->hptiles.empty()) {
     HIP_TRY(c, hipMalloc(&c->d_ptiles, sizeof(Tile) * c->hptiles.size()));
@@ -765,6 +775,47 @@ amrvac_status amrvac_fd_rhs(amrvac_ctx* c, double* const* rhs, double* cmax_out)
       for (int d = 0; d < c->cfg.ndim; ++d) cmax_out[d] = ch;
     }
     return read_status(c);
+  }
+  return AMRVAC_OK;
+}
+
+amrvac_status amrvac_divb(amrvac_ctx* c, double* const* out, double* mean_abs_out) {
+  if (!c) return AMRVAC_ERR_INVALID;
+  if (c->hb.empty()) return fail(c, AMRVAC_ERR_INVALID, "divb: no blocks set");
+  if (c->cfg.physics == AMRVAC_HD) return fail(c, AMRVAC_ERR_INVALID, "divb: hydro has no magnetic field");
+  const int nb = (int)c->hb.size();
+  if (out)
+    for (int b = 0; b < nb; ++b)
+      if (!out[b]) return fail(c, AMRVAC_ERR_INVALID, "divb: out[%d] is NULL", b);
+  const int nt = (int)c->htiles.size();
+  if (!c->d_divb_ptrs) HIP_TRY(c, hipMalloc(&c->d_divb_ptrs, sizeof(double*) * nb));
+  if (c->divb_cap < nt + 1) {   // the tile list changes with the variant and the active set
+    if (c->d_divb_sum) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      (void)hipFree(c->d_divb_sum);
+      c->d_divb_sum = nullptr;
+      c->divb_cap = 0;
+    }
+    HIP_TRY(c, hipMalloc(&c->d_divb_sum, sizeof(double) * (nt + 1)));
+    c->divb_cap = nt + 1;
+  }
+  if (out) {
+    c->hdivb.assign(out, out + nb);
+    HIP_TRY(c, hipMemcpyAsync(c->d_divb_ptrs, c->hdivb.data(), sizeof(double*) * nb, hipMemcpyHostToDevice,
+                              c->stream));
+  }
+  const int grid = std::max(1, std::min(nt, c->ncu * 8));
+  launch_divb(c->cfg.ndim, state_table(c), c->d_tiles, nt, c->var->tx, c->var->ty, c->var->tz, 0,
+              out ? c->d_divb_ptrs : nullptr, c->d_divb_sum, c->d_divb_sum + nt, grid, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  if (mean_abs_out) {
+    double total = 0.0;
+    HIP_TRY(c, hipMemcpyAsync(&total, c->d_divb_sum + nt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    long long cells = 0;
+    for (int b = 0; b < nb; ++b)
+      if (c->active[b]) cells += (long long)c->hb[b].n[0] * c->hb[b].n[1] * c->hb[b].n[2];
+    *mean_abs_out = total / (double)cells;
   }
   return AMRVAC_OK;
 }

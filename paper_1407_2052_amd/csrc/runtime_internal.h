@@ -20,6 +20,8 @@ const StageVariant* stage_variants(int* count);
 // Code-emitting stage kernel for (ndim, physics), or nullptr.
 const StageVariant* emit_variant(int ndim, int mhd, int rec);
 void launch_cmax(int ndim, int mhd, const CmaxParams& p, int grid, hipStream_t s);
+void launch_divb(int ndim, const StateTable& st, const Tile* tiles, int ntiles, int tx, int ty, int tz, int in,
+                 double* const* out, double* tsum, double* total, int grid, hipStream_t s);
 void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int glm, int clear_lo, int clear_hi,
                        hipStream_t s);
 void launch_clear_slot(Control* ctl, int slot, hipStream_t s);
@@ -82,6 +84,11 @@ struct amrvac_ctx {
   int ndx = 0;
   double** d_rhs_ptrs = nullptr;
   std::vector<double*> hrhs;
+  // amrvac_divb: per-block output pointers, per-tile sums, total
+  double** d_divb_ptrs = nullptr;
+  std::vector<double*> hdivb;
+  double* d_divb_sum = nullptr;   // divb_cap doubles (tiles + 1)
+  int divb_cap = 0;
 
   std::map<int, GraphEntry> graphs;
 };

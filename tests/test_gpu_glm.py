@@ -188,3 +188,81 @@ def test_adjoint_refuses_glm():
         ctx.ssprk_adjoint(oracle.SSPRK54, 1e-3, 1, 1, lam)
     assert e.value.status == A.ERR_UNSUPPORTED
     ctx.close()
+
+
+# --------------------------------------------------------------- div B monitor
+DIVB_CASES = {
+    "ragged3d_mhd": lambda: strip_blocks(3, True, [9, 12], ny=7, nz=5, seed=3),
+    "uneven3d_fixed": lambda: inputs.uneven_3d(nblocks=14, seed=3, N=64),
+    "min3_3d_glm": lambda: CASES["min3_3d"](),
+    "ragged2d_glm": lambda: CASES["ragged2d"](),
+    "min3_1d_mhd": lambda: strip_blocks(1, True, [3, 5, 3, 3, 8, 3], seed=6),
+}
+
+
+@pytest.mark.parametrize("case", sorted(DIVB_CASES))
+def test_divb_monitor_matches_oracle(case):
+    say(f"[divb] {case}")
+    bs = DIVB_CASES[case]()
+    ref = oracle.divb(bs)
+    ctx, flat, views = A.context_for(bs)
+    fields, mean = ctx.divb()
+    got = [f.cpu().numpy() for f in fields]
+    _, mean2 = ctx.divb(want_field=False)
+    ctx.close()
+    scale = max(float(np.abs(r).max()) for r in ref)
+    for g, r in zip(got, ref):
+        assert np.abs(g - r).max() <= 1e-13 * scale
+    m_ref = math.fsum(float(np.abs(r).sum()) for r in ref) / sum(r.size for r in ref)
+    assert mean == pytest.approx(m_ref, rel=1e-13)
+    assert mean2 == mean   # fixed reduction order
+
+
+def test_divb_refuses_hydro():
+    bs = strip_blocks(2, False, [13, 19], ny=10, seed=1, gamma=1.4)
+    ctx, flat, views = A.context_for(bs)
+    with pytest.raises(A.AmrvacError) as e:
+        ctx.divb()
+    assert e.value.status == A.ERR_INVALID
+    ctx.close()
+
+
+@pytest.mark.parametrize("recon", [oracle.MP5, oracle.LIM03], ids=["mp5", "lim03"])
+def test_rotated_alfven_wave_3d_converges_on_gpu(recon):
+    # Sect. 4.5.1: circularly polarised Alfven wave, k = 2 pi (1, 2, 2), GLM
+    # state vector, one period (T = 1/|k|); the exact solution is the initial
+    # state.  Paper: fifth order with SSPRK(5,4) + MP5 and third order with
+    # RK3 + LIM03, div B falling at the reconstruction's order minus one.
+    scheme = oracle.SSPRK54 if recon == oracle.MP5 else oracle.RK3
+    l1, dv = [], []
+    for N in (16, 32, 64):
+        say(f"[alfven3d] recon={recon} N={N}")
+        bs = inputs.circular_alfven(3, N, block=N // 2, kvec=(1, 2, 2), glm=True)
+        _, cm = oracle.rhs(bs) if N == 16 else (None, oracle.cmax(bs))
+        dt0 = 0.4 / sum(cm[d] / bs.dx[0, d] for d in range(3))
+        n = int(math.ceil((1.0 / 3.0) / dt0))
+        dt = (1.0 / 3.0) / n
+        ctx, flat, views = A.context_for(bs, recon=recon)
+        ctx.ssprk_step(scheme, n, dt=dt, t=0.0)
+        _, mean_divb = ctx.divb(want_field=False)
+        out = bs.copy()
+        out.u = host_blocks(views)
+        ctx.close()
+        if N == 16:
+            oracle.set_recon(recon)
+            try:
+                ref, _ = oracle.run(bs, scheme, n, dt=dt)
+            finally:
+                oracle.set_recon(oracle.MP5)
+            assert_glm_state_parity(bs, out, ref, cm.max())
+        err = np.concatenate([np.abs(out.interior(b)[:8] - bs.interior(b)[:8]).reshape(8, -1)
+                              for b in range(bs.nb)], axis=1)
+        l1.append(err.mean())
+        dv.append(mean_divb)
+    o_state = math.log2(l1[1] / l1[2])
+    o_divb = math.log2(dv[1] / dv[2])
+    say(f"[alfven3d] recon={recon} L1 {l1} order {o_state:.2f}; div B {dv} order {o_divb:.2f}")
+    if recon == oracle.MP5:
+        assert o_state > 4.6 and o_divb > 3.6, (l1, dv)
+    else:
+        assert o_state > 2.6, l1
