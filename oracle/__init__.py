@@ -47,6 +47,8 @@ def lib():
         L.orc_prim.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
         L.orc_flux.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp]
         L.orc_flux_glm.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, dp, dp]
+        L.orc_set_hall.argtypes = [ctypes.c_double]
+        L.orc_flux_hall.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp, dp]
         L.orc_glm_cr.restype = ctypes.c_double
         L.orc_set_glm_cr.argtypes = [ctypes.c_double]
         L.orc_fast_speed.restype = ctypes.c_double
@@ -173,6 +175,36 @@ def flux_glm(ndim: int, gamma: float, d: int, ch: float, u: Sequence[float]) -> 
     f = np.zeros(9)
     lib().orc_flux_glm(ndim, gamma, d, ch, _dp(a), _dp(f))
     return f
+
+
+def set_hall(eta_h: float) -> None:
+    """Hall parameter of the later MHD rhs / run / cmax calls (Sect. 4.4;
+    0 = ideal MHD)."""
+    lib().orc_set_hall(float(eta_h))
+
+
+class use_hall:
+    """Context manager: `with use_hall(eta_h): ...` restores ideal MHD."""
+
+    def __init__(self, eta_h: float):
+        self.eta_h = eta_h
+
+    def __enter__(self):
+        set_hall(self.eta_h)
+        return self
+
+    def __exit__(self, *exc):
+        set_hall(0.0)
+        return False
+
+
+def flux_hall(ndim: int, gamma: float, eta_h: float, d: int, u: Sequence[float], J: Sequence[float]) -> np.ndarray:
+    """MHD flux along d with the Hall terms for the current J."""
+    a = np.zeros(9); a[:len(u)] = u
+    j = np.ascontiguousarray(J, np.float64)
+    f = np.zeros(9)
+    lib().orc_flux_hall(ndim, gamma, eta_h, d, _dp(a), _dp(j), _dp(f))
+    return f[:8]
 
 
 def glm_cr() -> float:

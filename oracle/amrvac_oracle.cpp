@@ -61,6 +61,15 @@
 //       is operator split after each step: psi *= exp(-dt c_h / c_r) with
 //       c_h of the step's initial state and c_r = c_p^2 / c_h = 0.18
 //       (the second of the two ways the section names).
+//   R9  Hall MHD (Sect. 4.4, conservative Hall MHD in finite differences,
+//       with B0 = 0 and eta = 0): the cell-centred current J = curl B by
+//       fourth-order central differences along each active direction (an
+//       inactive direction contributes no derivative); J of halo cells is
+//       the face neighbour's J, so every face must have a neighbour (fixed
+//       faces are refused).  Flux terms (eta_h/rho)(B_d J - J_d B) on B and
+//       (eta_h/rho)((J.B) B_d - B^2 J_d) on E.  Speed |v_d| + max(c_f,d,
+//       eta_h |B| k_max / rho) with k_max = pi max_d 1/dx_d of the cell's
+//       block, in the split and in the time step.
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -251,6 +260,8 @@ template <class T> static T lim03(T a, T b, T c, double dx) {
 
 // Reconstruction selected for the following calls (0: MP5, 1: LIM03).
 static int g_recon = 0;
+// Hall parameter of the following calls (reading R9; 0: ideal MHD).
+static double g_eta_h = 0.0;
 
 // ---------------------------------------------------------------------------
 // Physics (Sect. 3 hydro with an ideal-gas energy equation; Sect. 4.1 and 4.3
@@ -264,6 +275,7 @@ struct Phys {
   int ndim;
   int mhd;
   double gamma;
+  double eta_h = 0.0;   // Hall parameter (reading R9); 0: ideal MHD
   int nvar() const { return mhd == 2 ? 9 : mhd ? 8 : 2 + ndim; }
   bool glm() const { return mhd == 2; }
   int ncomp() const { return mhd ? 3 : ndim; }   // momentum components
@@ -297,9 +309,10 @@ static bool cons_to_prim(const Phys& ph, const T* u, Prim<T>& w) {
 }
 
 // Physical flux along direction d (ch: the GLM cleaning speed, unused
-// otherwise).
+// otherwise; J: the cell's current, used with the Hall term).
 template <class T>
-static void phys_flux(const Phys& ph, int d, const T* u, const Prim<T>& w, T* f, T ch = T(0.0)) {
+static void phys_flux(const Phys& ph, int d, const T* u, const Prim<T>& w, T* f, T ch = T(0.0),
+                      const T* J = nullptr) {
   const int nc = ph.ncomp();
   const T vd = w.v[d];
   f[0] = u[1 + d];                                           // m_d
@@ -320,6 +333,12 @@ static void phys_flux(const Phys& ph, int d, const T* u, const Prim<T>& w, T* f,
   if (ph.glm()) {
     f[5 + d] = f[5 + d] + u[8];   // + psi delta_kd (the k = d term above is 0)
     f[8] = ch * ch * Bd;          // c_h^2 B_d
+  }
+  if (ph.eta_h != 0.0 && J) {     // Hall terms (reading R9)
+    T h = T(ph.eta_h) / w.rho;
+    T jb = J[0] * w.B[0] + J[1] * w.B[1] + J[2] * w.B[2];
+    for (int k = 0; k < 3; ++k) f[5 + k] = f[5 + k] + h * (Bd * J[k] - J[d] * w.B[k]);
+    f[4] = f[4] + h * (jb * Bd - b2 * J[d]);
   }
 }
 
@@ -422,6 +441,7 @@ static int build_grid(Grid& G, int ndim, int mhd, double gamma, int nb, const in
                       const double* dx, const int* nbr) {
   if (ndim < 1 || ndim > 3 || nb <= 0 || mhd < 0 || mhd > 2) return ORC_ERR_INVALID;
   G.ph.ndim = ndim; G.ph.mhd = mhd; G.ph.gamma = gamma;
+  G.ph.eta_h = (mhd == 1) ? g_eta_h : 0.0;
   G.g.resize(nb);
   for (int b = 0; b < nb; ++b) {
     Geom& q = G.g[b];
@@ -445,8 +465,8 @@ static int build_grid(Grid& G, int ndim, int mhd, double gamma, int nb, const in
 // neighbour's interior; fixed faces (nbr < 0) keep their values.  Edges and
 // corners are never read by the dimension-by-dimension operator.
 template <class T>
-static void fill_ghosts(const Grid& G, State<T>& U) {
-  const int nv = G.ph.nvar();
+static void fill_ghosts(const Grid& G, State<T>& U, int nv_override = 0) {
+  const int nv = nv_override > 0 ? nv_override : G.ph.nvar();
   for (size_t b = 0; b < G.g.size(); ++b) {
     const Geom& q = G.g[b];
     for (int d = 0; d < G.ph.ndim; ++d) {
@@ -494,7 +514,16 @@ static int global_cmax(const Grid& G, const State<T>& U, T cmax[3]) {
           Prim<T> w;
           if (!cons_to_prim(G.ph, u, w)) return ORC_ERR_NONPHYSICAL;
           for (int d = 0; d < G.ph.ndim; ++d) {
-            T s = absv(w.v[d]) + fast_speed(G.ph, d, w);
+            T cf = fast_speed(G.ph, d, w);
+            if (G.ph.eta_h != 0.0) {   // fast whistler at k_max (reading R9)
+              double kmax = 0.0;
+              for (int e = 0; e < G.ph.ndim; ++e) kmax = std::max(kmax, 1.0 / q.dx[e]);
+              kmax = M_PI * kmax;
+              T babs = sqrt_(w.B[0] * w.B[0] + w.B[1] * w.B[1] + w.B[2] * w.B[2]);
+              T wh = T(G.ph.eta_h) * babs / w.rho * T(kmax);
+              if (val(wh) > val(cf)) cf = wh;
+            }
+            T s = absv(w.v[d]) + cf;
             if (first || val(s) > val(cmax[d])) { cmax[d] = s; arg[d] = ((uint64_t)b << 32) | c; }
           }
           first = false;
@@ -515,11 +544,54 @@ static int global_cmax(const Grid& G, const State<T>& U, T cmax[3]) {
 // with Fhat from the global Lax-Friedrichs split and MP5 (Sect. 2.2).
 // Ghost layers of U must be filled.  L has the padded layout; its ghost
 // entries are left at zero.
+// Cell-centred current J = curl B (Sect. 4.4, eq. jcd4 at cell centres) on
+// the interior cells of every block, then on the halo cells from the face
+// neighbours.  U's ghosts must be filled.  Fixed faces are refused.
+template <class T>
+static int current(const Grid& G, const State<T>& U, State<T>& J) {
+  const int nb = (int)G.g.size();
+  J.resize(nb);
+  for (int b = 0; b < nb; ++b) {
+    const Geom& q = G.g[b];
+    for (int d = 0; d < G.ph.ndim; ++d)
+      if (q.nbr[2 * d] < 0 || q.nbr[2 * d + 1] < 0) return ORC_ERR_INVALID;
+    J[b].assign(3 * q.ncell, T(0.0));
+    for (int k = 0; k < q.n[2]; ++k)
+      for (int j = 0; j < q.n[1]; ++j)
+        for (int i = 0; i < q.n[0]; ++i) {
+          T dB[3][3];   // dB[a][c] = d B_c / d x_a
+          for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) {
+              dB[a][c] = T(0.0);
+              if (a >= G.ph.ndim) continue;
+              auto Bc = [&](int sft) {
+                int p3[3] = {i, j, k};
+                p3[a] += sft;
+                return U[b][(5 + c) * q.ncell + q.idx(p3[0], p3[1], p3[2])];
+              };
+              dB[a][c] = (T(-1.0) * Bc(2) + T(8.0) * Bc(1) - T(8.0) * Bc(-1) + Bc(-2)) / T(12.0 * q.dx[a]);
+            }
+          const size_t o = q.idx(i, j, k);
+          J[b][0 * q.ncell + o] = dB[1][2] - dB[2][1];
+          J[b][1 * q.ncell + o] = dB[2][0] - dB[0][2];
+          J[b][2 * q.ncell + o] = dB[0][1] - dB[1][0];
+        }
+  }
+  fill_ghosts(G, J, 3);
+  return ORC_OK;
+}
+
 template <class T>
 static int rhs(const Grid& G, const State<T>& U, const T cmax[3], State<T>& L, double eps) {
   const int nv = G.ph.nvar();
   const int nb = (int)G.g.size();
   int status = ORC_OK;
+  State<T> Jc;
+  const bool hall = G.ph.eta_h != 0.0;
+  if (hall) {
+    int st = current(G, U, Jc);
+    if (st) return st;
+  }
 #pragma omp parallel for schedule(dynamic)
   for (int b = 0; b < nb; ++b) {
     const Geom& q = G.g[b];
@@ -546,7 +618,10 @@ static int rhs(const Grid& G, const State<T>& U, const T cmax[3], State<T>& L, d
 #pragma omp atomic write
                 status = ORC_ERR_NONPHYSICAL;
               }
-              phys_flux(G.ph, d, u, w, f, cmax[d]);
+              T jc[3] = {T(0.0), T(0.0), T(0.0)};
+              if (hall)
+                for (int v = 0; v < 3; ++v) jc[v] = Jc[b][v * q.ncell + c];
+              phys_flux(G.ph, d, u, w, f, cmax[d], hall ? jc : nullptr);
               for (int v = 0; v < nv; ++v) {
                 Fp[v * len + (m + NG)] = T(0.5) * (f[v] + cmax[d] * u[v]);
                 Fm[v * len + (m + NG)] = T(0.5) * (f[v] - cmax[d] * u[v]);
@@ -720,6 +795,9 @@ double orc_lim03_grad(const double* f, double dx, double* grad) {
 }
 
 // Reconstruction of the following rhs / run / jvp calls: 0 MP5, 1 LIM03.
+// Hall parameter eta_h of the following MHD calls (0: ideal MHD).
+void orc_set_hall(double eta_h) { g_eta_h = eta_h; }
+
 // Test hook: radius r of LIM03's asymptotic region (default 1).
 void orc_set_lim03_radius(double r) { LIM03_RADIUS = r; }
 
@@ -753,6 +831,15 @@ int orc_flux_glm(int ndim, double gamma, int d, double ch, const double* u, doub
   Prim<double> w;
   bool ok = cons_to_prim(ph, u, w);
   phys_flux(ph, d, u, w, f, ch);
+  return ok ? ORC_OK : ORC_ERR_NONPHYSICAL;
+}
+
+// MHD flux with the Hall terms (reading R9) for a given current J[3].
+int orc_flux_hall(int ndim, double gamma, double eta_h, int d, const double* u, const double* J, double* f) {
+  Phys ph; ph.ndim = ndim; ph.mhd = 1; ph.gamma = gamma; ph.eta_h = eta_h;
+  Prim<double> w;
+  bool ok = cons_to_prim(ph, u, w);
+  phys_flux(ph, d, u, w, f, 0.0, J);
   return ok ? ORC_OK : ORC_ERR_NONPHYSICAL;
 }
 

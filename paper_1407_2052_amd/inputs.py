@@ -394,6 +394,45 @@ def circular_alfven(ndim: int, N: int, block: Optional[int] = None, amp: float =
     return sample_blocks(ndim, 2 if glm else True, gamma, n, dx, xlo, nbr, f)
 
 
+def alfven_whistler(ndim: int, N: int, d: float, branch: int = -1, kvec: Tuple[int, int, int] = (1, 0, 0),
+                    block: Optional[int] = None, amp: float = 0.1, B0: float = 1.0, p0: float = 0.1,
+                    gamma: float = 5.0 / 3.0):
+    """Circularly polarised Alfven-whistler wave of Hall MHD (Sect. 4.5.3)
+    with rho = 1, ion inertial length d (= eta_h at rho = 1), along the wave
+    vector 2 pi kvec on the periodic unit box.  In the frame (k, e1, e2) the
+    transverse field b = b1 + i b2 = amp exp(i(k.x - w t)) and velocity
+    u = -(|k| B0 / w) b solve Hall MHD exactly; w = |k| v with v = B0 (-d|k|/2
+    + branch sqrt(1 + (d|k|/2)^2)): branch +1 the ion-cyclotron branch
+    (w > 0), -1 the whistler branch (w < 0, phase speed B0/2 (d|k| +
+    sqrt(4 + d^2 |k|^2)) in magnitude).  Returns (BlockSet at t = 0, v,
+    period 1 / (|kvec| |v|))."""
+    kv = np.array(kvec, np.float64)[:ndim]
+    kn = float(np.linalg.norm(kv))
+    K = 2 * math.pi * kn
+    khat = np.zeros(3); khat[:ndim] = kv / kn
+    trial = np.array([0.0, 0.0, 1.0]) if abs(khat[2]) < 0.9 else np.array([1.0, 0.0, 0.0])
+    e1 = np.cross(trial, khat); e1 /= np.linalg.norm(e1)
+    e2 = np.cross(khat, e1)
+    v = B0 * (-d * K / 2 + branch * math.sqrt(1 + (d * K / 2) ** 2))
+    om = K * v
+    n, dx, xlo, nbr, _ = uniform_blocks(ndim, [N] * ndim, [block or N] * ndim)
+
+    def f(X, Y, Z):
+        shape = np.broadcast_shapes(X.shape, Y.shape, Z.shape)
+        xs = [X, Y, Z]
+        ph = np.zeros(shape)
+        for q in range(ndim):
+            ph = ph + 2 * math.pi * kvec[q] * xs[q]
+        b1, b2 = amp * np.cos(ph), amp * np.sin(ph)
+        c = -(K * B0 / om)
+        B = [B0 * khat[q] + b1 * e1[q] + b2 * e2[q] for q in range(3)]
+        V = [c * (b1 * e1[q] + b2 * e2[q]) for q in range(3)]
+        one = np.ones(shape)
+        return {"rho": one, "p": p0 * one, "vx": V[0] * one, "vy": V[1] * one, "vz": V[2] * one,
+                "Bx": B[0] * one, "By": B[1] * one, "Bz": B[2] * one}
+    return sample_blocks(ndim, True, gamma, n, dx, xlo, nbr, f), v, 1.0 / (kn * abs(v))
+
+
 def as_glm(bs: BlockSet, psi: float = 0.0) -> BlockSet:
     """The MHD block list `bs` as a GLM-MHD list (Sect. 4.2): the same eight
     variables and a ninth, psi, set to `psi` everywhere (ghosts included)."""
