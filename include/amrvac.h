@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define AMRVAC_ABI_VERSION 2
+#define AMRVAC_ABI_VERSION 3
 #define AMRVAC_NGHOST 3
 
 typedef enum {
@@ -107,7 +107,23 @@ typedef struct {
   double gamma;    /* ratio of specific heats, finite and > 1       */
   int exec;        /* amrvac_exec                                   */
   int recon;       /* amrvac_recon (added in ABI version 2)         */
+  double eta_h;    /* Hall parameter (ABI version 3): 0 = ideal MHD;
+                      > 0 only with AMRVAC_MHD, see below            */
 } amrvac_config;
+
+/* Hall MHD (Sect. 4.4, conservative Hall MHD in finite differences, eta = 0,
+ * B0 = 0), selected by eta_h > 0 with AMRVAC_MHD:
+ *  * before every evaluation of L the cell-centred current J = curl B is
+ *    computed at every interior cell by fourth-order central differences
+ *    along each active direction, (-B[i+2] + 8 B[i+1] - 8 B[i-1] + B[i-2]) /
+ *    (12 dx); halo cells use their face neighbour's J, so every face of
+ *    every block must have a neighbour (set_blocks refuses fixed faces);
+ *  * the flux of B gains (eta_h/rho)(B_d J - J_d B) and that of E gains
+ *    (eta_h/rho)((J.B) B_d - B^2 J_d);
+ *  * the speed of every cell along d is |v_d| + max(c_f,d, eta_h |B| k_max /
+ *    rho) with k_max = pi max_d 1/dx_d of the cell's block, in c_max (split
+ *    and time step, which then scales with dx^2);
+ *  * amrvac_ssprk_adjoint refuses it (AMRVAC_ERR_UNSUPPORTED). */
 
 typedef struct {
   double *u;       /* device; padded conserved state (layout above)     */

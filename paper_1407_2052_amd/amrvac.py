@@ -22,7 +22,7 @@ RK3, SSPRK43, SSPRK54 = 0, 1, 2
 EXEC_PER_BLOCK, EXEC_BATCHED = 0, 1
 MP5, LIM03 = 0, 1
 NGHOST = 3
-ABI_VERSION = 2
+ABI_VERSION = 3
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NONPHYSICAL", 5: "UNSUPPORTED"}
 
 # Entry points declared in include/amrvac.h.
@@ -48,7 +48,7 @@ class AmrvacError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("physics", ctypes.c_int), ("gamma", ctypes.c_double),
-                ("exec", ctypes.c_int), ("recon", ctypes.c_int)]
+                ("exec", ctypes.c_int), ("recon", ctypes.c_int), ("eta_h", ctypes.c_double)]
 
 
 class Block(ctypes.Structure):
@@ -142,7 +142,7 @@ class Context:
     """One amrvac context bound to torch's current HIP stream."""
 
     def __init__(self, ndim: int, mhd: bool, gamma: float, exec: int = EXEC_BATCHED, stream=None,
-                 recon: int = MP5):
+                 recon: int = MP5, eta_h: float = 0.0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("amrvac.Context needs a HIP device")
@@ -151,7 +151,7 @@ class Context:
         self.physics = physics_of(mhd)
         self.nvar = {HD: 2 + ndim, MHD: 8, GLM: 9}[self.physics]
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        cfg = Config(ndim, self.physics, gamma, exec, recon)
+        cfg = Config(ndim, self.physics, gamma, exec, recon, eta_h)
         h = ctypes.c_void_p()
         st = lib().amrvac_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
                                  ctypes.byref(h))
@@ -273,9 +273,9 @@ def device_blocks(bs, device="cuda"):
     return flat, views
 
 
-def context_for(bs, exec: int = EXEC_BATCHED, device="cuda", recon: int = MP5):
+def context_for(bs, exec: int = EXEC_BATCHED, device="cuda", recon: int = MP5, eta_h: float = 0.0):
     """Context + device copy of a BlockSet (returns ctx, flat, views)."""
     flat, views = device_blocks(bs, device)
-    ctx = Context(bs.ndim, bs.mhd, bs.gamma, exec, recon=recon)
+    ctx = Context(bs.ndim, bs.mhd, bs.gamma, exec, recon=recon, eta_h=eta_h)
     ctx.set_blocks(views, bs.n, bs.dx, bs.xlo, bs.nbr)
     return ctx, flat, views

@@ -159,6 +159,7 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
     return ctx_fail(c, AMRVAC_ERR_INVALID, "ssprk_adjoint: invalid scheme, nsteps, ckpt_every or dt");
   if (c->n_active < nb) return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: some blocks are passive");
   if (c->cfg.physics == AMRVAC_GLM) return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: GLM is not supported");
+  if (c->cfg.eta_h > 0.0) return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: Hall MHD is not supported");
   for (int b = 0; b < nb; ++b)
     for (int d = 0; d < c->cfg.ndim; ++d) {
       if (c->hb[b].nbr[2 * d] < 0 || c->hb[b].nbr[2 * d + 1] < 0)

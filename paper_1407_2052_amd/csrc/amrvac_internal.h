@@ -90,6 +90,11 @@ struct StageParams {
   double* const* rhs_out;
   // GLM: multiply psi by the step's decay factor (last stage of a step)
   int decay_psi;
+  // Hall MHD: eta_h and the cell-centred current of the input state, three
+  // planes of interior cells (plane v at J + v * jplane, block at coff)
+  double eta_h;
+  const double* J;
+  long long jplane;
   // Optional (only the code-emitting kernels write it): linear-piece codes
   // of the reconstructions (MP5 or LIM03) of L(in), one byte per
   // (direction, cell, variable) for the
@@ -109,6 +114,7 @@ struct CmaxParams {
   double gamma;
   int in;
   int slot;
+  double eta_h;         // Hall MHD: the whistler speed enters c_max
 };
 
 constexpr int MAX_TERMS = 6;

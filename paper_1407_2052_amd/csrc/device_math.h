@@ -110,6 +110,25 @@ __device__ __forceinline__ void load_cell_vars(const StateTable& st, int blk, in
   for (int v = 0; v < VN; ++v) u[v] = p[(V0 + v) * vs];
 }
 
+// Value of plane v of a per-cell array (interior layout, block at coff, plane
+// stride `plane`) at cell (i,j,k) of block blk, where only coordinate D may
+// lie outside the block: then the face neighbour's cell (its face must
+// exist).
+template <int D>
+__device__ __forceinline__ double load_plane(const StateTable& st, const double* a, long long plane, int v, int blk,
+                                             int i, int j, int k) {
+  const BlockDev* B = &st.blocks[blk];
+  int c[3] = {i, j, k};
+  if (c[D] < 0) {
+    B = &st.blocks[B->nbr[2 * D]];
+    c[D] += B->n[D];
+  } else if (c[D] >= B->n[D]) {
+    c[D] -= B->n[D];
+    B = &st.blocks[B->nbr[2 * D + 1]];
+  }
+  return a[v * plane + B->coff + ((long long)c[2] * B->n[1] + c[1]) * B->n[0] + c[0]];
+}
+
 // ---------------------------------------------------------------------------
 // Physics: primitive recovery, flux along D, fast speed.
 // ---------------------------------------------------------------------------
@@ -166,6 +185,13 @@ __device__ __forceinline__ void phys_flux(const double* u, const PrimD& w, doubl
 #pragma unroll
     for (int k = 0; k < 3; ++k) F[5 + k] = (k == D) ? 0.0 : fma(vd, w.B[k], -(Bd * w.v[k]));
   }
+}
+
+// Hall MHD: the fast whistler speed eta_h |B| k_max / rho at k_max = pi
+// max_d 1/dx_d of the block (Sect. 4.4).
+__device__ __forceinline__ double whistler_speed(const PrimD& w, double eta_h, double kmax) {
+  const double babs = sqrt(w.B[0] * w.B[0] + w.B[1] * w.B[1] + w.B[2] * w.B[2]);
+  return eta_h * babs / w.rho * kmax;
 }
 
 // Fast magnetosonic speed along d (sound speed for hydro).

@@ -44,8 +44,9 @@ namespace amrvac {
 // Fused stage kernel.
 // ---------------------------------------------------------------------------
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
-          bool RUNS = false, bool LIM = false, bool GLM = false>
+          bool RUNS = false, bool LIM = false, bool GLM = false, bool HALL = false>
 __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
+  static_assert(!HALL || (MHD && !GLM), "Hall terms are built for ideal MHD");
   // halo of the extended box: MP5 reaches 3 cells, LIM03 2
   constexpr int HG = LIM ? 2 : NG;
   using E = Eq<NDIM, MHD, GLM>;
@@ -155,6 +156,19 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
             if constexpr (GLM) {
               F[5 + D] += u[8];             // psi on the flux of B_D
               F[8] = (c * c) * u[5 + D];    // c_h^2 B_D
+            }
+            if constexpr (HALL) {
+              // (eta_h/rho)(B_D J - J_D B) on B, (eta_h/rho)((J.B) B_D - B^2 J_D) on E
+              double Jc[3];
+#pragma unroll
+              for (int v = 0; v < 3; ++v) Jc[v] = load_plane<D>(st, P.J, P.jplane, v, tl.block, cc[0], cc[1], cc[2]);
+              const double h = P.eta_h / w.rho;
+              const double jb = Jc[0] * w.B[0] + Jc[1] * w.B[1] + Jc[2] * w.B[2];
+              const double bb = w.B[0] * w.B[0] + w.B[1] * w.B[1] + w.B[2] * w.B[2];
+              const double Bd = w.B[D];
+#pragma unroll
+              for (int k = 0; k < 3; ++k) F[5 + k] = F[5 + k] + h * (Bd * Jc[k] - Jc[D] * w.B[k]);
+              F[4] = F[4] + h * (jb * Bd - bb * Jc[D]);
             }
             const int el = a[0] + E0P * (a[1] + E1 * a[2]);
 #pragma unroll
@@ -418,8 +432,17 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
       if (P.cm_out >= 0) {
         PrimD w;
         ok_all = prim<NDIM, MHD>(un, gamma, w) && ok_all;
+        if constexpr (HALL) {
+          double km = B.inv_dx[0];
 #pragma unroll
-        for (int d = 0; d < NDIM; ++d) run[d] = fmax(run[d], fabs(w.v[d]) + fast_speed<MHD>(w, d, gamma));
+          for (int d = 1; d < NDIM; ++d) km = fmax(km, B.inv_dx[d]);
+          const double wh = whistler_speed(w, P.eta_h, M_PI * km);
+#pragma unroll
+          for (int d = 0; d < NDIM; ++d) run[d] = fmax(run[d], fabs(w.v[d]) + fmax(fast_speed<MHD>(w, d, gamma), wh));
+        } else {
+#pragma unroll
+          for (int d = 0; d < NDIM; ++d) run[d] = fmax(run[d], fabs(w.v[d]) + fast_speed<MHD>(w, d, gamma));
+        }
       }
     }
   }
@@ -473,8 +496,14 @@ __global__ void __launch_bounds__(256) k_cmax(CmaxParams P) {
       for (int v = 0; v < NV; ++v) u[v] = p[v * vs];
       PrimD w;
       ok_all = prim<NDIM, MHD>(u, P.gamma, w) && ok_all;
+      double wh = 0.0;   // Hall MHD: fast whistler at k_max of the block
+      if (MHD && P.eta_h != 0.0) {
+        double km = B.inv_dx[0];
+        for (int d = 1; d < NDIM; ++d) km = fmax(km, B.inv_dx[d]);
+        wh = whistler_speed(w, P.eta_h, M_PI * km);
+      }
 #pragma unroll
-      for (int d = 0; d < NDIM; ++d) run[d] = fmax(run[d], fabs(w.v[d]) + fast_speed<MHD>(w, d, P.gamma));
+      for (int d = 0; d < NDIM; ++d) run[d] = fmax(run[d], fabs(w.v[d]) + fmax(fast_speed<MHD>(w, d, P.gamma), wh));
     }
   }
 #pragma unroll
@@ -551,6 +580,47 @@ __global__ void __launch_bounds__(256) k_copy_interior(StateTable st, const Tile
   }
 }
 
+// Cell-centred current J = curl B of buffer `in` at every interior cell of
+// the tile list, by fourth-order central differences (Sect. 4.4, eq. jcd4
+// at cell centres) along each active direction; halos from the face
+// neighbours (every face must have one).  Plane v of J at J + v * jplane.
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_current(StateTable st, const Tile* tiles, int ntiles, int tx, int ty, int tz,
+                                               int in, double* J, long long jplane) {
+  const int tcells = tx * ty * tz;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Tile tl = tiles[t];
+    const BlockDev& B = st.blocks[tl.block];
+    for (int c = threadIdx.x; c < tcells; c += 256) {
+      const int i = tl.o[0] + c % tx, j = tl.o[1] + (c / tx) % ty, k = tl.o[2] + c / (tx * ty);
+      if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
+      double dB[3][3];   // dB[a][q] = d B_q / d x_a
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) dB[a][q] = 0.0;
+      static_for<0, NDIM>([&](auto Ac) {
+        constexpr int A = decltype(Ac)::value;
+        double b[5][3];
+#pragma unroll
+        for (int s = -2; s <= 2; ++s) {
+          if (s == 0) continue;
+          int cc[3] = {i, j, k};
+          cc[A] += s;
+          load_cell_vars<5, 3, A>(st, tl.block, in, cc[0], cc[1], cc[2], b[s + 2]);
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          dB[A][q] = (-1.0 * b[4][q] + 8.0 * b[3][q] - 8.0 * b[1][q] + b[0][q]) / (12.0 * B.dx[A]);
+      });
+      const long long o = B.coff + ((long long)k * B.n[1] + j) * B.n[0] + i;
+      J[o] = dB[1][2] - dB[2][1];
+      J[jplane + o] = dB[2][0] - dB[0][2];
+      J[2 * jplane + o] = dB[0][1] - dB[1][0];
+    }
+  }
+}
+
 // Divergence of B by fourth-order central differences along each active
 // direction (the monitor of Sect. 4.5.1), at every interior cell of the tile
 // list, from buffer `in` with face neighbours' interiors (or fixed ghost
@@ -614,43 +684,49 @@ __global__ void k_clear_slot(Control* ctl, int slot) {
 // Variant table.
 // ---------------------------------------------------------------------------
 struct StageVariant {
-  int ndim, mhd, rec, tx, ty, tz, nt, ngrp, wpe;
+  int ndim, mhd, rec, hall, tx, ty, tz, nt, ngrp, wpe;
   const void* fn;
   void (*launch)(const StageParams&, int grid, hipStream_t);
   const char* name;
 };
 
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
-          bool RUNS = false, bool LIM = false, bool GLM = false>
+          bool RUNS = false, bool LIM = false, bool GLM = false, bool HALL = false>
 static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE, EMIT, RUNS, LIM, GLM>), dim3(grid), dim3(NT),
-                     0, s, p);
+  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE, EMIT, RUNS, LIM, GLM, HALL>), dim3(grid),
+                     dim3(NT), 0, s, p);
 }
 
 // rec: the reconstruction (0 MP5, 1 LIM03)
 #define AMRVAC_VARIANT(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                          \
-  {ND, M, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE>, \
+  {ND, M, 0, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE>, \
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE}
 // the same with interfaces evaluated in runs along each pencil
 #define AMRVAC_VARIANT_R(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                     \
-  {ND, M, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>, \
+  {ND, M, 0, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>, \
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs"}
 // GLM-MHD (physics code 2), MP5 or LIM03 (REC), in runs along each pencil
 #define AMRVAC_VARIANT_G(ND, REC, TX, TY, TZ, NT, NGRP, WPE)                                                    \
-  {ND, 2, REC, TX, TY, TZ, NT, NGRP, WPE,                                                                       \
+  {ND, 2, REC, 0, TX, TY, TZ, NT, NGRP, WPE,                                                                       \
    (const void*)&k_stage<ND, true, TX, TY, TZ, NT, NGRP, WPE, false, true, (REC == 1), true>,                  \
    &launch_stage<ND, true, TX, TY, TZ, NT, NGRP, WPE, false, true, (REC == 1), true>,                          \
    #ND "d-glm-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-rec" #REC}
+// Hall MHD (physics MHD, eta_h > 0), MP5 or LIM03 (REC), in runs along each pencil
+#define AMRVAC_VARIANT_H(ND, REC, TX, TY, TZ, NT, NGRP, WPE)                                                   \
+  {ND, 1, REC, 1, TX, TY, TZ, NT, NGRP, WPE,                                                                   \
+   (const void*)&k_stage<ND, true, TX, TY, TZ, NT, NGRP, WPE, false, true, (REC == 1), false, true>,          \
+   &launch_stage<ND, true, TX, TY, TZ, NT, NGRP, WPE, false, true, (REC == 1), false, true>,                  \
+   #ND "d-hall-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-rec" #REC}
 // LIM03 reconstruction in runs along each pencil
 #define AMRVAC_VARIANT_LR(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                         \
-  {ND, M, 1, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true, true>, \
+  {ND, M, 1, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true, true>, \
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-lim03"}
 // LIM03 reconstruction
 #define AMRVAC_VARIANT_L(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                            \
-  {ND, M, 1, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, false, true>, \
+  {ND, M, 1, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, false, true>, \
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, false, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-lim03"}
 
@@ -728,6 +804,14 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT_G(2, 1, 16, 16, 1, 256, 2, 2),
     AMRVAC_VARIANT_G(3, 1, 8, 8, 4, 256, 2, 1),
     AMRVAC_VARIANT_G(3, 1, 8, 8, 4, 256, 2, 3),
+    // Hall MHD
+    AMRVAC_VARIANT_H(1, 0, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT_H(2, 0, 16, 16, 1, 256, 2, 2),
+    AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 2),
+    AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 1),
+    AMRVAC_VARIANT_H(1, 1, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT_H(2, 1, 16, 16, 1, 256, 2, 2),
+    AMRVAC_VARIANT_H(3, 1, 8, 8, 4, 256, 2, 1),
 };
 
 const StageVariant* stage_variants(int* count) {
@@ -738,11 +822,11 @@ const StageVariant* stage_variants(int* count) {
 // Code-emitting stage kernels (the adjoint's forward recompute), one per
 // (ndim, physics); their tile shapes match the adjoint kernels'.
 #define AMRVAC_EMIT(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                          \
-  {ND, M, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true>, \
+  {ND, M, 0, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true>, \
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-emit"}
 #define AMRVAC_EMIT_L(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                             \
-  {ND, M, 1, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true, true>, \
+  {ND, M, 1, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true, true>, \
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-lim03-emit"}
 
@@ -791,6 +875,14 @@ void launch_copy_interior(const StateTable& st, const Tile* tiles, int ntiles, i
                           int src, int dst, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_interior, dim3(grid), dim3(256), 0, s, st, tiles, ntiles, tx, ty, tz, nv, src,
                      dst);
+}
+
+void launch_current(int ndim, const StateTable& st, const Tile* tiles, int ntiles, int tx, int ty, int tz, int in,
+                    double* J, long long jplane, int grid, hipStream_t s) {
+  if (ntiles <= 0) return;
+  if (ndim == 1) hipLaunchKernelGGL(k_current<1>, dim3(grid), dim3(256), 0, s, st, tiles, ntiles, tx, ty, tz, in, J, jplane);
+  if (ndim == 2) hipLaunchKernelGGL(k_current<2>, dim3(grid), dim3(256), 0, s, st, tiles, ntiles, tx, ty, tz, in, J, jplane);
+  if (ndim == 3) hipLaunchKernelGGL(k_current<3>, dim3(grid), dim3(256), 0, s, st, tiles, ntiles, tx, ty, tz, in, J, jplane);
 }
 
 void launch_divb(int ndim, const StateTable& st, const Tile* tiles, int ntiles, int tx, int ty, int tz, int in,

@@ -56,6 +56,8 @@ static void free_tables(amrvac_ctx* c) {
   if (c->d_rhs_ptrs) (void)hipFree(c->d_rhs_ptrs);
   if (c->d_ptiles) (void)hipFree(c->d_ptiles);
   if (c->d_divb_ptrs) (void)hipFree(c->d_divb_ptrs);
+  if (c->d_J) (void)hipFree(c->d_J);
+  c->d_J = nullptr;
   if (c->d_divb_sum) (void)hipFree(c->d_divb_sum);
   c->d_divb_ptrs = nullptr;
   c->d_divb_sum = nullptr;
@@ -89,7 +91,9 @@ static int count_variants(const amrvac_ctx* c) {
   int nv = 0, k = 0;
   const StageVariant* v = stage_variants(&nv);
   for (int i = 0; i < nv; ++i)
-    if (v[i].ndim == c->cfg.ndim && v[i].mhd == c->cfg.physics && v[i].rec == c->cfg.recon) ++k;
+    if (v[i].ndim == c->cfg.ndim && v[i].mhd == c->cfg.physics && v[i].rec == c->cfg.recon &&
+        v[i].hall == (c->cfg.eta_h > 0.0))
+      ++k;
   return k;
 }
 
@@ -98,7 +102,8 @@ static const StageVariant* pick_variant(const amrvac_ctx* c, int want) {
   const StageVariant* v = stage_variants(&nv);
   int k = 0;
   for (int i = 0; i < nv; ++i) {
-    if (v[i].ndim == c->cfg.ndim && v[i].mhd == c->cfg.physics && v[i].rec == c->cfg.recon) {
+    if (v[i].ndim == c->cfg.ndim && v[i].mhd == c->cfg.physics && v[i].rec == c->cfg.recon &&
+        v[i].hall == (c->cfg.eta_h > 0.0)) {
       if (k == want) return &v[i];
       ++k;
     }
@@ -174,11 +179,6 @@ static amrvac_status build_tiles(amrvac_ctx* c) {
   HIP_TRY(c, hipMemcpyAsync(c->d_tiles, c->htiles.data(), sizeof(Tile) * c->htiles.size(),
                             hipMemcpyHostToDevice, c->stream));
   if (c->d_ptiles) (void)hipFree(c->d_ptiles);
-  if (c->d_divb_ptrs) (void)hipFree(c->d_divb_ptrs);
-  if (c->d_divb_sum) (void)hipFree(c->d_divb_sum);
-  c->d_divb_ptrs = nullptr;
-  c->d_divb_sum = nullptr;
-  c->divb_cap = 0;
   c->d_ptiles = nullptr;
   if (!c->hptiles.empty()) {
     HIP_TRY(c, hipMalloc(&c->d_ptiles, sizeof(Tile) * c->hptiles.size()));
@@ -366,11 +366,27 @@ static StageParams make_params(const amrvac_ctx* c, const Recipe& r, int cm_in, 
   p.sb = r.sb;
   p.sdst = r.sdst;
   p.rhs_out = nullptr;
+  p.eta_h = c->cfg.eta_h;
+  p.J = c->d_J;
+  p.jplane = c->total_cells;
   return p;
+}
+
+// Hall MHD: the current of buffer `buf` on every interior cell (active and
+// passive blocks), before a stage reads it.
+static void launch_current_of(amrvac_ctx* c, int buf, hipStream_t s) {
+  if (!(c->cfg.eta_h > 0.0)) return;
+  const StateTable st = state_table(c);
+  const int nt = (int)c->htiles.size(), np = (int)c->hptiles.size();
+  launch_current(c->cfg.ndim, st, c->d_tiles, nt, c->var->tx, c->var->ty, c->var->tz, buf, c->d_J, c->total_cells,
+                 std::max(1, std::min(nt, c->ncu * 8)), s);
+  launch_current(c->cfg.ndim, st, c->d_ptiles, np, c->var->tx, c->var->ty, c->var->tz, buf, c->d_J, c->total_cells,
+                 std::max(1, std::min(np, c->ncu * 8)), s);
 }
 
 // Launch one stage in the context's execution form.
 static void launch_stage(amrvac_ctx* c, StageParams p, int exec, hipStream_t s) {
+  launch_current_of(c, p.in, s);
   if (exec == AMRVAC_EXEC_BATCHED) {
     c->var->launch(p, c->grid_batched, s);
     return;
@@ -403,6 +419,7 @@ void launch_cmax_of(amrvac_ctx* c, int buf, int slot, hipStream_t s) {
   q.gamma = c->cfg.gamma;
   q.in = buf;
   q.slot = slot;
+  q.eta_h = c->cfg.eta_h;
   launch_clear_slot(c->d_ctl, slot, s);
   int grid = (int)std::min<long long>((long long)c->ncu * 8, (long long)c->htiles.size());
   // psi enters no wave speed: GLM uses the MHD reduction
@@ -481,6 +498,7 @@ static bool config_ok(const amrvac_config* cfg) {
          (cfg->physics == AMRVAC_HD || cfg->physics == AMRVAC_MHD || cfg->physics == AMRVAC_GLM) &&
          (cfg->exec == AMRVAC_EXEC_PER_BLOCK || cfg->exec == AMRVAC_EXEC_BATCHED) &&
          (cfg->recon == AMRVAC_MP5 || cfg->recon == AMRVAC_LIM03) &&
+         std::isfinite(cfg->eta_h) && cfg->eta_h >= 0.0 && (cfg->eta_h == 0.0 || cfg->physics == AMRVAC_MHD) &&
          std::isfinite(cfg->gamma) && cfg->gamma > 1.0;
 }
 
@@ -539,7 +557,7 @@ amrvac_status amrvac_create(const amrvac_config* cfg, void* hip_stream, amrvac_c
     return AMRVAC_ERR_INVALID;
   }
   if (!config_ok(cfg)) {
-    g_noctx_error = "amrvac_create: invalid config (ndim 1..3, physics HD/MHD/GLM, exec, recon, gamma > 1)";
+    g_noctx_error = "amrvac_create: invalid config (ndim 1..3, physics HD/MHD/GLM, exec, recon, gamma > 1, eta_h >= 0 with MHD only)";
     return AMRVAC_ERR_INVALID;
   }
   amrvac_ctx* c = new amrvac_ctx();
@@ -569,7 +587,7 @@ amrvac_status amrvac_validate_blocks(const amrvac_config* cfg, const amrvac_bloc
   std::string m;
   amrvac_status st = AMRVAC_OK;
   if (!config_ok(cfg)) {
-    m = "invalid config (ndim 1..3, physics HD/MHD/GLM, exec, recon, gamma > 1)";
+    m = "invalid config (ndim 1..3, physics HD/MHD/GLM, exec, recon, gamma > 1, eta_h >= 0 with MHD only)";
     st = AMRVAC_ERR_INVALID;
   } else if (!blocks_ok(cfg->ndim, blocks, nblocks, m)) {
     st = AMRVAC_ERR_INVALID;
@@ -586,6 +604,11 @@ amrvac_status amrvac_set_blocks(amrvac_ctx* c, const amrvac_block* blocks, int n
   {
     std::string m;
     if (!blocks_ok(nd, blocks, nblocks, m)) return fail(c, AMRVAC_ERR_INVALID, "set_blocks: %s", m.c_str());
+    if (c->cfg.eta_h > 0.0)
+      for (int b = 0; b < nblocks; ++b)
+        for (int d = 0; d < nd; ++d)
+          if (blocks[b].nbr[2 * d] < 0 || blocks[b].nbr[2 * d + 1] < 0)
+            return fail(c, AMRVAC_ERR_INVALID, "set_blocks: Hall MHD needs a neighbour on every face (block %d)", b);
   }
   drop_graphs(c);
   free_tables(c);
@@ -621,6 +644,8 @@ amrvac_status amrvac_set_blocks(amrvac_ctx* c, const amrvac_block* blocks, int n
     }
   }
   c->total_cells = off / c->nvar;
+  if (c->cfg.eta_h > 0.0)   // Hall MHD: the current of every interior cell, three planes
+    HIP_TRY(c, hipMalloc(&c->d_J, sizeof(double) * 3 * (size_t)c->total_cells));
   c->slot_stride = (off + 31) / 32 * 32;
   c->ndx = (int)(dxt.size() / 3);
   HIP_TRY(c, hipMalloc(&c->d_blocks, sizeof(BlockDev) * nblocks));

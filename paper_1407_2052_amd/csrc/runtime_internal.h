@@ -11,7 +11,7 @@
 namespace amrvac {
 
 struct StageVariant {
-  int ndim, mhd, rec, tx, ty, tz, nt, ngrp, wpe;   // rec: 0 MP5, 1 LIM03
+  int ndim, mhd, rec, hall, tx, ty, tz, nt, ngrp, wpe;   // mhd: physics code; rec: 0 MP5, 1 LIM03
   const void* fn;
   void (*launch)(const StageParams&, int grid, hipStream_t);
   const char* name;
@@ -20,6 +20,8 @@ const StageVariant* stage_variants(int* count);
 // Code-emitting stage kernel for (ndim, physics), or nullptr.
 const StageVariant* emit_variant(int ndim, int mhd, int rec);
 void launch_cmax(int ndim, int mhd, const CmaxParams& p, int grid, hipStream_t s);
+void launch_current(int ndim, const StateTable& st, const Tile* tiles, int ntiles, int tx, int ty, int tz, int in,
+                    double* J, long long jplane, int grid, hipStream_t s);
 void launch_divb(int ndim, const StateTable& st, const Tile* tiles, int ntiles, int tx, int ty, int tz, int in,
                  double* const* out, double* tsum, double* total, int grid, hipStream_t s);
 void launch_step_begin(Control* ctl, const double* dxtab, int ndim, int glm, int clear_lo, int clear_hi,
@@ -88,6 +90,7 @@ struct amrvac_ctx {
   double** d_divb_ptrs = nullptr;
   std::vector<double*> hdivb;
   double* d_divb_sum = nullptr;   // divb_cap doubles (tiles + 1)
+  double* d_J = nullptr;          // Hall MHD: current, 3 planes of total_cells
   int divb_cap = 0;
 
   std::map<int, GraphEntry> graphs;

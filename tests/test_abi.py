@@ -53,7 +53,9 @@ def test_create_rejects_invalid_config_without_device():
                 A.Config(2, 7, 1.4, A.EXEC_BATCHED), A.Config(2, A.HD, 1.0, A.EXEC_BATCHED),
                 A.Config(2, A.HD, float("nan"), A.EXEC_BATCHED), A.Config(2, A.HD, 1.4, 9),
                 A.Config(2, A.HD, 1.4, A.EXEC_BATCHED, 2), A.Config(2, A.HD, 1.4, A.EXEC_BATCHED, -1),
-                A.Config(2, 3, 1.4, A.EXEC_BATCHED)):
+                A.Config(2, 3, 1.4, A.EXEC_BATCHED), A.Config(2, A.HD, 1.4, A.EXEC_BATCHED, 0, 0.1),
+                A.Config(2, A.GLM, 1.4, A.EXEC_BATCHED, 0, 0.1), A.Config(2, A.MHD, 1.4, A.EXEC_BATCHED, 0, -1.0),
+                A.Config(2, A.MHD, 1.4, A.EXEC_BATCHED, 0, float("inf"))):
         assert L.amrvac_create(ctypes.byref(cfg), None, ctypes.byref(h)) == A.ERR_INVALID
         assert h.value is None
     assert b"invalid config" in L.amrvac_last_error(None)

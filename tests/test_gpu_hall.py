@@ -1,0 +1,155 @@
+"""GPU parity of Hall MHD (Sect. 4.4: cell-centred current by fourth-order
+central differences, Hall terms in the fluxes of B and E, whistler-augmented
+speeds) through the C ABI against the oracle: right-hand sides, states after
+SSPRK(5,4) + MP5 and RK3 + LIM03 steps, bitwise equality of every tile shape
+and of both execution forms, the exact Alfven-whistler waves of Sect. 4.5.3
+at fourth order, and the refusals (fixed faces, adjoint)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_l1, strip_blocks
+from paper_1407_2052_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1407_2052_amd import amrvac as A  # noqa: E402
+from test_gpu_parity import compare_rhs, host_blocks  # noqa: E402
+
+ETA = 0.2
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def hall_oracle():
+    oracle.set_hall(ETA)
+    yield
+    oracle.set_hall(0.0)
+    oracle.set_recon(oracle.MP5)
+
+
+CASES = {
+    "whistler1d": lambda: inputs.alfven_whistler(1, 64, ETA, -1, block=16)[0],
+    "whistler2d": lambda: inputs.alfven_whistler(2, 32, ETA, -1, kvec=(1, 1, 0), block=16)[0],
+    "ragged2d": lambda: strip_blocks(2, True, [13, 19, 7], ny=21, seed=2),
+    "ragged3d": lambda: strip_blocks(3, True, [9, 12], ny=7, nz=5, seed=3),
+    "mhd3d": lambda: inputs.mhd_turbulence_3d(N=32, block=16, seed=5),
+    "min3_1d": lambda: strip_blocks(1, True, [3, 5, 3, 3, 8, 3], seed=6),
+    "min3_3d": lambda: strip_blocks(3, True, [3, 4, 3], ny=3, nz=3, seed=7),
+}
+
+
+def assert_state_parity(bs, out_g, out_o, tol=1e-11):
+    # relative L1 per variable; a variable the solution keeps at rounding
+    # level (the momentum along k in an Alfven-whistler wave) is compared on
+    # the scale of the whole state instead
+    nums, dens = zip(*[rel_l1(out_g.u, out_o.u, bs, v) for v in range(bs.nvar)])
+    total = sum(dens)
+    for v in range(bs.nvar):
+        assert nums[v] <= tol * max(dens[v], 1e-3 * total), (v, nums[v], dens[v], total)
+
+
+def gpu_ctx(bs, recon=A.MP5, exec=A.EXEC_BATCHED):
+    return A.context_for(bs, exec, recon=recon, eta_h=ETA)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_rhs_matches_oracle(case):
+    say(f"[hall rhs] {case}")
+    bs = CASES[case]()
+    Lo, cmo = oracle.rhs(bs)
+    ctx, flat, views = gpu_ctx(bs)
+    Lg, cmg = ctx.fd_rhs()
+    Lg = [x.cpu().numpy() for x in Lg]
+    ctx.close()
+    np.testing.assert_allclose(cmg[:bs.ndim], cmo[:bs.ndim], rtol=1e-14, atol=0)
+    compare_rhs(bs, Lg, Lo, cmo)
+
+
+STEP_CASES = [("whistler1d", 40), ("whistler2d", 20), ("ragged2d", 20), ("ragged3d", 10), ("mhd3d", 5),
+              ("min3_1d", 20), ("min3_3d", 8)]
+
+
+@pytest.mark.parametrize("recon", [oracle.MP5, oracle.LIM03], ids=["mp5", "lim03"])
+@pytest.mark.parametrize("case,nsteps", STEP_CASES, ids=[c for c, _ in STEP_CASES])
+def test_steps_match_oracle(case, nsteps, recon):
+    scheme = oracle.SSPRK54 if recon == oracle.MP5 else oracle.RK3
+    say(f"[hall steps] {case} recon={recon} n={nsteps}")
+    bs = CASES[case]()
+    oracle.set_recon(recon)
+    out_o, dts = oracle.run(bs, scheme, nsteps, cfl=0.4)
+    ctx, flat, views = gpu_ctx(bs, recon)
+    t = ctx.ssprk_step(scheme, nsteps, cfl=0.4, t=0.0)
+    out_g = bs.copy()
+    out_g.u = host_blocks(views)
+    ctx.close()
+    assert abs(t - dts.sum()) <= 1e-12 * dts.sum()
+    assert_state_parity(bs, out_g, out_o)
+
+
+@pytest.mark.parametrize("case", ["ragged2d", "ragged3d", "min3_3d", "min3_1d"])
+def test_every_tile_shape_and_both_exec_forms_are_bitwise_identical(case):
+    bs = CASES[case]()
+    ctx0, _, _ = gpu_ctx(bs)
+    names = ctx0.variants()
+    ctx0.close()
+    assert names and all("hall" in n for n in names)
+    ref = None
+    for i, name in enumerate(names + ["per-block"]):
+        say(f"[hall variant] {case} {name}")
+        ctx, flat, views = gpu_ctx(bs, exec=A.EXEC_PER_BLOCK if name == "per-block" else A.EXEC_BATCHED)
+        if name != "per-block":
+            ctx.set_variant(i)
+        t = ctx.ssprk_step(oracle.SSPRK54, 3, t=0.0)
+        got = (host_blocks(views), t)
+        ctx.close()
+        if ref is None:
+            ref = got
+            continue
+        assert got[1] == ref[1], name
+        for x, y in zip(got[0], ref[0]):
+            assert np.array_equal(x, y), name
+
+
+@pytest.mark.parametrize("branch", [+1, -1], ids=["ion_cyclotron", "whistler"])
+def test_alfven_whistler_wave_fourth_order_on_gpu(branch):
+    # Sect. 4.5.3: one period of the exact wave, oblique on a 2D grid
+    oracle.set_hall(0.1)
+    errs = []
+    for N in (32, 64, 128):
+        bs, v, T = inputs.alfven_whistler(2, N, 0.1, branch, kvec=(1, 1, 0), block=N // 2)
+        cm = oracle.cmax(bs)
+        dt0 = 0.4 / sum(cm[d] / bs.dx[0, d] for d in range(2))
+        n = int(math.ceil(T / dt0))
+        ctx, flat, views = A.context_for(bs, recon=A.MP5, eta_h=0.1)
+        ctx.ssprk_step(oracle.SSPRK54, n, dt=T / n, t=0.0)
+        out = host_blocks(views)
+        ctx.close()
+        errs.append(np.mean([np.abs(bs.interior(b, out[b]) - bs.interior(b)).mean() for b in range(bs.nb)]))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    say(f"[hall whistler] branch={branch} errors {errs} orders {orders}")
+    assert orders[-1] > 3.7 and errs[-1] < 1e-6, (errs, orders)
+
+
+def test_refusals():
+    with pytest.raises(A.AmrvacError) as e:
+        A.context_for(inputs.brio_wu(64), eta_h=ETA)   # fixed faces
+    assert e.value.status == A.ERR_INVALID
+    bs = CASES["ragged2d"]()
+    ctx, flat, views = gpu_ctx(bs)
+    lam = [torch.zeros_like(v) for v in views]
+    with pytest.raises(A.AmrvacError) as e:
+        ctx.ssprk_adjoint(oracle.SSPRK54, 1e-4, 1, 1, lam)
+    assert e.value.status == A.ERR_UNSUPPORTED
+    ctx.close()
