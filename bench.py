@@ -226,6 +226,8 @@ def main():
                     help="also time the adjoint with this checkpoint interval (0: no)")
     ap.add_argument("--adjoint-2d-steps", type=int, default=200,
                     help="steps of the 2D Euler adjoint leg")
+    ap.add_argument("--no-hall", action="store_true",
+                    help="skip the Hall-MHD leg on the 256^3 periodic list")
     ap.add_argument("--no-glm", action="store_true",
                     help="skip the GLM-MHD leg on the same block list")
     ap.add_argument("--no-lim03", action="store_true",
@@ -332,6 +334,35 @@ def main():
                "ms_per_step": 1e3 * elg / args.steps, "cell_updates_per_s": cells * args.steps / elg,
                "step_time_over_mhd": (1e3 * elg / args.steps) / ms_per_step}
 
+    hall = None
+    if not args.no_hall:
+        # Hall MHD needs neighbours on every face: the 256^3 periodic list,
+        # timed with eta_h = 0.01 and as ideal MHD
+        print("bench: Hall MHD (eta_h = 0.01) and ideal MHD on the 256^3 periodic list", file=sys.stderr, flush=True)
+        hbs = inputs.mhd_turbulence_3d()
+        hcells = hbs.interior_cells()
+        res = {}
+        for eta in (0.01, 0.0):
+            ctx, flat, views = amrvac.context_for(hbs, amrvac.EXEC_BATCHED, eta_h=eta)
+            hvar, _ = ctx.autotune(amrvac.SSPRK54, 2)
+            ctx.ssprk_step(amrvac.SSPRK54, args.warmup, cfl=0.4, t=None)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.ssprk_step(amrvac.SSPRK54, args.steps, cfl=0.4, t=None)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ctx.sync()
+            res[eta] = (e0.elapsed_time(e1) / args.steps, hvar)
+            ctx.close()
+            del flat, views
+        del hbs
+        hall = {"workload": "3D Hall MHD 256^3 periodic, 4096 x 16^3, eta_h = 0.01, SSPRK(5,4) + MP5",
+                "tile_shape": res[0.01][1], "steps": args.steps, "ms_per_step": res[0.01][0],
+                "cell_updates_per_s": hcells / (res[0.01][0] / 1e3),
+                "ideal_mhd_ms_per_step": res[0.0][0], "step_time_over_ideal": res[0.01][0] / res[0.0][0]}
+
     if args.copy_probe > 0:
         # a plain copy kernel of known size: FETCH_SIZE / WRITE_SIZE of this
         # dispatch calibrate the counters against bytes really moved
@@ -380,6 +411,7 @@ def main():
         "adjoint_2d_euler": adjoint_2d,
         "lim03": lim03,
         "glm": glm,
+        "hall": hall,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
