@@ -16,6 +16,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -44,11 +45,26 @@ PEAK_HBM_GBS = 8000.0
 STAGES = 5
 
 
-def kernel_source_hash():
+def strip_comments(src):
+    """C++ source without comments and with whitespace collapsed (comment
+    edits leave the code, and so the measurements taken on it, unchanged)."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
+def kernel_source_hash(read=None):
+    """Hash of the code (comments and whitespace aside) of the stage kernel
+    and the runtime that launches it."""
     h = hashlib.sha256()
     for f in ("kernels.hip", "device_math.h", "runtime.cpp", "amrvac_internal.h"):
-        with open(os.path.join(ROOT, "paper_1407_2052_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        path = os.path.join("paper_1407_2052_amd", "csrc", f)
+        if read is None:
+            with open(os.path.join(ROOT, path)) as fh:
+                src = fh.read()
+        else:
+            src = read(path)
+        h.update(strip_comments(src).encode())
     return h.hexdigest()[:16]
 
 

@@ -13,8 +13,8 @@
  *     (Sect. 2.3, Shu-Osher form; RK3, SSPRK(4,3), SSPRK(5,4)),
  *
  * for ideal hydrodynamics (Sect. 3, ideal-gas energy equation), ideal MHD
- * (Sects. 4.1 and 4.3 with B0 = 0, eta = eta_h = 0) and GLM-MHD (Sect. 4.2,
- * the glm3 variant).
+ * (Sects. 4.1 and 4.3 with B0 = 0, eta = eta_h = 0), GLM-MHD (Sect. 4.2, the
+ * glm3 variant) and Hall MHD (Sect. 4.4, eta_h > 0, eta = 0).
  *
  * Conventions shared by every call
  * --------------------------------

@@ -1,5 +1,6 @@
 // Device arithmetic shared by the forward stage kernel and the adjoint:
-// state addressing, primitive recovery, physical flux, fast speed and MP5.
+// state addressing, primitive recovery, physical flux, fast and whistler
+// speeds, MP5 and LIM03, tile geometry and the XCD-aware tile schedule.
 // Sharing one definition makes the adjoint's recompute of the forward pass
 // bitwise identical to the forward pass (no automatic FMA contraction; every
 // fused multiply-add is explicit).

@@ -2,23 +2,28 @@
 // of Porth et al. (2014), Sect. 2:
 //   * k_stage: one fused Shu-Osher stage (Sect. 2.3) on tiles of blocks:
 //     halo load -> primitive recovery -> physical flux -> global
-//     Lax-Friedrichs split (Sect. 2.2) -> MP5 of F+ (left-biased) and F-
-//     (right-biased) -> interface flux -> conservative difference (Sect.
-//     2.1, eq. fdcons) -> stage combination -> |v_d| + c_f,d of the new
-//     state for the next stage's c_max;
+//     Lax-Friedrichs split (Sect. 2.2) -> MP5 or LIM03 of F+ (left-biased)
+//     and F- (right-biased) -> interface flux -> conservative difference
+//     (Sect. 2.1, eq. fdcons) -> stage combination -> |v_d| + c_f,d of the
+//     new state for the next stage's c_max.  Template flags select LIM03,
+//     GLM-MHD (Sect. 4.2, glm3) and Hall MHD (Sect. 4.4), and the
+//     code-emitting form of the adjoint's recompute;
 //   * k_cmax: c_max of a state (Sect. 2.2);
 //   * k_step_begin: dt from c_max (multi-D form of the Sect. 4.4 bound),
-//     t accumulation and c_max slot resets, so a whole step runs without
-//     a host round trip.
+//     t accumulation, the GLM decay factor and c_max slot resets, so a
+//     whole step runs without a host round trip;
+//   * k_current: the cell-centred current of Hall MHD (Sect. 4.4);
+//   * k_divb, k_sum_fixed: the div B monitor of Sect. 4.5.1.
 //
 // Work decomposition.  A tile is a TX x TY x TZ box of one block's interior;
 // one work-group owns one tile at a time and loops over tiles (persistent
 // grid).  Per direction d and per group of variables the work-group
-//   A) computes F+ and F- for the tile extended by 3 cells along d (halo
-//      cells come from the neighbour's interior or the fixed ghost layers)
-//      into LDS,
-//   B) evaluates MP5(F+) + MP5(F-) for every (interface, variable) of the
-//      tile (T_d + 1 interfaces per pencil) into registers, then LDS,
+//   A) computes F+ and F- for the tile extended by 3 cells along d (2 for
+//      LIM03; halo cells come from the neighbour's interior or the fixed
+//      ghost layers) into LDS,
+//   B) evaluates R(F+) + R(F-) for every (interface, variable) of the tile
+//      (T_d + 1 interfaces per pencil), per interface or in runs of up to 5
+//      interfaces per pencil, into registers, then LDS,
 //   C) accumulates -(Fhat_{i+1/2} - Fhat_{i-1/2}) / dx_d into per-thread
 //      register accumulators of the cells it owns.
 // The stage update reads its sources once per cell and writes the result;
