@@ -150,3 +150,37 @@ def test_passive_blocks_are_rejected_where_unsupported():
         ctx.set_active(np.zeros(bs.nb, np.uint8))
     assert ei.value.status == A.ERR_INVALID
     ctx.close()
+
+
+@pytest.mark.parametrize("physics", ["glm", "hall_lim03"])
+def test_masked_steps_with_glm_and_hall(physics):
+    # passive blocks keep psi (no decay) and still supply the current their
+    # active neighbours read as halo in Hall MHD
+    say(f"[active] {physics}")
+    base = inputs.orszag_tang_2d(64, 16)
+    bs = inputs.as_glm(base, psi=0.01) if physics == "glm" else base
+    flags = mask_for(bs, 7)
+    recon, eta, scheme = (A.MP5, 0.0, oracle.SSPRK54) if physics == "glm" else (A.LIM03, 0.02, oracle.RK3)
+    oracle.set_active(flags)
+    oracle.set_recon(recon)
+    oracle.set_hall(eta)
+    try:
+        out_o, dts = oracle.run(bs, scheme, 12, cfl=0.4)
+    finally:
+        oracle.set_active(None)
+        oracle.set_recon(oracle.MP5)
+        oracle.set_hall(0.0)
+    ctx, flat, views = A.context_for(bs, recon=recon, eta_h=eta)
+    ctx.set_active(flags)
+    t = ctx.ssprk_step(scheme, 12, cfl=0.4, t=0.0)
+    out_g = bs.copy()
+    out_g.u = [v.cpu().numpy() for v in views]
+    ctx.close()
+    assert abs(t - dts.sum()) <= 1e-12 * dts.sum()
+    dens = [rel_l1(out_o.u, out_o.u, bs, v)[1] for v in range(bs.nvar)]
+    for v in range(bs.nvar):
+        num, den = rel_l1(out_g.u, out_o.u, bs, v)
+        assert num <= 1e-11 * max(den, 1e-3 * sum(dens)), (v, num, den)
+    for b in range(bs.nb):
+        if not flags[b]:
+            assert np.array_equal(out_g.interior(b), bs.interior(b)), b
