@@ -239,3 +239,29 @@ def test_brio_wu_contact_without_overshoot():
     mp5 = overshoot(oracle.MP5, oracle.SSPRK54)
     assert abs(lim - paper_number("brio_wu_lim03_fd_density_overshoot_percent")) < 1.0, lim
     assert mp5 - lim > 1.5, (mp5, lim)
+
+
+def test_brio_wu_at_the_maximal_ssp_courant_numbers():
+    # Sect. 4.5.2: both FD combinations run the tube at the largest Courant
+    # number their SSP property allows; MP5's oscillation level there is
+    # comparable to Courant 0.4, while the third-order scheme departs more.
+    N = int(paper_number("brio_wu_cells"))
+    t_end = paper_number("brio_wu_t_end")
+
+    def vy(recon, scheme, cfl):
+        with oracle.use_recon(recon):
+            out = run_to_time(inputs.brio_wu(N), t_end, cfl=cfl, scheme=scheme)
+        u = out.interior(0)[:, 0, 0, :]
+        rho, E = u[0], u[4]
+        p = (paper_number("brio_wu_gamma") - 1) * (E - 0.5 * (u[1] ** 2 + u[2] ** 2 + u[3] ** 2) / rho
+                                                   - 0.5 * (u[5] ** 2 + u[6] ** 2 + u[7] ** 2))
+        assert np.all(rho > 0) and np.all(p > 0)
+        return u[2] / rho
+
+    lim_lo = vy(oracle.LIM03, oracle.SSPRK43, 0.4)
+    lim_hi = vy(oracle.LIM03, oracle.SSPRK43, paper_number("brio_wu_ssp_courant_ssprk43_lim03"))
+    mp5_lo = vy(oracle.MP5, oracle.SSPRK54, 0.4)
+    mp5_hi = vy(oracle.MP5, oracle.SSPRK54, paper_number("brio_wu_ssp_courant_ssprk54_mp5"))
+    tv = lambda a: np.abs(np.diff(a)).sum()
+    assert abs(tv(mp5_hi) / tv(mp5_lo) - 1.0) < 0.05
+    assert np.abs(lim_hi - lim_lo).max() > 2.0 * np.abs(mp5_hi - mp5_lo).max()
