@@ -153,3 +153,23 @@ def test_refusals():
         ctx.ssprk_adjoint(oracle.SSPRK54, 1e-4, 1, 1, lam)
     assert e.value.status == A.ERR_UNSUPPORTED
     ctx.close()
+
+
+def test_alfven_whistler_wave_3d_fourth_order_on_gpu():
+    # Sect. 4.5.3 runs the wave along k = 2 pi m (1, 1, 1) in 3D; whistler
+    # branch, d = 0.1, one period, 16^3 -> 32^3 -> 64^3
+    oracle.set_hall(0.1)
+    errs = []
+    for N in (16, 32, 64):
+        bs, v, T = inputs.alfven_whistler(3, N, 0.1, -1, kvec=(1, 1, 1), block=N // 2)
+        cm = oracle.cmax(bs)
+        dt0 = 0.4 / sum(cm[d] / bs.dx[0, d] for d in range(3))
+        n = int(math.ceil(T / dt0))
+        ctx, flat, views = A.context_for(bs, recon=A.MP5, eta_h=0.1)
+        ctx.ssprk_step(oracle.SSPRK54, n, dt=T / n, t=0.0)
+        out = host_blocks(views)
+        ctx.close()
+        errs.append(np.mean([np.abs(bs.interior(b, out[b]) - bs.interior(b)).mean() for b in range(bs.nb)]))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    say(f"[hall whistler 3d] errors {errs} orders {orders}")
+    assert orders[-1] > 3.7, (errs, orders)
