@@ -167,6 +167,21 @@ def adjoint_ratio(nsteps, ckpt, warm=80, ckpt_also=None):
         out["ckpt_every" + key] = k
         out["adjoint_s" + key] = adj
         out["ratio" + key] = adj / fwd
+    # the same window with RK3 + LIM03 (the paper's other FD combination)
+    ctx3, flat3, views3 = amrvac.context_for(bs, amrvac.EXEC_BATCHED, recon=amrvac.LIM03)
+    flat3.copy_(u_w)
+    ctx3.ssprk_step(amrvac.RK3, 1, dt=dt, t=None)          # graph capture
+    flat3.copy_(u_w)
+    fwd3 = timed(lambda: ctx3.ssprk_step(amrvac.RK3, nsteps, dt=dt, t=None))
+    ctx3.sync()
+    flat3.copy_(u_w)
+    lam = [l.clone() for l in lam_n]
+    print(f"bench: RK3 + LIM03 adjoint of {nsteps} steps (checkpoints every {ckpt})", file=sys.stderr, flush=True)
+    adj3 = timed(lambda: ctx3.ssprk_adjoint(amrvac.RK3, dt, nsteps, ckpt, lam))
+    ctx3.close()
+    del flat3, views3, lam
+    out["lim03_rk3"] = {"steps": nsteps, "ckpt_every": ckpt, "forward_s": fwd3, "adjoint_s": adj3,
+                        "ratio": adj3 / fwd3}
     # dynamic grid activation: blocks whose centre lies within 0.25 of the
     # box centre are active, plus a safety belt of one block
     centres = bs.xlo + 0.5 * bs.n * bs.dx
