@@ -82,47 +82,81 @@ def measured_traffic(variant):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(bs_full, min_seconds=10.0, max_steps=4):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(bs_full, min_seconds=10.0, max_steps=4, single_seconds=5.0):
     """The oracle as it stands, on a bounded sample of the same block list:
     512 blocks drawn with the same 1:2:4 size mix, SSPRK(5,4) steps until at
-    least `min_seconds` of wall time."""
+    least `min_seconds` of wall time, OpenMP over blocks on every core; then
+    one thread on 64 of those blocks (same mix) for at least
+    `single_seconds`."""
     import numpy as np
     import oracle
-    from paper_1407_2052_amd import inputs
 
     rng = np.random.default_rng(11)
     sizes = bs_full.n[:, 0]
-    idx = []
-    for s, k in ((32, 73), (16, 146), (8, 293)):
-        pool = np.where(sizes == s)[0]
-        idx.extend(rng.choice(pool, min(k, len(pool)), replace=False).tolist())
-    idx = np.array(sorted(idx))
-    sub = bs_full.copy()
-    sub.u = [bs_full.u[i] for i in idx]
-    sub.n, sub.dx, sub.xlo, sub.nbr = bs_full.n[idx], bs_full.dx[idx], bs_full.xlo[idx], bs_full.nbr[idx]
+
+    def sample(counts):
+        idx = []
+        for s, k in zip((32, 16, 8), counts):
+            pool = np.where(sizes == s)[0]
+            idx.extend(rng.choice(pool, min(k, len(pool)), replace=False).tolist())
+        idx = np.array(sorted(idx))
+        sub = bs_full.copy()
+        sub.u = [bs_full.u[i] for i in idx]
+        sub.n, sub.dx, sub.xlo, sub.nbr = bs_full.n[idx], bs_full.dx[idx], bs_full.xlo[idx], bs_full.nbr[idx]
+        return sub
+
+    def run(sub, seconds):
+        t0 = time.perf_counter()
+        steps = 0
+        cur = sub
+        while steps < max_steps:
+            cur, _ = oracle.run(cur, oracle.SSPRK54, 1, cfl=0.4)
+            steps += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        return steps, time.perf_counter() - t0
+
+    sub = sample((73, 146, 293))
     cells = sub.interior_cells()
-    t0 = time.perf_counter()
-    steps = 0
-    cur = sub
-    while steps < max_steps:
-        cur, _ = oracle.run(cur, oracle.SSPRK54, 1, cfl=0.4)
-        steps += 1
-        if time.perf_counter() - t0 >= min_seconds:
-            break
-    el = time.perf_counter() - t0
-    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{len(idx)} of the 4096 blocks (32^3:16^3:8^3 = 73:146:293, {cells} cells), "
-                      f"{steps} SSPRK(5,4) steps, {el:.1f} s wall, OpenMP over blocks"}
+    threads = oracle.num_threads()
+    steps, el = run(sub, min_seconds)
+    out = {"value": cells * steps / el, "unit": "cell-updates/s", "cores": threads,
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"{sub.nb} of the 4096 blocks (32^3:16^3:8^3 = 73:146:293, {cells} cells), "
+                     f"{steps} SSPRK(5,4) steps, {el:.1f} s wall, OpenMP over blocks"}
+    if single_seconds > 0:
+        sub1 = sample((9, 18, 37))
+        cells1 = sub1.interior_cells()
+        oracle.set_threads(1)
+        try:
+            steps1, el1 = run(sub1, single_seconds)
+        finally:
+            oracle.set_threads(threads)
+        out["single_thread"] = {"value": cells1 * steps1 / el1, "unit": "cell-updates/s",
+                                "sample": f"{sub1.nb} blocks (9:18:37, {cells1} cells), {steps1} "
+                                          f"SSPRK(5,4) steps, {el1:.1f} s wall, one thread"}
+    return out
 
 
-def adjoint_ratio(nsteps, ckpt, warm=80, ckpt_also=None):
+def adjoint_ratio(nsteps, ckpt, warm=80, ckpt_also=None, per_block_steps=2):
     """Adjoint / forward wall-time ratio on 3D ideal MHD, 256^3 periodic as
     4096 blocks of 16^3 (16-mode velocity and field perturbations, plasma
     beta 1), fixed dt from the CFL rule on the initial state: `warm` steps
     forward (untimed), then `nsteps` timed forward steps, then the adjoint of
     those nsteps (checkpoints every `ckpt` steps, recompute included) with
-    lambda_N = rho_N - 1 in the density slot.  Then the same forward steps
+    lambda_N = rho_N - 1 in the density slot.  The plain per-block launch is
+    timed on the same window start.  Then the same forward steps
     with only the blocks near the box centre active (dynamic grid
     activation, safety belt of one block)."""
     import numpy as np
@@ -182,6 +216,17 @@ def adjoint_ratio(nsteps, ckpt, warm=80, ckpt_also=None):
     del flat3, views3, lam
     out["lim03_rk3"] = {"steps": nsteps, "ckpt_every": ckpt, "forward_s": fwd3, "adjoint_s": adj3,
                         "ratio": adj3 / fwd3}
+    # the plain per-block launch on the same list (one launch per block per stage)
+    flat.copy_(u_w)
+    ctx.set_exec(amrvac.EXEC_PER_BLOCK)
+    ctx.ssprk_step(amrvac.SSPRK54, 1, dt=dt, t=None)      # first launches
+    flat.copy_(u_w)
+    print(f"bench: per-block launch on the 256^3 list, {per_block_steps} steps", file=sys.stderr, flush=True)
+    pb = timed(lambda: ctx.ssprk_step(amrvac.SSPRK54, per_block_steps, dt=dt, t=None))
+    ctx.sync()
+    ctx.set_exec(amrvac.EXEC_BATCHED)
+    out["per_block"] = {"steps": per_block_steps, "cell_updates_per_s": cells * per_block_steps / pb,
+                        "batched_over_per_block": (cells * nsteps / fwd) / (cells * per_block_steps / pb)}
     # dynamic grid activation: blocks whose centre lies within 0.25 of the
     # box centre are active, plus a safety belt of one block
     centres = bs.xlo + 0.5 * bs.n * bs.dx
@@ -408,7 +453,8 @@ def main():
     adjoint = adjoint_2d = None
     if not args.no_adjoint:
         adjoint = adjoint_ratio(args.adjoint_steps, args.ckpt, args.adjoint_warm,
-                                args.ckpt_also if args.ckpt_also > 0 else None)
+                                args.ckpt_also if args.ckpt_also > 0 else None,
+                                max(1, args.per_block_steps))
         adjoint_2d = adjoint_ratio_2d(args.adjoint_2d_steps)
 
     flops = FLOPS_PER_CELL_STAGE_MHD3D * cells
@@ -435,6 +481,7 @@ def main():
                    "blocks": bs.nb, "cells": cells, "exec": "batched persistent, HIP graph per step",
                    "tile_shape": variant,
                    "parallelism": "single GPU"},
+        "per_stage": {"ms": 1e3 * stage_s, "cell_updates_per_s": cells / stage_s},
         "per_block": per_block,
         "batched_over_per_block": (value / per_block["value"]) if per_block else None,
         "adjoint_forward_ratio": adjoint["ratio"] if adjoint else None,
