@@ -131,11 +131,19 @@ def test_checkpoint_interval_changes_nothing_bitwise():
 
 
 def test_zero_steps_is_identity():
-    bs = periodic_state(2, False, 32, 16, seed=1)
-    lam_n = random_cotangent(bs, 2)
-    got = gpu_adjoint(bs, oracle.SSPRK54, 1e-3, 0, 1, lam_n)
-    for x, y in zip(got, lam_n):
-        assert np.array_equal(x, y)
+    """lam_0 = lam_N on the interiors, ghost entries set to 0 (non-zero on
+    entry here), for Euler and MHD."""
+    for mhd, seed in ((False, 1), (True, 7)):
+        bs = periodic_state(2, mhd, 32, 16, seed=seed)
+        lam_n = random_cotangent(bs, seed + 1)
+        for x in lam_n:
+            x[...] = np.where(x == 0.0, 3.0, x)
+        got = gpu_adjoint(bs, oracle.SSPRK54, 1e-3, 0, 5, lam_n)
+        for b, (x, y) in enumerate(zip(got, lam_n)):
+            assert np.array_equal(bs.interior(b, x), bs.interior(b, y))
+            ghost = np.ones(x.shape, dtype=bool)
+            bs.interior(b, ghost)[...] = False
+            assert np.all(x[ghost] == 0.0)
 
 
 def test_unsupported_inputs_are_reported():

@@ -255,6 +255,21 @@ def test_invalid_arguments_leave_state_untouched():
     ctx.close()
 
 
+def test_zero_steps_leave_state_and_time_untouched():
+    say("[edge] nsteps = 0, both execution forms and every scheme")
+    bs = uneven_small()
+    ctx, flat, views = A.context_for(bs)
+    before = flat.clone()
+    for exec in (A.EXEC_BATCHED, A.EXEC_PER_BLOCK):
+        ctx.set_exec(exec)
+        for scheme in (oracle.RK3, oracle.SSPRK43, oracle.SSPRK54):
+            assert ctx.ssprk_step(scheme, 0, t=0.125) == 0.125
+            assert ctx.ssprk_step(scheme, 0, dt=1e-3, t=0.25) == 0.25
+    torch.cuda.synchronize()
+    assert torch.equal(before, flat)
+    ctx.close()
+
+
 # ---------------------------------------------------------------- full sizes
 def test_full_size_2d_mhd_rhs_and_100_steps():
     """512^2 as 1024 blocks of 16^2 (the 2D MHD workload), right-hand side
