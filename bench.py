@@ -71,15 +71,19 @@ def kernel_source_hash(read=None):
 def measured_traffic(variant):
     """HBM bytes per stage launch from committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE runs (calibrated against a plain copy), if they were taken on
-    the current kernel source and on the tile shape that is being timed."""
+    the current kernel source and include the tile shape that is being timed
+    (the autotuner launches every shape on the same list, so one run covers
+    them all)."""
     path = os.path.join(ROOT, "profiles", "stage_kernel_mhd3d_uneven4096_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("variant") != variant:
+    if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    if rec.get("variant") == variant:
+        return rec.get("bytes_per_launch")
+    return rec.get("variants", {}).get(variant, {}).get("bytes_per_launch")
 
 
 def cpu_model():

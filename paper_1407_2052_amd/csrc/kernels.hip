@@ -68,7 +68,10 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
                              NDIM >= 3 ? S::NIFC(2) : 0>::v;
   constexpr int LDS_N = cmax_i<2 * VPG * EXT, VPG * IFC>::v;
   __shared__ double lds[LDS_N];
-  __shared__ double red[NT / 64][3];
+  // the closing c_max reduction reuses the start of lds: every wave has
+  // passed the barrier that ends the last phase C before any writes it
+  static_assert(LDS_N >= 3 * (NT / 64), "lds too small for the c_max reduction");
+  double (*red)[3] = reinterpret_cast<double (*)[3]>(lds);
 
   const int tid = threadIdx.x;
   const StateTable& st = P.st;
@@ -770,8 +773,10 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 1),
     AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 2),
     AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 3),
+    AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 4),
     AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 1),
     AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 2),
+    AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 4),
     // LIM03 (pencil runs first: the defaults)
     AMRVAC_VARIANT_LR(1, true, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_LR(2, false, 16, 16, 1, 256, 1, 1),
@@ -781,8 +786,10 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 1),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 2),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 3),
+    AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 4),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 8, 512, 2, 1),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 8, 512, 2, 2),
+    AMRVAC_VARIANT_LR(3, true, 8, 8, 8, 512, 2, 4),
     AMRVAC_VARIANT_L(1, false, 128, 1, 1, 128, 1, 1),
     AMRVAC_VARIANT_L(1, false, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_L(1, true, 128, 1, 1, 128, 1, 1),
@@ -805,18 +812,22 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT_G(3, 0, 8, 8, 4, 256, 2, 3),
     AMRVAC_VARIANT_G(3, 0, 8, 8, 4, 256, 2, 1),
     AMRVAC_VARIANT_G(3, 0, 8, 8, 4, 256, 3, 3),
+    AMRVAC_VARIANT_G(3, 0, 8, 8, 4, 256, 3, 4),
     AMRVAC_VARIANT_G(1, 1, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_G(2, 1, 16, 16, 1, 256, 2, 2),
     AMRVAC_VARIANT_G(3, 1, 8, 8, 4, 256, 2, 1),
     AMRVAC_VARIANT_G(3, 1, 8, 8, 4, 256, 2, 3),
+    AMRVAC_VARIANT_G(3, 1, 8, 8, 4, 256, 2, 4),
     // Hall MHD
     AMRVAC_VARIANT_H(1, 0, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_H(2, 0, 16, 16, 1, 256, 2, 2),
     AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 2),
     AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 1),
+    AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 4),
     AMRVAC_VARIANT_H(1, 1, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_H(2, 1, 16, 16, 1, 256, 2, 2),
     AMRVAC_VARIANT_H(3, 1, 8, 8, 4, 256, 2, 1),
+    AMRVAC_VARIANT_H(3, 1, 8, 8, 4, 256, 2, 4),
 };
 
 const StageVariant* stage_variants(int* count) {
