@@ -33,6 +33,15 @@ __device__ __forceinline__ void static_for(F&& f) {
 // ---------------------------------------------------------------------------
 // Addressing of state buffers.
 // ---------------------------------------------------------------------------
+// A wave-uniform int the compiler must treat as unknown at this point: the
+// stage update's buffer addresses derived from it are then rebuilt per tile
+// (a few scalar operations) instead of being hoisted out of the tile loop and
+// held, or spilled, across it.  The empty asm emits no instruction.
+__device__ __forceinline__ int opaque_uniform(int x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
 __device__ __forceinline__ const double* cell_addr(const StateTable& st, const BlockDev& B, int buf,
                                                    int i, int j, int k, long long& vstride) {
   if (buf == 0) {

@@ -230,26 +230,35 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
             // fp[kk ..] and F- from fm[RUN - 1 - kk ..].
             constexpr int W = RUN + 2 * HG - 2;
             const int eb = a[0] + E0P * (a[1] + E1 * a[2]);
-            double fp[W], fm[W];
-#pragma unroll
-            for (int m = 0; m < W; ++m) {
-              fp[m] = lds[vg * NEXTP + eb + m * SD];
-              fm[m] = lds[(VPG + vg) * NEXTP + eb + (W - m) * SD];
-            }
-            double op[RUN], om[RUN];
+            // one window at a time (F+, then F-) keeps fewer registers live;
+            // res = R(F+) + R(F-) in that operand order either way
             int cp[RUN], cm[RUN];
-            if constexpr (LIM) {
+            {
+              double fw[W], o[RUN];
 #pragma unroll
-              for (int kk = 0; kk < RUN; ++kk) {
-                op[kk] = lim03_eval<EMIT>(fp[kk], fp[kk + 1], fp[kk + 2], kr, cp[kk]);
-                om[kk] = lim03_eval<EMIT>(fm[kk], fm[kk + 1], fm[kk + 2], kr, cm[kk]);
+              for (int m = 0; m < W; ++m) fw[m] = lds[vg * NEXTP + eb + m * SD];
+              if constexpr (LIM) {
+#pragma unroll
+                for (int kk = 0; kk < RUN; ++kk) o[kk] = lim03_eval<EMIT>(fw[kk], fw[kk + 1], fw[kk + 2], kr, cp[kk]);
+              } else {
+                mp5_run<RUN, EMIT>(fw, o, cp);
               }
-            } else {
-              mp5_run<RUN, EMIT>(fp, op, cp);
-              mp5_run<RUN, EMIT>(fm, om, cm);
-            }
 #pragma unroll
-            for (int kk = 0; kk < RUN; ++kk) res[r][kk] = op[kk] + om[RUN - 1 - kk];
+              for (int kk = 0; kk < RUN; ++kk) res[r][kk] = o[kk];
+            }
+            {
+              double fw[W], o[RUN];
+#pragma unroll
+              for (int m = 0; m < W; ++m) fw[m] = lds[(VPG + vg) * NEXTP + eb + (W - m) * SD];
+              if constexpr (LIM) {
+#pragma unroll
+                for (int kk = 0; kk < RUN; ++kk) o[kk] = lim03_eval<EMIT>(fw[kk], fw[kk + 1], fw[kk + 2], kr, cm[kk]);
+              } else {
+                mp5_run<RUN, EMIT>(fw, o, cm);
+              }
+#pragma unroll
+              for (int kk = 0; kk < RUN; ++kk) res[r][kk] = res[r][kk] + o[RUN - 1 - kk];
+            }
             if constexpr (EMIT) {
               // linear pieces, stored on the lower face of cell a_D
 #pragma unroll
@@ -401,7 +410,7 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
         const double* sp[MAX_SRC];
 #pragma unroll
         for (int q = 0; q < MAX_SRC; ++q)
-          if (q < P.nsrc) sp[q] = cell_addr(st, B, P.src[q], i, j, k, vs[q]);
+          if (q < P.nsrc) sp[q] = cell_addr(st, B, opaque_uniform(P.src[q]), i, j, k, vs[q]);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double acc = P.a[0] * sp[0][v * vs[0]];
@@ -419,9 +428,9 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
         const double* sp[MAX_SRC];
 #pragma unroll
         for (int q = 0; q < MAX_SRC; ++q)
-          if (q < P.snsrc) sp[q] = cell_addr(st, B, P.ssrc[q], i, j, k, vs[q]);
+          if (q < P.snsrc) sp[q] = cell_addr(st, B, opaque_uniform(P.ssrc[q]), i, j, k, vs[q]);
         long long ws;
-        double* sd = cell_addr_w(st, B, P.sdst, i, j, k, ws);
+        double* sd = cell_addr_w(st, B, opaque_uniform(P.sdst), i, j, k, ws);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double acc = P.sa[0] * sp[0][v * vs[0]];
@@ -433,7 +442,7 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
       }
       {
         long long ws;
-        double* dp = cell_addr_w(st, B, P.dst, i, j, k, ws);
+        double* dp = cell_addr_w(st, B, opaque_uniform(P.dst), i, j, k, ws);
 #pragma unroll
         for (int v = 0; v < NV; ++v) dp[v * ws] = un[v];
       }
