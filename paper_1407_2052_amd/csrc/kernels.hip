@@ -773,6 +773,7 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT(3, false, 8, 8, 4, 256, 1, 1),
     AMRVAC_VARIANT(3, false, 8, 8, 8, 512, 2, 4),
     AMRVAC_VARIANT_R(3, false, 8, 8, 4, 256, 1, 2),
+    AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 4),
     AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 2, 1),
     AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 2, 4),
     AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 2, 1),
@@ -782,7 +783,6 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 1),
     AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 2),
     AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 3),
-    AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 4),
     AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 1),
     AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 2),
     AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 4),
@@ -792,10 +792,10 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT_LR(2, true, 16, 16, 1, 256, 1, 1),
     AMRVAC_VARIANT_LR(2, true, 16, 16, 1, 256, 2, 2),
     AMRVAC_VARIANT_LR(3, false, 8, 8, 4, 256, 1, 2),
+    AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 4),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 1),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 2),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 3),
-    AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 4),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 8, 512, 2, 1),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 8, 512, 2, 2),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 8, 512, 2, 4),
@@ -830,13 +830,13 @@ static const StageVariant g_variants[] = {
     // Hall MHD
     AMRVAC_VARIANT_H(1, 0, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_H(2, 0, 16, 16, 1, 256, 2, 2),
+    AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 4),
     AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 2),
     AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 1),
-    AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 4),
     AMRVAC_VARIANT_H(1, 1, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_H(2, 1, 16, 16, 1, 256, 2, 2),
-    AMRVAC_VARIANT_H(3, 1, 8, 8, 4, 256, 2, 1),
     AMRVAC_VARIANT_H(3, 1, 8, 8, 4, 256, 2, 4),
+    AMRVAC_VARIANT_H(3, 1, 8, 8, 4, 256, 2, 1),
 };
 
 const StageVariant* stage_variants(int* count) {
