@@ -27,8 +27,9 @@
 //   C) accumulates -(Fhat_{i+1/2} - Fhat_{i-1/2}) / dx_d into per-thread
 //      register accumulators of the cells it owns.
 // The stage update reads its sources once per cell and writes the result;
-// the only HBM traffic beyond the algorithmic state passes is the 3-cell
-// halo of tiles (served mostly by L2).
+// the traffic beyond the algorithmic state passes is the re-reading of each
+// tile's extended boxes, which L2 serves only in part (the more tiles are in
+// flight per XCD, the less), and the spills of the 4-wave shapes.
 //
 // Floating point: automatic FMA contraction is off for this file (the build
 // passes -ffp-contract=off) and every fused multiply-add is written
