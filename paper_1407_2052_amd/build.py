@@ -28,13 +28,18 @@ def build(verbose: bool = False) -> str:
               "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-function"]
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
+    # the four translation units compile side by side (kernels.hip dominates)
+    procs = []
     for src in SOURCES:
         obj = os.path.join(bdir, src + ".o")
         cmd = [HIPCC, "-c", *common, "-x", "hip", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [cmd for cmd, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", *objs, "-o", OUT + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
