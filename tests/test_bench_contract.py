@@ -1,0 +1,67 @@
+"""Host-side checks of bench.py's measurement bookkeeping (no GPU): the HBM
+traffic it reports comes from the committed rocprofv3 record only while the
+kernel code and the timed tile shape match that record."""
+import json
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+RECORD = os.path.join(ROOT, "profiles", "stage_kernel_mhd3d_uneven4096_traffic.json")
+
+
+def record():
+    with open(RECORD) as f:
+        return json.load(f)
+
+
+def test_comment_edits_keep_the_hash_and_code_edits_change_it():
+    src = "int f(int x) {\n  // a comment\n  return x + 1; /* another */\n}\n"
+    assert bench.strip_comments(src) == bench.strip_comments(src.replace("a comment", "edited"))
+    assert bench.strip_comments(src) != bench.strip_comments(src.replace("x + 1", "x + 2"))
+
+    def reader(edit):
+        def read(path):
+            with open(os.path.join(ROOT, path)) as f:
+                s = f.read()
+            return edit(s) if path.endswith("kernels.hip") else s
+        return read
+
+    h0 = bench.kernel_source_hash()
+    assert bench.kernel_source_hash(reader(lambda s: s + "\n// trailing comment\n")) == h0
+    assert bench.kernel_source_hash(reader(lambda s: s + "\nstatic int unused_probe;\n")) != h0
+
+
+def test_traffic_is_reported_for_recorded_shapes_of_the_current_code():
+    rec = record()
+    if rec["kernel_source_hash"] != bench.kernel_source_hash():
+        pytest.skip("the traffic record predates the current kernel code")
+    assert bench.measured_traffic(rec["variant"]) == rec["bytes_per_launch"]
+    for name, v in rec.get("variants", {}).items():
+        assert bench.measured_traffic(name) == v["bytes_per_launch"]
+    assert bench.measured_traffic("no-such-tile-shape") is None
+
+
+def test_traffic_is_withheld_when_the_code_changes(monkeypatch):
+    rec = record()
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda read=None: "0" * 16)
+    assert bench.measured_traffic(rec["variant"]) is None
+
+
+def test_record_is_calibrated_and_consistent():
+    rec = record()
+    kib = 1024.0
+    assert rec["copy_probe"]["bytes"] / kib / rec["copy_probe"]["fetch_size_kib"] == pytest.approx(rec["read_factor"])
+    assert rec["copy_probe"]["bytes"] / kib / rec["copy_probe"]["write_size_kib"] == pytest.approx(rec["write_factor"])
+    total = (rec["fetch_size_kib_per_dispatch"] * kib * rec["read_factor"]
+             + rec["write_size_kib_per_dispatch"] * kib * rec["write_factor"])
+    assert total == pytest.approx(rec["bytes_per_launch"], rel=1e-6)
+    # algorithmic bytes: 17 state passes x 8 variables x 8 bytes per cell and step, over 5 stages
+    assert rec["algorithmic_bytes_per_launch"] == pytest.approx(
+        bench.BYTES_PER_CELL_STEP_MHD3D / bench.STAGES * 25160192)
+    assert rec["variants"][rec["variant"]]["bytes_per_launch"] == pytest.approx(rec["bytes_per_launch"])
