@@ -40,7 +40,9 @@ class SSPRKSteps(torch.autograd.Function):
                 *u0: torch.Tensor):
         outs = [u.detach().clone().contiguous() for u in u0]
         solver.bind(outs)
-        solver.ctx.ssprk_step(scheme, nsteps, dt=dt, t=None)
+        # t=0.0 waits for the steps and reads the device status, so a
+        # non-physical forward state raises here rather than in backward
+        solver.ctx.ssprk_step(scheme, nsteps, dt=dt, t=0.0)
         ctx.solver, ctx.scheme, ctx.dt, ctx.nsteps, ctx.ckpt = solver, scheme, dt, nsteps, ckpt_every
         ctx.save_for_backward(*u0)
         return tuple(outs)

@@ -61,3 +61,42 @@ def rel_l1(a_blocks, b_blocks, bs, v):
               enumerate(zip(a_blocks, b_blocks)))
     den = sum(float(np.abs(bs.interior(i, b)[v]).sum()) for i, b in enumerate(b_blocks))
     return num, den
+
+
+# ---------------------------------------------------------------------------
+# Summaries of a full-size state, so that a stored oracle run can be compared
+# with a GPU run without storing the whole state.
+# ---------------------------------------------------------------------------
+def state_summary(bs, u_blocks, seed=12345, nsample=4096):
+    """Per block and variable: L1 = sum |U|, S = sum U and P = sum w U with
+    seeded weights w ~ U(-1, 1) per interior cell (|P_a - P_b| <= ||U_a -
+    U_b||_1, so P catches localised differences); plus the state at nsample
+    seeded interior cells (block, z, y, x)."""
+    nb, nv = bs.nb, bs.nvar
+    l1 = np.zeros((nb, nv))
+    s = np.zeros((nb, nv))
+    p = np.zeros((nb, nv))
+    for b in range(nb):
+        x = bs.interior(b, u_blocks[b])
+        w = np.random.default_rng([seed, b]).uniform(-1.0, 1.0, size=x.shape[1:])
+        l1[b] = np.abs(x).reshape(nv, -1).sum(axis=1)
+        s[b] = x.reshape(nv, -1).sum(axis=1)
+        p[b] = (x * w[None]).reshape(nv, -1).sum(axis=1)
+    rng = np.random.default_rng(seed)
+    idx = np.zeros((nsample, 4), np.int64)
+    val = np.zeros((nsample, nv))
+    for q in range(nsample):
+        b = int(rng.integers(0, nb))
+        z, y, xx = (int(rng.integers(0, bs.n[b, d])) if d < bs.ndim else 0 for d in (2, 1, 0))
+        idx[q] = (b, z, y, xx)
+        val[q] = bs.interior(b, u_blocks[b])[:, z, y, xx]
+    return {"l1": l1, "sum": s, "proj": p, "sample_idx": idx, "sample_val": val}
+
+
+def input_digest(bs):
+    """sha256 of every block's padded state (identifies the generated input)."""
+    import hashlib
+    h = hashlib.sha256()
+    for x in bs.u:
+        h.update(np.ascontiguousarray(x).tobytes())
+    return h.hexdigest()

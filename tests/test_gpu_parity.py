@@ -127,10 +127,10 @@ STEP_CASES = [
     ("hydro2d", oracle.RK3, 100),
     ("ragged2d_hd", oracle.SSPRK54, 100),
     ("ragged2d_mhd", oracle.SSPRK43, 60),
-    ("ragged3d_mhd", oracle.SSPRK54, 30),
-    ("ragged3d_hd", oracle.RK3, 30),
-    ("mhd3d", oracle.SSPRK54, 20),
-    ("uneven3d", oracle.SSPRK54, 10),
+    ("ragged3d_mhd", oracle.SSPRK54, 100),
+    ("ragged3d_hd", oracle.RK3, 100),
+    ("mhd3d", oracle.SSPRK54, 100),
+    ("uneven3d", oracle.SSPRK54, 100),
     ("min3_1d_mhd", oracle.SSPRK54, 50),
     ("min3_3d_mhd", oracle.RK3, 10),
     ("big2d_single", oracle.SSPRK54, 2),
