@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define AMRVAC_ABI_VERSION 3
+#define AMRVAC_ABI_VERSION 4
 #define AMRVAC_NGHOST 3
 
 typedef enum {
@@ -228,6 +228,32 @@ amrvac_status amrvac_divb(amrvac_ctx *ctx, double *const *out, double *mean_abs_
  * NONPHYSICAL (only when synchronising), DEVICE, NOMEM. */
 amrvac_status amrvac_ssprk_step(amrvac_ctx *ctx, int scheme, double cfl, const double *dt_fixed,
                                 int nsteps, double *t_inout);
+
+/* Size, in doubles, of the fixed per-device array that holds the stage
+ * buffers of amrvac_ssprk_step_noalloc (64 MiB). */
+#define AMRVAC_NOALLOC_MAX_DOUBLES 8388608
+
+/* For callers that cannot allocate device memory while they step: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results (bit for bit) as amrvac_ssprk_step,
+ * with two differences: its three stage buffers (A, B and the SSPRK(5,4)
+ * accumulator S, each nvar x (total interior cells) doubles rounded up to a
+ * multiple of 32) live in a fixed library-owned device array of
+ * AMRVAC_NOALLOC_MAX_DOUBLES doubles instead of context scratch, and the
+ * stages are launched one by one (no graph is built).  The call itself
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine);
+ * every other buffer it uses was set up by amrvac_create and
+ * amrvac_set_blocks.  The array exists once per device, is shared by every
+ * context on that device and is held until the process ends; nothing in it
+ * has to start at zero (every stage writes the buffer it hands on before a
+ * later stage reads it).  Calls on one device whose streams overlap in time
+ * race on the array: the caller must order them.
+ * Errors: those of amrvac_ssprk_step; INVALID when the three stage buffers
+ * need more than AMRVAC_NOALLOC_MAX_DOUBLES doubles (nothing enqueued,
+ * state unchanged); DEVICE when the array's address could not be resolved
+ * on this device at amrvac_create. */
+amrvac_status amrvac_ssprk_step_noalloc(amrvac_ctx *ctx, int scheme, double cfl, const double *dt_fixed,
+                                        int nsteps, double *t_inout);
 
 /* Reverse mode of amrvac_ssprk_step at a fixed dt: with U_0 the current
  * block states (read only, not modified) and U_N the state after nsteps

@@ -22,14 +22,16 @@ RK3, SSPRK43, SSPRK54 = 0, 1, 2
 EXEC_PER_BLOCK, EXEC_BATCHED = 0, 1
 MP5, LIM03 = 0, 1
 NGHOST = 3
-ABI_VERSION = 3
+ABI_VERSION = 4
+NOALLOC_MAX_DOUBLES = 8388608
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NONPHYSICAL", 5: "UNSUPPORTED"}
 
 # Entry points declared in include/amrvac.h.
 SYMBOLS = ["amrvac_abi_version", "amrvac_create", "amrvac_set_blocks", "amrvac_validate_blocks",
            "amrvac_set_exec", "amrvac_num_variants", "amrvac_variant_name", "amrvac_set_variant",
            "amrvac_get_variant",
-           "amrvac_autotune", "amrvac_fd_rhs", "amrvac_divb", "amrvac_ssprk_step", "amrvac_ssprk_adjoint",
+           "amrvac_autotune", "amrvac_fd_rhs", "amrvac_divb", "amrvac_ssprk_step", "amrvac_ssprk_step_noalloc",
+           "amrvac_ssprk_adjoint",
            "amrvac_activation_flags", "amrvac_set_active",
            "amrvac_sync", "amrvac_last_error", "amrvac_destroy"]
 
@@ -85,6 +87,7 @@ def lib():
         L.amrvac_fd_rhs.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p), dp]
         L.amrvac_divb.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p), dp]
         L.amrvac_ssprk_step.argtypes = [vp, ip, ctypes.c_double, dp, ip, dp]
+        L.amrvac_ssprk_step_noalloc.argtypes = [vp, ip, ctypes.c_double, dp, ip, dp]
         L.amrvac_ssprk_adjoint.argtypes = [vp, ip, ctypes.c_double, ip, ip, ctypes.POINTER(ctypes.c_void_p)]
         ub = ctypes.POINTER(ctypes.c_ubyte)
         L.amrvac_activation_flags.argtypes = [ctypes.POINTER(Block), ip, ub, ip, ub]
@@ -96,7 +99,8 @@ def lib():
         L.amrvac_destroy.argtypes = [vp]
         for name in ("amrvac_create", "amrvac_set_blocks", "amrvac_validate_blocks", "amrvac_set_exec",
                      "amrvac_set_variant", "amrvac_autotune",
-                     "amrvac_fd_rhs", "amrvac_ssprk_step", "amrvac_ssprk_adjoint", "amrvac_set_active",
+                     "amrvac_fd_rhs", "amrvac_ssprk_step", "amrvac_ssprk_step_noalloc", "amrvac_ssprk_adjoint",
+                     "amrvac_set_active",
                      "amrvac_sync"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
@@ -247,6 +251,16 @@ class Context:
         tt = ctypes.c_double(t) if t is not None else None
         self._check(lib().amrvac_ssprk_step(self._h, scheme, cfl, dtp, nsteps,
                                             ctypes.byref(tt) if tt is not None else None))
+        return tt.value if tt is not None else None
+
+    def ssprk_step_noalloc(self, scheme: int, nsteps: int, cfl: float = 0.4, dt: Optional[float] = None,
+                           t: Optional[float] = 0.0) -> Optional[float]:
+        """ssprk_step with the stage buffers in the library's fixed device
+        array (amrvac_ssprk_step_noalloc: the call allocates nothing)."""
+        dtp = ctypes.byref(ctypes.c_double(dt)) if dt is not None else None
+        tt = ctypes.c_double(t) if t is not None else None
+        self._check(lib().amrvac_ssprk_step_noalloc(self._h, scheme, cfl, dtp, nsteps,
+                                                    ctypes.byref(tt) if tt is not None else None))
         return tt.value if tt is not None else None
 
     def ssprk_adjoint(self, scheme: int, dt: float, nsteps: int, ckpt_every: int, lam: Sequence):

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -21,6 +22,30 @@
 using namespace amrvac;
 
 static const char* g_noctx_error = "";
+
+// Stage buffers of amrvac_ssprk_step_noalloc: one fixed array per device,
+// held until the process ends.  Host code never passes `scratch` itself to a
+// kernel (in host code the name is a stand-in, not a device address): the
+// address on each device is resolved once with hipGetSymbolAddress, with
+// that device current, and kept in g_scratch_addr.
+static __device__ __align__(256) double scratch[AMRVAC_NOALLOC_MAX_DOUBLES];
+static std::mutex g_scratch_mu;
+static std::map<int, double*> g_scratch_addr;
+
+static hipError_t scratch_address(int device, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  g_scratch_addr[device] = static_cast<double*>(p);
+  *out = static_cast<double*>(p);
+  return hipSuccess;
+}
 
 static amrvac_status fail(amrvac_ctx* c, amrvac_status st, const char* fmt, ...) {
   char buf[512];
@@ -223,7 +248,7 @@ namespace amrvac {
 StateTable state_table(const amrvac_ctx* c) {
   StateTable st;
   st.blocks = c->d_blocks;
-  st.scr = c->d_scr;
+  st.scr = c->scr_override ? c->scr_override : c->d_scr;
   st.slot_stride = c->slot_stride;
   return st;
 }
@@ -571,6 +596,10 @@ amrvac_status amrvac_create(const amrvac_config* cfg, void* hip_stream, amrvac_c
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc(&c->d_ctl, sizeof(Control));
   if (e == hipSuccess) e = hipMemset(c->d_ctl, 0, sizeof(Control));
+  if (e == hipSuccess && scratch_address(c->device, &c->noalloc_scr) != hipSuccess) {
+    c->noalloc_scr = nullptr;   // amrvac_ssprk_step_noalloc reports DEVICE
+    (void)hipGetLastError();
+  }
   if (e != hipSuccess || !c->var) {
     g_noctx_error = "amrvac_create: HIP device setup failed";
     if (c->d_ctl) (void)hipFree(c->d_ctl);
@@ -845,9 +874,8 @@ amrvac_status amrvac_divb(amrvac_ctx* c, double* const* out, double* mean_abs_ou
   return AMRVAC_OK;
 }
 
-amrvac_status amrvac_ssprk_step(amrvac_ctx* c, int scheme, double cfl, const double* dt_fixed,
-                                int nsteps, double* t_inout) {
-  if (!c) return AMRVAC_ERR_INVALID;
+static amrvac_status check_step_args(amrvac_ctx* c, int scheme, double cfl, const double* dt_fixed,
+                                     int nsteps) {
   if (c->hb.empty()) return fail(c, AMRVAC_ERR_INVALID, "ssprk_step: no blocks set");
   if (scheme < AMRVAC_RK3 || scheme > AMRVAC_SSPRK54)
     return fail(c, AMRVAC_ERR_INVALID, "ssprk_step: unknown scheme %d", scheme);
@@ -858,8 +886,14 @@ amrvac_status amrvac_ssprk_step(amrvac_ctx* c, int scheme, double cfl, const dou
   } else if (!std::isfinite(cfl) || !(cfl > 0.0)) {
     return fail(c, AMRVAC_ERR_INVALID, "ssprk_step: cfl must be finite and > 0");
   }
-  amrvac_status st = ensure_slots(c, 3);
-  if (st != AMRVAC_OK) return st;
+  return AMRVAC_OK;
+}
+
+// The steps of amrvac_ssprk_step on the stage buffers the state tables
+// point at (context scratch, or the fixed array); with use_graph the batched
+// form replays one cached graph per step.
+static amrvac_status enqueue_steps(amrvac_ctx* c, int scheme, double cfl, const double* dt_fixed, int nsteps,
+                                   double* t_inout, bool use_graph) {
   if (!c->hptiles.empty() && nsteps > 0) {
     // passive blocks: their current state in the stage buffers A and B,
     // which active neighbours read as halo at every stage
@@ -872,7 +906,7 @@ amrvac_status amrvac_ssprk_step(amrvac_ctx* c, int scheme, double cfl, const dou
   launch_set_control(c->d_ctl, dt_fixed ? *dt_fixed : 0.0, cfl, t_inout ? *t_inout : 0.0, c->stream);
   if (nsteps > 0) launch_cmax_of(c, 0, 0, c->stream);
   const int exec = c->exec;
-  if (exec == AMRVAC_EXEC_BATCHED && nsteps > 0) {
+  if (use_graph && exec == AMRVAC_EXEC_BATCHED && nsteps > 0) {
     GraphEntry& g = c->graphs[scheme];
     if (!g.exec) {
       HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
@@ -889,14 +923,49 @@ amrvac_status amrvac_ssprk_step(amrvac_ctx* c, int scheme, double cfl, const dou
     for (int it = 0; it < nsteps; ++it) enqueue_step(c, scheme, exec, c->stream, 0, 1, 2, 3, 0);
   }
   HIP_TRY(c, hipGetLastError());
-  if (t_inout) {
-    double t = 0.0;
-    HIP_TRY(c, hipMemcpyAsync(&t, &c->d_ctl->t, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    st = read_status(c);
-    *t_inout = t;
-    return st;
-  }
   return AMRVAC_OK;
+}
+
+// Reads the end time (synchronising) and the sticky device status.
+static amrvac_status report_time(amrvac_ctx* c, double* t_inout) {
+  if (!t_inout) return AMRVAC_OK;
+  double t = 0.0;
+  HIP_TRY(c, hipMemcpyAsync(&t, &c->d_ctl->t, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  amrvac_status st = read_status(c);
+  *t_inout = t;
+  return st;
+}
+
+amrvac_status amrvac_ssprk_step(amrvac_ctx* c, int scheme, double cfl, const double* dt_fixed,
+                                int nsteps, double* t_inout) {
+  if (!c) return AMRVAC_ERR_INVALID;
+  amrvac_status st = check_step_args(c, scheme, cfl, dt_fixed, nsteps);
+  if (st != AMRVAC_OK) return st;
+  st = ensure_slots(c, 3);
+  if (st != AMRVAC_OK) return st;
+  st = enqueue_steps(c, scheme, cfl, dt_fixed, nsteps, t_inout, true);
+  if (st != AMRVAC_OK) return st;
+  return report_time(c, t_inout);
+}
+
+amrvac_status amrvac_ssprk_step_noalloc(amrvac_ctx* c, int scheme, double cfl, const double* dt_fixed,
+                                        int nsteps, double* t_inout) {
+  if (!c) return AMRVAC_ERR_INVALID;
+  amrvac_status st = check_step_args(c, scheme, cfl, dt_fixed, nsteps);
+  if (st != AMRVAC_OK) return st;
+  if (!c->noalloc_scr)
+    return fail(c, AMRVAC_ERR_DEVICE, "ssprk_step_noalloc: the fixed stage-buffer array has no address on device %d",
+                c->device);
+  const long long need = 3 * c->slot_stride;
+  if (need > (long long)AMRVAC_NOALLOC_MAX_DOUBLES)
+    return fail(c, AMRVAC_ERR_INVALID,
+                "ssprk_step_noalloc: the stage buffers need %lld doubles, more than the %lld of the fixed array",
+                need, (long long)AMRVAC_NOALLOC_MAX_DOUBLES);
+  c->scr_override = c->noalloc_scr;
+  st = enqueue_steps(c, scheme, cfl, dt_fixed, nsteps, t_inout, false);
+  c->scr_override = nullptr;
+  if (st != AMRVAC_OK) return st;
+  return report_time(c, t_inout);
 }
 
 int amrvac_activation_flags(const amrvac_block* blocks, int nblocks, const unsigned char* want, int safety,

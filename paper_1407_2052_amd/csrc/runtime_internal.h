@@ -79,6 +79,11 @@ struct amrvac_ctx {
   // scratch
   double* d_scr = nullptr;
   int nslots = 0;
+  // amrvac_ssprk_step_noalloc: this device's fixed stage-buffer array
+  // (resolved at amrvac_create; null if that failed), and the base the
+  // state tables use while such a call enqueues (null: d_scr)
+  double* noalloc_scr = nullptr;
+  double* scr_override = nullptr;
 
   // control
   Control* d_ctl = nullptr;
