@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
       for (int v = 0; v < NV; ++v) nu[r][v] = 0.0;
       if (own[r]) {
         long long vs;
-        const double* p = cell_addr(st, B, P.in, tl.o[0] + a0, tl.o[1] + a1, tl.o[2] + a2, vs);
+        gptr p = cell_addr(st, B, P.in, tl.o[0] + a0, tl.o[1] + a1, tl.o[2] + a2, vs);
 #pragma unroll
         for (int v = 0; v < NV; ++v) uo[r][v] = p[v * vs];
       } else {
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
         if (Bn) {
           for (int q = 0; q < P.nmu; ++q) {
             long long vs;
-            const double* p = cell_addr(st, *Bn, P.mu_src[q], cc[0], cc[1], cc[2], vs);
+            gptr p = cell_addr(st, *Bn, P.mu_src[q], cc[0], cc[1], cc[2], vs);
 #pragma unroll
             for (int v = 0; v < NV; ++v) mu[v] = fma(P.mu_a[q], p[v * vs], mu[v]);
           }
@@ -446,12 +446,12 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
       for (int v = 0; v < NV; ++v) acc[v] = 0.0;
       for (int q = 0; q < P.nlam; ++q) {
         long long vs;
-        const double* p = cell_addr(st, B, P.lam_src[q], i, j, k, vs);
+        gptr p = cell_addr(st, B, P.lam_src[q], i, j, k, vs);
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = fma(P.lam_a[q], p[v * vs], acc[v]);
       }
       long long ws;
-      double* p = cell_addr_w(st, B, P.dst, i, j, k, ws);
+      gptr_w p = cell_addr_w(st, B, P.dst, i, j, k, ws);
 #pragma unroll
       for (int v = 0; v < NV; ++v) p[v * ws] = fma(P.scale, nu[r][v], acc[v]);
     }
@@ -504,7 +504,7 @@ __global__ void __launch_bounds__(256) k_argmax_tiles(StateTable st, const Tile*
       const int i = tl.o[0] + c % tx, j = tl.o[1] + (c / tx) % ty, k = tl.o[2] + c / (tx * ty);
       if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
       long long vs;
-      const double* p = cell_addr(st, B, in, i, j, k, vs);
+      gptr p = cell_addr(st, B, in, i, j, k, vs);
       double u[E::NV];
 #pragma unroll
       for (int v = 0; v < E::NV; ++v) u[v] = p[v * vs];
@@ -606,14 +606,14 @@ __global__ void __launch_bounds__(256) k_vjp_cmax(StateTable st, int nblocks, co
     }
     const int i = (int)(cell % B.n[0]), j = (int)((cell / B.n[0]) % B.n[1]), k = (int)(cell / ((long long)B.n[0] * B.n[1]));
     long long vs, ws;
-    const double* p = cell_addr(st, B, in, i, j, k, vs);
+    gptr p = cell_addr(st, B, in, i, j, k, vs);
     double u[E::NV], lu[E::NV];
     for (int v = 0; v < E::NV; ++v) {
       u[v] = p[v * vs];
       lu[v] = 0.0;
     }
     speed_vjp<NDIM, MHD>(u, gamma, d, s[0][d], lu);
-    double* q = const_cast<double*>(cell_addr(st, B, lam, i, j, k, ws));
+    gptr_w q = (gptr_w)(cell_addr(st, B, lam, i, j, k, ws));
     for (int v = 0; v < E::NV; ++v) q[v * ws] = fma(scale, lu[v], q[v * ws]);
   }
 }
@@ -639,9 +639,9 @@ __global__ void __launch_bounds__(256) k_combine(CombineParams P) {
       const int i = tl.o[0] + c % P.tx, j = tl.o[1] + (c / P.tx) % P.ty, k = tl.o[2] + c / (P.tx * P.ty);
       if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
       long long vs[6], ws;
-      const double* sp[6];
+      gptr sp[6];
       for (int q = 0; q < P.n; ++q) sp[q] = cell_addr(P.st, B, P.src[q], i, j, k, vs[q]);
-      double* dp = const_cast<double*>(cell_addr(P.st, B, P.dst, i, j, k, ws));
+      gptr_w dp = (gptr_w)(cell_addr(P.st, B, P.dst, i, j, k, ws));
       for (int v = 0; v < P.nv; ++v) {
         double acc = 0.0;
         for (int q = 0; q < P.n; ++q) acc = fma(P.a[q], sp[q][v * vs[q]], acc);
@@ -661,8 +661,9 @@ __global__ void __launch_bounds__(256) k_lam_import(StateTable st, double* const
     const long long pstride = (long long)B.P[0] * B.P[1] * B.P[2];
     const long long pidx = ((long long)(k + B.g[2]) * B.P[1] + (j + B.g[1])) * B.P[0] + (i + B.g[0]);
     long long ws;
-    double* q = const_cast<double*>(cell_addr(st, B, dst, i, j, k, ws));
-    for (int v = 0; v < nv; ++v) q[v * ws] = ptrs[b][v * pstride + pidx];
+    gptr_w q = (gptr_w)(cell_addr(st, B, dst, i, j, k, ws));
+    gptr src = (gptr)ptrs[b];
+    for (int v = 0; v < nv; ++v) q[v * ws] = src[v * pstride + pidx];
   }
 }
 
@@ -674,12 +675,13 @@ __global__ void __launch_bounds__(256) k_lam_export(StateTable st, double* const
     const int pi = (int)(pc % B.P[0]), pj = (int)((pc / B.P[0]) % B.P[1]), pk = (int)(pc / ((long long)B.P[0] * B.P[1]));
     const int i = pi - B.g[0], j = pj - B.g[1], k = pk - B.g[2];
     const bool inside = i >= 0 && i < B.n[0] && j >= 0 && j < B.n[1] && k >= 0 && k < B.n[2];
+    gptr_w out = (gptr_w)ptrs[b];
     if (inside) {
       long long vs;
-      const double* p = cell_addr(st, B, src, i, j, k, vs);
-      for (int v = 0; v < nv; ++v) ptrs[b][v * pstride + pc] = p[v * vs];
+      gptr p = cell_addr(st, B, src, i, j, k, vs);
+      for (int v = 0; v < nv; ++v) out[v * pstride + pc] = p[v * vs];
     } else {
-      for (int v = 0; v < nv; ++v) ptrs[b][v * pstride + pc] = 0.0;
+      for (int v = 0; v < nv; ++v) out[v * pstride + pc] = 0.0;
     }
   }
 }

@@ -42,20 +42,27 @@ __device__ __forceinline__ int opaque_uniform(int x) {
   return x;
 }
 
-__device__ __forceinline__ const double* cell_addr(const StateTable& st, const BlockDev& B, int buf,
-                                                   int i, int j, int k, long long& vstride) {
+// Pointers into global memory (address space 1).  Block states and scratch
+// slots are reached through pointers read from the block table, which the
+// compiler would otherwise treat as generic: generic accesses compile to
+// flat instructions, whose completion the LDS counter waits for as well, so
+// every LDS wait would also wait for the global loads in flight.
+using gptr = __attribute__((address_space(1))) const double*;
+using gptr_w = __attribute__((address_space(1))) double*;
+
+__device__ __forceinline__ gptr cell_addr(const StateTable& st, const BlockDev& B, int buf, int i, int j, int k,
+                                          long long& vstride) {
   if (buf == 0) {
     vstride = (long long)B.P[0] * B.P[1] * B.P[2];
-    return B.u + (((long long)(k + B.g[2]) * B.P[1] + (j + B.g[1])) * B.P[0] + (i + B.g[0]));
+    return (gptr)(B.u + (((long long)(k + B.g[2]) * B.P[1] + (j + B.g[1])) * B.P[0] + (i + B.g[0])));
   }
   vstride = B.cells;
-  return st.scr + (long long)(buf - 1) * st.slot_stride + B.off +
-         (((long long)k * B.n[1] + j) * B.n[0] + i);
+  return (gptr)(st.scr + (long long)(buf - 1) * st.slot_stride + B.off + (((long long)k * B.n[1] + j) * B.n[0] + i));
 }
 
-__device__ __forceinline__ double* cell_addr_w(const StateTable& st, const BlockDev& B, int buf,
-                                               int i, int j, int k, long long& vstride) {
-  return const_cast<double*>(cell_addr(st, B, buf, i, j, k, vstride));
+__device__ __forceinline__ gptr_w cell_addr_w(const StateTable& st, const BlockDev& B, int buf, int i, int j, int k,
+                                              long long& vstride) {
+  return (gptr_w)cell_addr(st, B, buf, i, j, k, vstride);
 }
 
 // Load all NV variables of cell (i,j,k) of block blk, where only coordinate
@@ -85,7 +92,7 @@ __device__ __forceinline__ void load_cell(const StateTable& st, int blk, int buf
     }
   }
   long long vs;
-  const double* p = cell_addr(st, *B, bf, c[0], c[1], c[2], vs);
+  gptr p = cell_addr(st, *B, bf, c[0], c[1], c[2], vs);
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = p[v * vs];
 }
@@ -115,7 +122,7 @@ __device__ __forceinline__ void load_cell_vars(const StateTable& st, int blk, in
     }
   }
   long long vs;
-  const double* p = cell_addr(st, *B, bf, c[0], c[1], c[2], vs);
+  gptr p = cell_addr(st, *B, bf, c[0], c[1], c[2], vs);
 #pragma unroll
   for (int v = 0; v < VN; ++v) u[v] = p[(V0 + v) * vs];
 }
@@ -136,7 +143,7 @@ __device__ __forceinline__ double load_plane(const StateTable& st, const double*
     c[D] -= B->n[D];
     B = &st.blocks[B->nbr[2 * D + 1]];
   }
-  return a[v * plane + B->coff + ((long long)c[2] * B->n[1] + c[1]) * B->n[0] + c[0]];
+  return ((gptr)a)[v * plane + B->coff + ((long long)c[2] * B->n[1] + c[1]) * B->n[0] + c[0]];
 }
 
 // ---------------------------------------------------------------------------

@@ -50,7 +50,7 @@ namespace amrvac {
 // Fused stage kernel.
 // ---------------------------------------------------------------------------
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
-          bool RUNS = false, bool LIM = false, bool GLM = false, bool HALL = false>
+          bool RUNS = false, bool LIM = false, bool GLM = false, bool HALL = false, bool CORE = false>
 __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
   static_assert(!HALL || (MHD && !GLM), "Hall terms are built for ideal MHD");
   // halo of the extended box: MP5 reaches 3 cells, LIM03 2
@@ -119,6 +119,25 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) L[r][v] = 0.0;
 
+    // CORE: the owned cells' state of buffer `in`, read once per tile; every
+    // direction's phase A then takes the owned cells from registers and loads
+    // only the halo planes, and the stage update takes the source equal to
+    // `in` from registers too.
+    double uc[CORE ? CPT : 1][NV];
+    if constexpr (CORE) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        const int cidx = tid + r * NT;
+        const int a0 = cidx % TX, a1 = (cidx / TX) % TY, a2 = cidx / (TX * TY);
+        if (cidx < TC && a0 < tend[0] && a1 < tend[1] && a2 < tend[2]) {
+          long long vs;
+          gptr p = cell_addr(st, B, P.in, tl.o[0] + a0, tl.o[1] + a1, tl.o[2] + a2, vs);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) uc[r][v] = p[v * vs];
+        }
+      }
+    }
+
     static_for<0, NDIM>([&](auto Dc) {
       constexpr int D = decltype(Dc)::value;
       constexpr int E0 = S::E(D, 0), E1 = S::E(D, 1);
@@ -137,56 +156,92 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
 
       static_for<0, NGRP>([&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
-        // A) split fluxes of the extended tile -> LDS
-        for (int e = tid; e < NEXT_D; e += NT) {
-          int a[3];
-          a[0] = e % E0;
-          a[1] = (e / E0) % E1;
-          a[2] = e / (E0 * E1);
-          bool valid = true;
-          int cc[3];
+        // A) split fluxes of the extended tile -> LDS.  split_to_lds: state u
+        // of the cell at extended-box position a (block coordinates cc).
+        auto split_to_lds = [&](const double* u, const int* a, const int* cc) {
+          PrimD w;
+          ok_all = prim<NDIM, MHD>(u, gamma, w) && ok_all;
+          double F[NV];
+          phys_flux<NDIM, MHD, D>(u, w, F);
+          if constexpr (GLM) {
+            F[5 + D] += u[8];             // psi on the flux of B_D
+            F[8] = (c * c) * u[5 + D];    // c_h^2 B_D
+          }
+          if constexpr (HALL) {
+            // (eta_h/rho)(B_D J - J_D B) on B, (eta_h/rho)((J.B) B_D - B^2 J_D) on E
+            double Jc[3];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            if (d == D) {
-              valid = valid && (a[d] < tend[d] + 2 * HG);
-              cc[d] = tl.o[d] + a[d] - HG;
-            } else {
-              valid = valid && (a[d] < tend[d]);
-              cc[d] = tl.o[d] + a[d];
+            for (int v = 0; v < 3; ++v) Jc[v] = load_plane<D>(st, P.J, P.jplane, v, tl.block, cc[0], cc[1], cc[2]);
+            const double h = P.eta_h / w.rho;
+            const double jb = Jc[0] * w.B[0] + Jc[1] * w.B[1] + Jc[2] * w.B[2];
+            const double bb = w.B[0] * w.B[0] + w.B[1] * w.B[1] + w.B[2] * w.B[2];
+            const double Bd = w.B[D];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) F[5 + k] = F[5 + k] + h * (Bd * Jc[k] - Jc[D] * w.B[k]);
+            F[4] = F[4] + h * (jb * Bd - bb * Jc[D]);
+          }
+          const int el = a[0] + E0P * (a[1] + E1 * a[2]);
+#pragma unroll
+          for (int vg = 0; vg < VPG; ++vg) {
+            const int v = G * VPG + vg;
+            if (v < NV) {
+              lds[vg * NEXTP + el] = 0.5 * fma(c, u[v], F[v]);
+              lds[(VPG + vg) * NEXTP + el] = 0.5 * fma(-c, u[v], F[v]);
             }
           }
-          if (valid) {
+        };
+        if constexpr (CORE) {
+          // owned cells from registers
+#pragma unroll
+          for (int r = 0; r < CPT; ++r) {
+            const int cidx = tid + r * NT;
+            int a[3] = {cidx % TX, (cidx / TX) % TY, cidx / (TX * TY)};
+            if (cidx < TC && a[0] < tend[0] && a[1] < tend[1] && a[2] < tend[2]) {
+              const int cc[3] = {tl.o[0] + a[0], tl.o[1] + a[1], tl.o[2] + a[2]};
+              a[D] += HG;
+              split_to_lds(uc[r], a, cc);
+            }
+          }
+          // the 2 HG halo planes along D from memory: plane p < HG is
+          // extended-box row p, plane p >= HG row tend_D + p
+          constexpr int H0 = D == 0 ? 2 * HG : TX, H1 = D == 1 ? 2 * HG : TY, H2 = D == 2 ? 2 * HG : TZ;
+          for (int h = tid; h < H0 * H1 * H2; h += NT) {
+            int a[3] = {h % H0, (h / H0) % H1, h / (H0 * H1)};
+            bool valid = true;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+              if (d != D) valid = valid && (a[d] < tend[d]);
+            if (!valid) continue;
+            if (a[D] >= HG) a[D] += tend[D];
+            int cc[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) cc[d] = tl.o[d] + a[d] - (d == D ? HG : 0);
             double u[NV];
             load_cell<NV, D>(st, tl.block, P.in, cc[0], cc[1], cc[2], u);
-            PrimD w;
-            ok_all = prim<NDIM, MHD>(u, gamma, w) && ok_all;
-            double F[NV];
-            phys_flux<NDIM, MHD, D>(u, w, F);
-            if constexpr (GLM) {
-              F[5 + D] += u[8];             // psi on the flux of B_D
-              F[8] = (c * c) * u[5 + D];    // c_h^2 B_D
-            }
-            if constexpr (HALL) {
-              // (eta_h/rho)(B_D J - J_D B) on B, (eta_h/rho)((J.B) B_D - B^2 J_D) on E
-              double Jc[3];
+            split_to_lds(u, a, cc);
+          }
+        } else {
+          for (int e = tid; e < NEXT_D; e += NT) {
+            int a[3];
+            a[0] = e % E0;
+            a[1] = (e / E0) % E1;
+            a[2] = e / (E0 * E1);
+            bool valid = true;
+            int cc[3];
 #pragma unroll
-              for (int v = 0; v < 3; ++v) Jc[v] = load_plane<D>(st, P.J, P.jplane, v, tl.block, cc[0], cc[1], cc[2]);
-              const double h = P.eta_h / w.rho;
-              const double jb = Jc[0] * w.B[0] + Jc[1] * w.B[1] + Jc[2] * w.B[2];
-              const double bb = w.B[0] * w.B[0] + w.B[1] * w.B[1] + w.B[2] * w.B[2];
-              const double Bd = w.B[D];
-#pragma unroll
-              for (int k = 0; k < 3; ++k) F[5 + k] = F[5 + k] + h * (Bd * Jc[k] - Jc[D] * w.B[k]);
-              F[4] = F[4] + h * (jb * Bd - bb * Jc[D]);
-            }
-            const int el = a[0] + E0P * (a[1] + E1 * a[2]);
-#pragma unroll
-            for (int vg = 0; vg < VPG; ++vg) {
-              const int v = G * VPG + vg;
-              if (v < NV) {
-                lds[vg * NEXTP + el] = 0.5 * fma(c, u[v], F[v]);
-                lds[(VPG + vg) * NEXTP + el] = 0.5 * fma(-c, u[v], F[v]);
+            for (int d = 0; d < 3; ++d) {
+              if (d == D) {
+                valid = valid && (a[d] < tend[d] + 2 * HG);
+                cc[d] = tl.o[d] + a[d] - HG;
+              } else {
+                valid = valid && (a[d] < tend[d]);
+                cc[d] = tl.o[d] + a[d];
               }
+            }
+            if (valid) {
+              double u[NV];
+              load_cell<NV, D>(st, tl.block, P.in, cc[0], cc[1], cc[2], u);
+              split_to_lds(u, a, cc);
             }
           }
         }
@@ -400,15 +455,34 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
       if (!(a[0] < tend[0] && a[1] < tend[1] && a[2] < tend[2])) continue;
       const int i = tl.o[0] + a[0], j = tl.o[1] + a[1], k = tl.o[2] + a[2];
       if (P.mode == 1) {
-        double* out = P.rhs_out[tl.block] + (((long long)k * B.n[1] + j) * B.n[0] + i);
+        gptr_w out = (gptr_w)(P.rhs_out[tl.block] + (((long long)k * B.n[1] + j) * B.n[0] + i));
 #pragma unroll
         for (int v = 0; v < NV; ++v) out[v * B.cells] = L[r][v];
         continue;
       }
       double un[NV];
-      {
+      if constexpr (CORE) {
+        // the same sum, source by source; the source equal to `in` from
+        // registers
+        double acc[NV];
+#pragma unroll
+        for (int q = 0; q < MAX_SRC; ++q) {
+          if (q >= P.nsrc) continue;
+          if (P.src[q] == P.in) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] = q == 0 ? P.a[0] * uc[CORE ? r : 0][v] : fma(P.a[q], uc[CORE ? r : 0][v], acc[v]);
+          } else {
+            long long vs;
+            gptr sp = cell_addr(st, B, opaque_uniform(P.src[q]), i, j, k, vs);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] = q == 0 ? P.a[0] * sp[v * vs] : fma(P.a[q], sp[v * vs], acc[v]);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) un[v] = fma(dtb, L[r][v], acc[v]);
+      } else {
         long long vs[MAX_SRC];
-        const double* sp[MAX_SRC];
+        gptr sp[MAX_SRC];
 #pragma unroll
         for (int q = 0; q < MAX_SRC; ++q)
           if (q < P.nsrc) sp[q] = cell_addr(st, B, opaque_uniform(P.src[q]), i, j, k, vs[q]);
@@ -420,30 +494,52 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
             if (q < P.nsrc) acc = fma(P.a[q], sp[q][v * vs[q]], acc);
           un[v] = fma(dtb, L[r][v], acc);
         }
+      }
+      {
         if constexpr (GLM) {
           if (P.decay_psi) un[8] = un[8] * psi_decay;   // operator-split decay of psi
         }
       }
       if (P.sdst >= 0) {
         long long vs[MAX_SRC];
-        const double* sp[MAX_SRC];
-#pragma unroll
-        for (int q = 0; q < MAX_SRC; ++q)
-          if (q < P.snsrc) sp[q] = cell_addr(st, B, opaque_uniform(P.ssrc[q]), i, j, k, vs[q]);
+        gptr sp[MAX_SRC];
         long long ws;
-        double* sd = cell_addr_w(st, B, opaque_uniform(P.sdst), i, j, k, ws);
+        gptr_w sd = cell_addr_w(st, B, opaque_uniform(P.sdst), i, j, k, ws);
+        if constexpr (CORE) {
+          double acc[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          double acc = P.sa[0] * sp[0][v * vs[0]];
+          for (int q = 0; q < MAX_SRC; ++q) {
+            if (q >= P.snsrc) continue;
+            if (P.ssrc[q] == P.in) {
 #pragma unroll
-          for (int q = 1; q < MAX_SRC; ++q)
-            if (q < P.snsrc) acc = fma(P.sa[q], sp[q][v * vs[q]], acc);
-          sd[v * ws] = fma(dtsb, L[r][v], acc);
+              for (int v = 0; v < NV; ++v)
+                acc[v] = q == 0 ? P.sa[0] * uc[CORE ? r : 0][v] : fma(P.sa[q], uc[CORE ? r : 0][v], acc[v]);
+            } else {
+              long long vq;
+              gptr spq = cell_addr(st, B, opaque_uniform(P.ssrc[q]), i, j, k, vq);
+#pragma unroll
+              for (int v = 0; v < NV; ++v) acc[v] = q == 0 ? P.sa[0] * spq[v * vq] : fma(P.sa[q], spq[v * vq], acc[v]);
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sd[v * ws] = fma(dtsb, L[r][v], acc[v]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < MAX_SRC; ++q)
+            if (q < P.snsrc) sp[q] = cell_addr(st, B, opaque_uniform(P.ssrc[q]), i, j, k, vs[q]);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            double acc = P.sa[0] * sp[0][v * vs[0]];
+#pragma unroll
+            for (int q = 1; q < MAX_SRC; ++q)
+              if (q < P.snsrc) acc = fma(P.sa[q], sp[q][v * vs[q]], acc);
+            sd[v * ws] = fma(dtsb, L[r][v], acc);
+          }
         }
       }
       {
         long long ws;
-        double* dp = cell_addr_w(st, B, opaque_uniform(P.dst), i, j, k, ws);
+        gptr_w dp = cell_addr_w(st, B, opaque_uniform(P.dst), i, j, k, ws);
 #pragma unroll
         for (int v = 0; v < NV; ++v) dp[v * ws] = un[v];
       }
@@ -508,7 +604,7 @@ __global__ void __launch_bounds__(256) k_cmax(CmaxParams P) {
       const int k = tl.o[2] + c / (P.tx * P.ty);
       if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
       long long vs;
-      const double* p = cell_addr(P.st, B, P.in, i, j, k, vs);
+      gptr p = cell_addr(P.st, B, P.in, i, j, k, vs);
       double u[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) u[v] = p[v * vs];
@@ -591,8 +687,8 @@ __global__ void __launch_bounds__(256) k_copy_interior(StateTable st, const Tile
       const int i = tl.o[0] + c % tx, j = tl.o[1] + (c / tx) % ty, k = tl.o[2] + c / (tx * ty);
       if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
       long long vs, ws;
-      const double* p = cell_addr(st, B, src, i, j, k, vs);
-      double* q = cell_addr_w(st, B, dst, i, j, k, ws);
+      gptr p = cell_addr(st, B, src, i, j, k, vs);
+      gptr_w q = cell_addr_w(st, B, dst, i, j, k, ws);
       for (int v = 0; v < nv; ++v) q[v * ws] = p[v * vs];
     }
   }
@@ -709,10 +805,10 @@ struct StageVariant {
 };
 
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
-          bool RUNS = false, bool LIM = false, bool GLM = false, bool HALL = false>
+          bool RUNS = false, bool LIM = false, bool GLM = false, bool HALL = false, bool CORE = false>
 static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE, EMIT, RUNS, LIM, GLM, HALL>), dim3(grid),
-                     dim3(NT), 0, s, p);
+  hipLaunchKernelGGL((k_stage<NDIM, MHD, TX, TY, TZ, NT, NGRP, WPE, EMIT, RUNS, LIM, GLM, HALL, CORE>),
+                     dim3(grid), dim3(NT), 0, s, p);
 }
 
 // rec: the reconstruction (0 MP5, 1 LIM03)
@@ -725,6 +821,12 @@ static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
   {ND, M, 0, 0, TX, TY, TZ, NT, NGRP, WPE, (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>, \
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs"}
+// the same with the owned cells' state kept in registers for the whole tile
+#define AMRVAC_VARIANT_RC(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                  \
+  {ND, M, 0, 0, TX, TY, TZ, NT, NGRP, WPE,                                                                   \
+   (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true, false, false, false, true>,          \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true, false, false, false, true>,                  \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-core"}
 // GLM-MHD (physics code 2), MP5 or LIM03 (REC), in runs along each pencil
 #define AMRVAC_VARIANT_G(ND, REC, TX, TY, TZ, NT, NGRP, WPE)                                                    \
   {ND, 2, REC, 0, TX, TY, TZ, NT, NGRP, WPE,                                                                       \
@@ -748,6 +850,24 @@ static void launch_stage(const StageParams& p, int grid, hipStream_t s) {
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, false, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-lim03"}
 
+// Owned cells kept in registers for the whole tile (CORE), for LIM03, GLM
+// and Hall MHD
+#define AMRVAC_VARIANT_LRC(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                  \
+  {ND, M, 1, 0, TX, TY, TZ, NT, NGRP, WPE,                                                                   \
+   (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true, true, false, false, true>,           \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, false, true, true, false, false, true>,                   \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-lim03-core"}
+#define AMRVAC_VARIANT_GC(ND, REC, TX, TY, TZ, NT, NGRP, WPE)                                                 \
+  {ND, 2, REC, 0, TX, TY, TZ, NT, NGRP, WPE,                                                                 \
+   (const void*)&k_stage<ND, true, TX, TY, TZ, NT, NGRP, WPE, false, true, (REC == 1), true, false, true>,   \
+   &launch_stage<ND, true, TX, TY, TZ, NT, NGRP, WPE, false, true, (REC == 1), true, false, true>,           \
+   #ND "d-glm-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-rec" #REC "-core"}
+#define AMRVAC_VARIANT_HC(ND, REC, TX, TY, TZ, NT, NGRP, WPE)                                                 \
+  {ND, 1, REC, 1, TX, TY, TZ, NT, NGRP, WPE,                                                                 \
+   (const void*)&k_stage<ND, true, TX, TY, TZ, NT, NGRP, WPE, false, true, (REC == 1), false, true, true>,   \
+   &launch_stage<ND, true, TX, TY, TZ, NT, NGRP, WPE, false, true, (REC == 1), false, true, true>,           \
+   #ND "d-hall-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-rec" #REC "-core"}
+
 // Tile shapes the autotuner chooses from (the first of each (ndim,
 // physics) is the default).  WPE = minimum waves per SIMD requested from
 // the register allocator.
@@ -755,50 +875,53 @@ static const StageVariant g_variants[] = {
     // 1D
     AMRVAC_VARIANT(1, false, 128, 1, 1, 128, 1, 1),
     AMRVAC_VARIANT(1, false, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT_RC(1, false, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT(1, true, 128, 1, 1, 128, 1, 1),
     AMRVAC_VARIANT(1, true, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_R(1, true, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT_RC(1, true, 64, 1, 1, 64, 1, 1),
     // 2D
     AMRVAC_VARIANT(2, false, 16, 16, 1, 256, 1, 1),
     AMRVAC_VARIANT(2, false, 16, 16, 1, 256, 1, 3),
     AMRVAC_VARIANT(2, false, 32, 8, 1, 256, 1, 1),
     AMRVAC_VARIANT_R(2, false, 16, 16, 1, 256, 1, 1),
+    AMRVAC_VARIANT_RC(2, false, 16, 16, 1, 256, 1, 2),
     AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 2, 1),
     AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 1, 1),
     AMRVAC_VARIANT(2, true, 16, 16, 1, 256, 2, 3),
     AMRVAC_VARIANT(2, true, 32, 8, 1, 256, 2, 1),
     AMRVAC_VARIANT_R(2, true, 16, 16, 1, 256, 1, 1),
     AMRVAC_VARIANT_R(2, true, 16, 16, 1, 256, 2, 2),
-    // 3D
+    AMRVAC_VARIANT_RC(2, true, 16, 16, 1, 256, 1, 2),
+    AMRVAC_VARIANT_RC(2, true, 16, 16, 1, 256, 2, 2),
+    // 3D: the owned-cell (CORE) forms first
+    AMRVAC_VARIANT_RC(3, false, 8, 8, 4, 256, 1, 2),
     AMRVAC_VARIANT(3, false, 8, 8, 8, 512, 2, 1),
     AMRVAC_VARIANT(3, false, 8, 8, 4, 256, 1, 1),
-    AMRVAC_VARIANT(3, false, 8, 8, 8, 512, 2, 4),
     AMRVAC_VARIANT_R(3, false, 8, 8, 4, 256, 1, 2),
+    AMRVAC_VARIANT_RC(3, true, 8, 8, 8, 512, 1, 2),
+    AMRVAC_VARIANT_RC(3, true, 8, 8, 4, 256, 1, 2),
+    AMRVAC_VARIANT_RC(3, true, 8, 4, 4, 128, 1, 2),
+    AMRVAC_VARIANT_RC(3, true, 8, 8, 4, 256, 2, 3),
     AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 4),
-    AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 2, 1),
-    AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 2, 4),
-    AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 2, 1),
-    AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 2, 3),
-    AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 4, 4),
-    AMRVAC_VARIANT(3, true, 8, 8, 8, 512, 4, 4),
-    AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 1),
-    AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 2),
     AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 2, 3),
-    AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 1),
-    AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 2),
     AMRVAC_VARIANT_R(3, true, 8, 8, 8, 512, 2, 4),
-    // LIM03 (pencil runs first: the defaults)
+    AMRVAC_VARIANT_R(3, true, 8, 8, 4, 256, 1, 2),
+    AMRVAC_VARIANT(3, true, 8, 8, 4, 256, 2, 3),
+    // LIM03 (the default of each (ndim, physics) first)
     AMRVAC_VARIANT_LR(1, true, 64, 1, 1, 64, 1, 1),
+    AMRVAC_VARIANT_LRC(1, true, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_LR(2, false, 16, 16, 1, 256, 1, 1),
+    AMRVAC_VARIANT_LRC(2, false, 16, 16, 1, 256, 1, 2),
     AMRVAC_VARIANT_LR(2, true, 16, 16, 1, 256, 1, 1),
     AMRVAC_VARIANT_LR(2, true, 16, 16, 1, 256, 2, 2),
+    AMRVAC_VARIANT_LRC(2, true, 16, 16, 1, 256, 1, 2),
+    AMRVAC_VARIANT_LRC(3, false, 8, 8, 4, 256, 1, 2),
     AMRVAC_VARIANT_LR(3, false, 8, 8, 4, 256, 1, 2),
+    AMRVAC_VARIANT_LRC(3, true, 8, 8, 4, 256, 1, 2),
+    AMRVAC_VARIANT_LRC(3, true, 8, 8, 8, 512, 1, 2),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 4),
-    AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 1),
-    AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 2),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 4, 256, 2, 3),
-    AMRVAC_VARIANT_LR(3, true, 8, 8, 8, 512, 2, 1),
-    AMRVAC_VARIANT_LR(3, true, 8, 8, 8, 512, 2, 2),
     AMRVAC_VARIANT_LR(3, true, 8, 8, 8, 512, 2, 4),
     AMRVAC_VARIANT_L(1, false, 128, 1, 1, 128, 1, 1),
     AMRVAC_VARIANT_L(1, false, 64, 1, 1, 64, 1, 1),
@@ -811,33 +934,32 @@ static const StageVariant g_variants[] = {
     AMRVAC_VARIANT_L(2, true, 32, 8, 1, 256, 2, 1),
     AMRVAC_VARIANT_L(3, false, 8, 8, 4, 256, 1, 1),
     AMRVAC_VARIANT_L(3, false, 8, 8, 8, 512, 2, 1),
-    AMRVAC_VARIANT_L(3, true, 8, 8, 4, 256, 2, 1),
     AMRVAC_VARIANT_L(3, true, 8, 8, 4, 256, 2, 3),
-    AMRVAC_VARIANT_L(3, true, 8, 8, 8, 512, 2, 1),
-    AMRVAC_VARIANT_L(3, true, 8, 8, 4, 256, 4, 4),
     // GLM-MHD
     AMRVAC_VARIANT_G(1, 0, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_G(2, 0, 16, 16, 1, 256, 2, 2),
     AMRVAC_VARIANT_G(2, 0, 16, 16, 1, 256, 1, 1),
+    AMRVAC_VARIANT_GC(2, 0, 16, 16, 1, 256, 1, 2),
+    AMRVAC_VARIANT_GC(3, 0, 8, 8, 4, 256, 1, 2),
+    AMRVAC_VARIANT_GC(3, 0, 8, 8, 8, 512, 1, 2),
+    AMRVAC_VARIANT_GC(3, 0, 8, 8, 4, 256, 3, 3),
     AMRVAC_VARIANT_G(3, 0, 8, 8, 4, 256, 2, 3),
-    AMRVAC_VARIANT_G(3, 0, 8, 8, 4, 256, 2, 1),
-    AMRVAC_VARIANT_G(3, 0, 8, 8, 4, 256, 3, 3),
     AMRVAC_VARIANT_G(3, 0, 8, 8, 4, 256, 3, 4),
     AMRVAC_VARIANT_G(1, 1, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_G(2, 1, 16, 16, 1, 256, 2, 2),
-    AMRVAC_VARIANT_G(3, 1, 8, 8, 4, 256, 2, 1),
-    AMRVAC_VARIANT_G(3, 1, 8, 8, 4, 256, 2, 3),
+    AMRVAC_VARIANT_GC(3, 1, 8, 8, 4, 256, 1, 2),
     AMRVAC_VARIANT_G(3, 1, 8, 8, 4, 256, 2, 4),
+    AMRVAC_VARIANT_G(3, 1, 8, 8, 4, 256, 2, 3),
     // Hall MHD
     AMRVAC_VARIANT_H(1, 0, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_H(2, 0, 16, 16, 1, 256, 2, 2),
+    AMRVAC_VARIANT_HC(3, 0, 8, 8, 4, 256, 1, 2),
     AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 4),
     AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 2),
-    AMRVAC_VARIANT_H(3, 0, 8, 8, 4, 256, 2, 1),
     AMRVAC_VARIANT_H(1, 1, 64, 1, 1, 64, 1, 1),
     AMRVAC_VARIANT_H(2, 1, 16, 16, 1, 256, 2, 2),
+    AMRVAC_VARIANT_HC(3, 1, 8, 8, 4, 256, 1, 2),
     AMRVAC_VARIANT_H(3, 1, 8, 8, 4, 256, 2, 4),
-    AMRVAC_VARIANT_H(3, 1, 8, 8, 4, 256, 2, 1),
 };
 
 const StageVariant* stage_variants(int* count) {
@@ -856,19 +978,30 @@ const StageVariant* stage_variants(int* count) {
    &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true, true>,                                             \
    #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-lim03-emit"}
 
+#define AMRVAC_EMIT_C(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                       \
+  {ND, M, 0, 0, TX, TY, TZ, NT, NGRP, WPE,                                                                   \
+   (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true, false, false, false, true>,           \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true, false, false, false, true>,                   \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-emit-core"}
+#define AMRVAC_EMIT_LC(ND, M, TX, TY, TZ, NT, NGRP, WPE)                                                      \
+  {ND, M, 1, 0, TX, TY, TZ, NT, NGRP, WPE,                                                                   \
+   (const void*)&k_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true, true, false, false, true>,            \
+   &launch_stage<ND, M, TX, TY, TZ, NT, NGRP, WPE, true, true, true, false, false, true>,                    \
+   #ND "d-" #M "-tile" #TX "x" #TY "x" #TZ "-nt" #NT "-g" #NGRP "-w" #WPE "-runs-lim03-emit-core"}
+
 static const StageVariant g_emit[] = {
     AMRVAC_EMIT(1, false, 64, 1, 1, 64, 1, 1),
     AMRVAC_EMIT(1, true, 64, 1, 1, 64, 1, 1),
-    AMRVAC_EMIT(2, false, 16, 16, 1, 256, 1, 1),
-    AMRVAC_EMIT(2, true, 16, 16, 1, 256, 2, 1),
-    AMRVAC_EMIT(3, false, 8, 8, 4, 256, 1, 2),
-    AMRVAC_EMIT(3, true, 8, 8, 4, 256, 2, 2),
+    AMRVAC_EMIT_C(2, false, 16, 16, 1, 256, 1, 2),
+    AMRVAC_EMIT_C(2, true, 16, 16, 1, 256, 1, 2),
+    AMRVAC_EMIT_C(3, false, 8, 8, 4, 256, 1, 2),
+    AMRVAC_EMIT_C(3, true, 8, 8, 4, 256, 1, 2),
     AMRVAC_EMIT_L(1, false, 64, 1, 1, 64, 1, 1),
     AMRVAC_EMIT_L(1, true, 64, 1, 1, 64, 1, 1),
-    AMRVAC_EMIT_L(2, false, 16, 16, 1, 256, 1, 1),
-    AMRVAC_EMIT_L(2, true, 16, 16, 1, 256, 2, 1),
-    AMRVAC_EMIT_L(3, false, 8, 8, 4, 256, 1, 2),
-    AMRVAC_EMIT_L(3, true, 8, 8, 4, 256, 2, 2),
+    AMRVAC_EMIT_LC(2, false, 16, 16, 1, 256, 1, 2),
+    AMRVAC_EMIT_LC(2, true, 16, 16, 1, 256, 1, 2),
+    AMRVAC_EMIT_LC(3, false, 8, 8, 4, 256, 1, 2),
+    AMRVAC_EMIT_LC(3, true, 8, 8, 4, 256, 1, 2),
 };
 
 const StageVariant* emit_variant(int ndim, int mhd, int rec) {
