@@ -114,7 +114,7 @@ struct Adj {
     StateTable st = state_table(c);
     V->argmax(st, d_tiles, ntiles(), V->tx, V->ty, V->tz, c->cfg.gamma, state, d_tmax, d_targ, grid_small,
               c->stream);
-    launch_argmax_reduce(d_tmax, d_targ, ntiles(), c->d_ctl, VJP_SLOT, c->stream);
+    launch_argmax_reduce(d_tmax, d_targ, grid_small, c->d_ctl, VJP_SLOT, c->stream);
     VjpParams p{};
     p.st = st;
     p.tiles = d_tiles;
@@ -140,7 +140,7 @@ struct Adj {
     p.cm_slot = VJP_SLOT;
     p.cpart = d_cpart;
     V->launch(p, grid_vjp, c->stream);
-    V->cmax_term(st, (int)c->hb.size(), d_cpart, ntiles(), c->d_ctl, c->cfg.gamma, state, dst, dt, c->stream);
+    V->cmax_term(st, (int)c->hb.size(), d_cpart, grid_vjp, c->d_ctl, c->cfg.gamma, state, dst, dt, c->stream);
   }
 };
 

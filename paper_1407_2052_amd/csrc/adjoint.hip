@@ -268,6 +268,9 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
   for (int d = 0; d < 3; ++d) cin[d] = __longlong_as_double((long long)P.ctl->cm[P.cm_slot][d]);
   __syncthreads();
 
+  // c_max adjoint sums of this work-group's tiles (taken in the fixed tile
+  // order of the schedule, then a fixed butterfly: deterministic)
+  double cp[3] = {0.0, 0.0, 0.0};
   const TileSchedule sched(P.ntiles);
   for (int t = sched.t; t < sched.end; t += sched.step) {
     const Tile tl = P.tiles[t];
@@ -278,12 +281,13 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
       const int rem = B.n[d] - tl.o[d];
       tend[d] = rem < S::T(d) ? rem : S::T(d);
     }
-    // owned cells: state, primitives, accumulators
+    // owned cells: state, primitives, accumulators, and mu (formed once per
+    // tile; each direction then loads only the halo rows of mu)
     double uo[CPT][NV];
     PrimD wo[CPT];
     double nu[CPT][NV];
+    double muo[CPT][NV];
     bool own[CPT];
-    double cp[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
       const int cidx = tid + r * NT;
@@ -302,6 +306,16 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
         uo[r][E::IE] = 1.0;
       }
       prim<NDIM, MHD>(uo[r], gamma, wo[r]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) muo[r][v] = 0.0;
+      if (own[r]) {
+        for (int q = 0; q < P.nmu; ++q) {
+          long long vs;
+          gptr p = cell_addr(st, B, P.mu_src[q], tl.o[0] + a0, tl.o[1] + a1, tl.o[2] + a2, vs);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) muo[r][v] = fma(P.mu_a[q], p[v * vs], muo[r][v]);
+        }
+      }
     }
 
     static_for<0, NDIM>([&](auto Dc) {
@@ -314,13 +328,27 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
       const double c = cin[D];
       const double idx_d = B.inv_dx[D];
 
-      // A) mu on the extended box, codes on the interface box (memory order)
-      for (int e = tid; e < E0 * E1 * E2; e += NT) {
-        const int a[3] = {e % E0, (e / E0) % E1, e / (E0 * E1)};
+      // A) mu on the extended box (owned cells from registers, the 3 + 3
+      // halo rows along D from memory), codes on the interface box
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        if (!own[r]) continue;
+        const int cidx = tid + r * NT;
+        int a[3] = {cidx % TX, (cidx / TX) % TY, cidx / (TX * TY)};
+        const int pen = S::PENC(D, a[0], a[1], a[2]);
+        const int row = a[D] + 3;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sMu[(v * MR + row) * PS + pen] = muo[r][v];
+      }
+      constexpr int H0 = D == 0 ? 6 : TX, H1 = D == 1 ? 6 : TY, H2 = D == 2 ? 6 : TZ;
+      for (int e = tid; e < H0 * H1 * H2; e += NT) {
+        int a[3] = {e % H0, (e / H0) % H1, e / (H0 * H1)};
         bool valid = true;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) valid = valid && a[d] < tend[d] + (d == D ? 6 : 0);
+        for (int d = 0; d < 3; ++d)
+          if (d != D) valid = valid && a[d] < tend[d];
         if (!valid) continue;
+        if (a[D] >= 3) a[D] += tend[D];   // rows 0..2 below the tile, tend+3 .. tend+5 above
         int cc[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) cc[d] = tl.o[d] + a[d] - (d == D ? 3 : 0);
@@ -353,7 +381,8 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
         unsigned long long code = 0ull;
         if (Bn) {
           const long long cell = ((long long)cc[2] * Bn->n[1] + cc[1]) * Bn->n[0] + cc[0];
-          code = *reinterpret_cast<const unsigned long long*>(P.codes + D * P.code_plane + (Bn->coff + cell) * 8);
+          code = *(__attribute__((address_space(1))) const unsigned long long*)(P.codes + D * P.code_plane +
+                                                                               (Bn->coff + cell) * 8);
         }
         sCode[a[D] * PS + S::PENC(D, a[0], a[1], a[2])] = code;
       }
@@ -455,28 +484,22 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) p[v * ws] = fma(P.scale, nu[r][v], acc[v]);
     }
-    // per-tile c_max adjoint sums (fixed reduction order)
+  }
+  // per-work-group c_max adjoint sums
+#pragma unroll
+  for (int d = 0; d < 3; ++d) cp[d] = wave_sum(cp[d]);
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) red[tid >> 6][d] = cp[d];
+  }
+  __syncthreads();
+  if (tid == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      double x = cp[d];
-#pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
-      cp[d] = x;
+      double x = red[0][d];
+      for (int q = 1; q < NT / 64; ++q) x += red[q][d];
+      P.cpart[3 * (long long)blockIdx.x + d] = x;
     }
-    if ((tid & 63) == 0) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) red[tid >> 6][d] = cp[d];
-    }
-    __syncthreads();
-    if (tid == 0) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        double x = red[0][d];
-        for (int q = 1; q < NT / 64; ++q) x += red[q][d];
-        P.cpart[3 * (long long)t + d] = x;
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -487,19 +510,32 @@ __device__ __forceinline__ bool better(double v, long long k, double bv, long lo
   return v > bv || (v == bv && k < bk);
 }
 
+// (value, key) maximum over the 64 lanes of a wave (largest value, then
+// lowest key): the result is the same whatever the order.
+__device__ __forceinline__ void argmax_wave(double& v, long long& k) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double ov = __shfl_xor(v, m, 64);
+    const long long ok = __shfl_xor(k, m, 64);
+    if (better(ov, ok, v, k)) { v = ov; k = ok; }
+  }
+}
+
+// Per work-group: the largest |v_d| + c_f,d over the work-group's tiles and
+// its lowest (block, cell) key, into tmax / targ[3 * blockIdx.x + d].
 template <int NDIM, bool MHD>
 __global__ void __launch_bounds__(256) k_argmax_tiles(StateTable st, const Tile* tiles, int ntiles, int tx, int ty,
                                                       int tz, double gamma, int in, double* tmax, long long* targ) {
   using E = Eq<NDIM, MHD>;
-  __shared__ double sv[256][3];
-  __shared__ long long sk[256][3];
+  __shared__ double sv[4][3];
+  __shared__ long long sk[4][3];
   const int tid = threadIdx.x;
   const int tcells = tx * ty * tz;
+  double bv[3] = {-1.0, -1.0, -1.0};
+  long long bk[3] = {0x7fffffffffffffffll, 0x7fffffffffffffffll, 0x7fffffffffffffffll};
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const Tile tl = tiles[t];
     const BlockDev& B = st.blocks[tl.block];
-    double bv[3] = {-1.0, -1.0, -1.0};
-    long long bk[3] = {0x7fffffffffffffffll, 0x7fffffffffffffffll, 0x7fffffffffffffffll};
     for (int c = tid; c < tcells; c += 256) {
       const int i = tl.o[0] + c % tx, j = tl.o[1] + (c / tx) % ty, k = tl.o[2] + c / (tx * ty);
       if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
@@ -517,77 +553,90 @@ __global__ void __launch_bounds__(256) k_argmax_tiles(StateTable st, const Tile*
         if (better(s, key, bv[d], bk[d])) { bv[d] = s; bk[d] = key; }
       }
     }
+  }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) { sv[tid][d] = bv[d]; sk[tid][d] = bk[d]; }
-    __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
-      if (tid < h) {
+  for (int d = 0; d < 3; ++d) argmax_wave(bv[d], bk[d]);
+  if ((tid & 63) == 0) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-          if (better(sv[tid + h][d], sk[tid + h][d], sv[tid][d], sk[tid][d])) {
-            sv[tid][d] = sv[tid + h][d];
-            sk[tid][d] = sk[tid + h][d];
-          }
-      }
-      __syncthreads();
+    for (int d = 0; d < 3; ++d) { sv[tid >> 6][d] = bv[d]; sk[tid >> 6][d] = bk[d]; }
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double v = sv[0][d];
+      long long k = sk[0][d];
+      for (int q = 1; q < 4; ++q)
+        if (better(sv[q][d], sk[q][d], v, k)) { v = sv[q][d]; k = sk[q][d]; }
+      tmax[3 * (long long)blockIdx.x + d] = v;
+      targ[3 * (long long)blockIdx.x + d] = k;
     }
-    if (tid == 0) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) { tmax[3 * (long long)t + d] = sv[0][d]; targ[3 * (long long)t + d] = sk[0][d]; }
-    }
-    __syncthreads();
   }
 }
 
-__global__ void __launch_bounds__(256) k_argmax_reduce(const double* tmax, const long long* targ, int ntiles,
-                                                       Control* ctl, int slot) {
-  __shared__ double sv[256][3];
-  __shared__ long long sk[256][3];
+// The global maximum and its key from the n per-work-group results (one
+// work-group of 1024 threads); the order of the reduction does not matter
+// (largest value, then lowest key).
+__global__ void __launch_bounds__(1024) k_argmax_reduce(const double* tmax, const long long* targ, int n,
+                                                        Control* ctl, int slot) {
+  __shared__ double sv[16][3];
+  __shared__ long long sk[16][3];
   const int tid = threadIdx.x;
   double bv[3] = {-1.0, -1.0, -1.0};
   long long bk[3] = {0x7fffffffffffffffll, 0x7fffffffffffffffll, 0x7fffffffffffffffll};
-  for (int t = tid; t < ntiles; t += 256)
+  for (int t = tid; t < n; t += 1024)
+#pragma unroll
     for (int d = 0; d < 3; ++d)
       if (better(tmax[3 * (long long)t + d], targ[3 * (long long)t + d], bv[d], bk[d])) {
         bv[d] = tmax[3 * (long long)t + d];
         bk[d] = targ[3 * (long long)t + d];
       }
-  for (int d = 0; d < 3; ++d) { sv[tid][d] = bv[d]; sk[tid][d] = bk[d]; }
-  __syncthreads();
-  for (int h = 128; h >= 1; h >>= 1) {
-    if (tid < h)
-      for (int d = 0; d < 3; ++d)
-        if (better(sv[tid + h][d], sk[tid + h][d], sv[tid][d], sk[tid][d])) {
-          sv[tid][d] = sv[tid + h][d];
-          sk[tid][d] = sk[tid + h][d];
-        }
-    __syncthreads();
+#pragma unroll
+  for (int d = 0; d < 3; ++d) argmax_wave(bv[d], bk[d]);
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { sv[tid >> 6][d] = bv[d]; sk[tid >> 6][d] = bk[d]; }
   }
+  __syncthreads();
   if (tid == 0)
     for (int d = 0; d < 3; ++d) {
-      const double m = sv[0][d] < 0.0 ? 0.0 : sv[0][d];
+      double v = sv[0][d];
+      long long k = sk[0][d];
+      for (int q = 1; q < 16; ++q)
+        if (better(sv[q][d], sk[q][d], v, k)) { v = sv[q][d]; k = sk[q][d]; }
+      const double m = v < 0.0 ? 0.0 : v;
       ctl->cm[slot][d] = (unsigned long long)__double_as_longlong(m);
-      ctl->arg[d] = sk[0][d];
+      ctl->arg[d] = k;
     }
 }
 
-// Sum of the per-tile c_max adjoints (fixed order), then
+// Sum of the per-work-group c_max adjoints (fixed order: strided per
+// thread, then a fixed butterfly per wave, then the 16 waves in order), then
 // lam[argmax_d] += scale * lamc_d * d(|v_d| + c_f,d)/dU at the maximiser.
 template <int NDIM, bool MHD>
-__global__ void __launch_bounds__(256) k_vjp_cmax(StateTable st, int nblocks, const double* cpart, int ntiles,
-                                                  Control* ctl, double gamma, int in, int lam, double scale) {
+__global__ void __launch_bounds__(1024) k_vjp_cmax(StateTable st, int nblocks, const double* cpart, int nparts,
+                                                   Control* ctl, double gamma, int in, int lam, double scale) {
   using E = Eq<NDIM, MHD>;
-  __shared__ double s[256][3];
+  __shared__ double s[1][3];
+  __shared__ double ws[16][3];
   const int tid = threadIdx.x;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int t = tid; t < ntiles; t += 256)
+  for (int t = tid; t < nparts; t += 1024)
+#pragma unroll
     for (int d = 0; d < 3; ++d) acc[d] += cpart[3 * (long long)t + d];
-  for (int d = 0; d < 3; ++d) s[tid][d] = acc[d];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) acc[d] = wave_sum(acc[d]);
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ws[tid >> 6][d] = acc[d];
+  }
   __syncthreads();
-  for (int h = 128; h >= 1; h >>= 1) {
-    if (tid < h)
-      for (int d = 0; d < 3; ++d) s[tid][d] += s[tid + h][d];
-    __syncthreads();
+  if (tid == 0) {
+    for (int d = 0; d < 3; ++d) {
+      double x = ws[0][d];
+      for (int q = 1; q < 16; ++q) x += ws[q][d];
+      s[0][d] = x;
+    }
   }
   if (tid != 0) return;
   for (int d = 0; d < NDIM; ++d) {
@@ -712,7 +761,7 @@ static void launch_argmax_t(StateTable st, const Tile* tiles, int ntiles, int tx
 template <int NDIM, bool MHD>
 static void launch_cmax_term_t(StateTable st, int nblocks, const double* cpart, int ntiles, Control* ctl, double gamma,
                                int in, int lam, double scale, hipStream_t s) {
-  hipLaunchKernelGGL((k_vjp_cmax<NDIM, MHD>), dim3(1), dim3(256), 0, s, st, nblocks, cpart, ntiles, ctl, gamma, in,
+  hipLaunchKernelGGL((k_vjp_cmax<NDIM, MHD>), dim3(1), dim3(1024), 0, s, st, nblocks, cpart, ntiles, ctl, gamma, in,
                      lam, scale);
 }
 
@@ -739,7 +788,7 @@ const VjpVariant* vjp_variant(int ndim, int mhd) {
 
 void launch_argmax_reduce(const double* tmax, const long long* targ, int ntiles, Control* ctl, int slot,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_argmax_reduce, dim3(1), dim3(256), 0, s, tmax, targ, ntiles, ctl, slot);
+  hipLaunchKernelGGL(k_argmax_reduce, dim3(1), dim3(1024), 0, s, tmax, targ, ntiles, ctl, slot);
 }
 
 void launch_combine(const CombineParams& p, int grid, hipStream_t s) {

@@ -306,6 +306,20 @@ __device__ __forceinline__ void mp5_run(const double* f, double* out, int* code)
   double m4[RUN + 1];   // limiter of the pair (j + 1, j + 2)
 #pragma unroll
   for (int j = 0; j < RUN + 1; ++j) m4[j] = m4pair(dc[j], dc[j + 1]);
+  // With CODES, the argument each pair limiter returned, in the two orders
+  // its interfaces number them: (4x - y, 4y - x, x, y) where it is the
+  // limiter at j+1/2 (fMD of interface kk = pair - 1), and (4y - x, 4x - y,
+  // y, x) where it is the limiter at j-1/2 (fLC of interface kk = pair).
+  int kpp[CODES ? RUN + 1 : 1], kmp[CODES ? RUN + 1 : 1];
+  if constexpr (CODES) {
+#pragma unroll
+    for (int j = 0; j < RUN + 1; ++j) {
+      const double x = dc[j], y = dc[j + 1], m = m4[j];
+      const bool z = m == 0.0, e1 = fma(4.0, x, -y) == m, e2 = fma(4.0, y, -x) == m, e3 = x == m, e4 = y == m;
+      kpp[j] = z ? 0 : e1 ? 1 : e2 ? 2 : e3 ? 3 : 4;
+      kmp[j] = z ? 0 : e2 ? 1 : e1 ? 2 : e4 ? 3 : 4;
+    }
+  }
 #pragma unroll
   for (int kk = 0; kk < RUN; ++kk) {
     const double a = f[kk], b = f[kk + 1], c = f[kk + 2], d = f[kk + 3], e = f[kk + 4];
@@ -313,12 +327,7 @@ __device__ __forceinline__ void mp5_run(const double* f, double* out, int* code)
     const double cb = c - b;
     Mp5Parts q;
     out[kk] = mp5_tail(c, d, fL, cb, m4[kk + 1], m4[kk], q);
-    if constexpr (CODES) {
-      const double dm = dc[kk], d0 = dc[kk + 1], dp = dc[kk + 2];
-      const int kp = minmod4_arg(m4[kk + 1], fma(4.0, d0, -dp), fma(4.0, dp, -d0), d0);
-      const int km = minmod4_arg(m4[kk], fma(4.0, d0, -dm), fma(4.0, dm, -d0), d0);
-      code[kk] = mp5_piece(c, d, fL, q, kp, km);
-    }
+    if constexpr (CODES) code[kk] = mp5_piece(c, d, fL, q, kpp[kk + 1], kmp[kk]);
   }
 }
 

@@ -67,7 +67,12 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
                              NDIM >= 3 ? S::NEXT(2) : 0>::v;
   constexpr int IFC = cmax_i<cmax_i<S::NIFC(0), NDIM >= 2 ? S::NIFC(1) : 0>::v,
                              NDIM >= 3 ? S::NIFC(2) : 0>::v;
-  constexpr int LDS_N = cmax_i<2 * VPG * EXT, VPG * IFC>::v;
+  // code-emitting run forms with one variable group stage the piece codes of
+  // a direction in LDS after the interface fluxes (8 bytes per interface,
+  // byte v for variable v) and store them as one 8-byte word per cell face
+  constexpr bool CODE_LDS = EMIT && RUNS && NGRP == 1;
+  static_assert(!CODE_LDS || NV <= 8, "8 code bytes per interface");
+  constexpr int LDS_N = cmax_i<2 * VPG * EXT, VPG * IFC + (CODE_LDS ? IFC : 0)>::v;
   __shared__ double lds[LDS_N];
   // the closing c_max reduction reuses the start of lds: every wave has
   // passed the barrier that ends the last phase C before any writes it
@@ -260,11 +265,16 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
           constexpr int NIT = VPG * NPEN * NRUN;
           constexpr int IPR = (NIT + NT - 1) / NT;
           double res[IPR][RUN];
+          unsigned char cbyte[CODE_LDS ? IPR : 1][RUN];
 #pragma unroll
           for (int r = 0; r < IPR; ++r) {
             const int w = tid + r * NT;
 #pragma unroll
             for (int kk = 0; kk < RUN; ++kk) res[r][kk] = 0.0;
+            if constexpr (CODE_LDS) {
+#pragma unroll
+              for (int kk = 0; kk < RUN; ++kk) cbyte[r][kk] = 0;
+            }
             if (w >= NIT) continue;
             const int pen = w % NPEN;
             const int run = (w / NPEN) % NRUN;
@@ -315,7 +325,10 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
 #pragma unroll
               for (int kk = 0; kk < RUN; ++kk) res[r][kk] = res[r][kk] + o[RUN - 1 - kk];
             }
-            if constexpr (EMIT) {
+            if constexpr (CODE_LDS) {
+#pragma unroll
+              for (int kk = 0; kk < RUN; ++kk) cbyte[r][kk] = (unsigned char)(cp[kk] | (cm[RUN - 1 - kk] << 4));
+            } else if constexpr (EMIT) {
               // linear pieces, stored on the lower face of cell a_D
 #pragma unroll
               for (int kk = 0; kk < RUN; ++kk) {
@@ -346,8 +359,30 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
             constexpr int SI = S::SI(D);
 #pragma unroll
             for (int kk = 0; kk < RUN; ++kk) lds[vg * NIFC_D + q0 + kk * SI] = res[r][kk];
+            if constexpr (CODE_LDS) {
+              if ((G * VPG + vg) < NV) {
+                unsigned char* lc = reinterpret_cast<unsigned char*>(lds + VPG * NIFC_D);
+#pragma unroll
+                for (int kk = 0; kk < RUN; ++kk) lc[(q0 + kk * SI) * 8 + vg] = cbyte[r][kk];
+              }
+            }
           }
           __syncthreads();
+          if constexpr (CODE_LDS) {
+            // one 8-byte word per owned cell: the codes of the interface on
+            // its lower face (unused bytes of a hydro word stay unspecified)
+            const unsigned long long* lc = reinterpret_cast<const unsigned long long*>(lds + VPG * NIFC_D);
+#pragma unroll
+            for (int r = 0; r < CPT; ++r) {
+              const int cidx = tid + r * NT;
+              if (cidx >= TC) continue;
+              const int a0 = cidx % TX, a1 = (cidx / TX) % TY, a2 = cidx / (TX * TY);
+              if (!(a0 < tend[0] && a1 < tend[1] && a2 < tend[2])) continue;
+              const long long cell = ((long long)(tl.o[2] + a2) * B.n[1] + (tl.o[1] + a1)) * B.n[0] + (tl.o[0] + a0);
+              ((__attribute__((address_space(1))) unsigned long long*)(P.codes + D * P.code_plane))[B.coff + cell] =
+                  lc[a0 + I0 * (a1 + I1 * a2)];
+            }
+          }
         } else {
           double res[IPT];
 #pragma unroll
