@@ -65,6 +65,9 @@ def lib():
         L.orc_run_jvp.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_int, ip, dp, ip, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int, dpp, dpp]
+        L.orc_run_vjp.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int, ip, dp, ip, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_int, dpp, dpp]
         L.orc_branch_hash_end.restype = ctypes.c_uint64
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_active.argtypes = [ctypes.POINTER(ctypes.c_ubyte), ctypes.c_int]
@@ -291,6 +294,21 @@ def run_jvp(bs, tangent: Sequence[np.ndarray], scheme: int, nsteps: int, dt: flo
                            scheme, float(dt), nsteps, _ptrs(out.u), _ptrs(du))
     _check(st, "jvp")
     return out, du
+
+
+def run_vjp(bs, lam_n: Sequence[np.ndarray], scheme: int, nsteps: int, dt: float,
+            eps: float = 0.0) -> List[np.ndarray]:
+    """Reverse mode of U0 -> U_N at fixed dt (local dual-number Jacobians,
+    transposed and scattered): from lam_N = dJ/dU_N (padded, ghosts ignored)
+    returns dJ/dU_0 (padded): interiors, plus the adjoint of the boundary data
+    in the face ghosts of fixed faces; every other ghost entry is 0."""
+    n, dx, nbr = _geom(bs)
+    u = [np.ascontiguousarray(x, np.float64).copy() for x in bs.u]
+    lam = [np.ascontiguousarray(x, np.float64).copy() for x in lam_n]
+    st = lib().orc_run_vjp(bs.ndim, int(bs.mhd), bs.gamma, eps, bs.nb, _ip(n), _dp(dx), _ip(nbr),
+                           scheme, float(dt), nsteps, _ptrs(u), _ptrs(lam))
+    _check(st, "vjp")
+    return lam
 
 
 def num_threads() -> int:

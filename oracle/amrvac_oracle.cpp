@@ -75,6 +75,7 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#include <array>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -125,6 +126,72 @@ static inline double val(double a) { return a; }
 static inline double val(Dual a) { return a.v; }
 static inline bool finite_(double a) { return std::isfinite(a); }
 static inline bool finite_(Dual a) { return std::isfinite(a.v) && std::isfinite(a.d); }
+
+// Forward-mode dual number with N tangents: the local Jacobians of the
+// reverse mode (one tangent per input of a cell's flux or of one
+// reconstruction).
+template <int N> struct DualN {
+  double v;
+  double d[N];
+  DualN() : v(0.0) { for (int k = 0; k < N; ++k) d[k] = 0.0; }
+  DualN(double x) : v(x) { for (int k = 0; k < N; ++k) d[k] = 0.0; }
+};
+template <int N> static inline DualN<N> operator+(const DualN<N>& a, const DualN<N>& b) {
+  DualN<N> r(a.v + b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+template <int N> static inline DualN<N> operator-(const DualN<N>& a, const DualN<N>& b) {
+  DualN<N> r(a.v - b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int N> static inline DualN<N> operator-(const DualN<N>& a) {
+  DualN<N> r(-a.v);
+  for (int k = 0; k < N; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int N> static inline DualN<N> operator*(const DualN<N>& a, const DualN<N>& b) {
+  DualN<N> r(a.v * b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int N> static inline DualN<N> operator/(const DualN<N>& a, const DualN<N>& b) {
+  const double q = a.v / b.v;
+  DualN<N> r(q);
+  for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - q * b.d[k]) / b.v;
+  return r;
+}
+template <int N> static inline DualN<N>& operator+=(DualN<N>& a, const DualN<N>& b) { a = a + b; return a; }
+template <int N> static inline DualN<N>& operator-=(DualN<N>& a, const DualN<N>& b) { a = a - b; return a; }
+template <int N> static inline DualN<N> sqrt_(const DualN<N>& a) {
+  const double s = std::sqrt(a.v);
+  DualN<N> r(s);
+  for (int k = 0; k < N; ++k) r.d[k] = s > 0.0 ? a.d[k] / (2.0 * s) : 0.0;
+  return r;
+}
+template <int N> static inline DualN<N> exp_(const DualN<N>& a) {
+  const double e = std::exp(a.v);
+  DualN<N> r(e);
+  for (int k = 0; k < N; ++k) r.d[k] = e * a.d[k];
+  return r;
+}
+template <int N> static inline double val(const DualN<N>& a) { return a.v; }
+template <int N> static inline bool finite_(const DualN<N>& a) {
+  bool ok = std::isfinite(a.v);
+  for (int k = 0; k < N; ++k) ok = ok && std::isfinite(a.d[k]);
+  return ok;
+}
+template <int N> static inline DualN<N> absv(const DualN<N>& x) {
+  if (x.v > 0.0) return x;
+  if (x.v < 0.0) return -x;
+  return DualN<N>(0.0);
+}
+template <int N> static inline DualN<N> seed(double x, int k) {
+  DualN<N> r(x);
+  r.d[k] = 1.0;
+  return r;
+}
 
 // |x| with derivative sign(x), and 0 at x == 0 (reading R6).
 static inline double absv(double x) { return std::fabs(x); }
@@ -497,7 +564,7 @@ static void fill_ghosts(const Grid& G, State<T>& U, int nv_override = 0) {
 // Domain-global per-direction maximum of |v_d| + c_{f,d} over interior
 // cells (reading R1).  Ties keep the first (lowest block, lowest cell).
 template <class T>
-static int global_cmax(const Grid& G, const State<T>& U, T cmax[3]) {
+static int global_cmax(const Grid& G, const State<T>& U, T cmax[3], uint64_t* argout = nullptr) {
   const int nv = G.ph.nvar();
   for (int d = 0; d < 3; ++d) cmax[d] = T(0.0);
   uint64_t arg[3] = {0, 0, 0};
@@ -530,6 +597,8 @@ static int global_cmax(const Grid& G, const State<T>& U, T cmax[3]) {
         }
   }
   for (int d = 0; d < G.ph.ndim; ++d) hash_mix(arg[d] * 3 + d);
+  if (argout)
+    for (int d = 0; d < 3; ++d) argout[d] = arg[d];
   if (G.ph.glm()) {   // reading R8: c_h = max_d c_max,d for every direction
     T ch = cmax[0];
     for (int d = 1; d < G.ph.ndim; ++d)
@@ -740,6 +809,254 @@ static int ssprk_step(const Grid& G, const Scheme& S, State<T>& U, double cfl, d
     }
   }
   if (dt_used) *dt_used = dt;
+  return ORC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode (adjoint) of the time integration at a fixed dt.
+//
+// The map differentiated is U^0 -> U^N of the scheme above, with c_max a
+// function of every stage state (its derivative goes to the maximising cell)
+// and, for fixed faces, the caller's ghost values as further inputs
+// (constant in time).  Local Jacobians come from dual numbers through the
+// same forward functions (the flux of each cell, each reconstruction), and
+// are applied transposed and scattered (no hand-written derivative):
+//   L_i = -(Fhat_{i+1/2} - Fhat_{i-1/2}) / dx   (per direction)
+//   => lamFhat_{i+1/2} = (mu_{i+1} - mu_i) / dx  (mu = 0 outside the interior)
+//   Fhat = R(F+ stencil) + R(F- stencil)
+//   => lamF+-_j += lamFhat * dR/dF+-_j           (dual numbers through R)
+//   F+-_j = (F(U_j) +- c U_j) / 2
+//   => lamU_j += (dF+-/dU_j)^T lamF+-_j,  lam_c += sum_j U_j (lamF+_j - lamF-_j)/2
+//   c = |v_d| + c_f,d at the maximising cell
+//   => lamU_argmax += lam_c d(|v_d| + c_f,d)/dU
+// Adjoints landing on the ghost cells of a periodic face belong to the
+// neighbour's interior cell they copy (the transpose of the ghost fill);
+// on a fixed face they are the adjoint of the boundary data.
+// ---------------------------------------------------------------------------
+
+// lam += scale * (dL/dU)^T mu for the state U (ghosts filled) with c_max
+// cmax and maximising cells arg (global_cmax's keys).  lam, gadj: padded
+// accumulators; interior entries of lam receive the interior adjoint,
+// gadj the fixed faces' ghost entries.
+static int rhs_vjp(const Grid& G, const State<double>& U, const double cmax[3], const uint64_t arg[3],
+                   const State<double>& mu, double scale, double eps, State<double>& lam, State<double>& gadj) {
+  const int nv = G.ph.nvar();
+  const int nb = (int)G.g.size();
+  State<double> acc(nb);   // per block: padded adjoint of this block's cells (its ghosts included)
+  std::vector<double> lamc(3 * nb, 0.0);
+#pragma omp parallel for schedule(dynamic)
+  for (int b = 0; b < nb; ++b) {
+    const Geom& q = G.g[b];
+    acc[b].assign(nv * q.ncell, 0.0);
+    for (int d = 0; d < G.ph.ndim; ++d) {
+      const int nd = q.n[d];
+      const int len = nd + 2 * NG;
+      const double c = cmax[d];
+      std::vector<double> lp(nv * len), lm(nv * len), Fp(nv * len), Fm(nv * len);
+      int lo[3] = {0, 0, 0}, hi[3] = {q.n[0], q.n[1], q.n[2]};
+      hi[d] = 1;
+      for (int k = lo[2]; k < hi[2]; ++k)
+        for (int j = lo[1]; j < hi[1]; ++j)
+          for (int i = lo[0]; i < hi[0]; ++i) {
+            auto cell = [&](int m) {
+              int c3[3] = {i, j, k};
+              c3[d] = m;
+              return q.idx(c3[0], c3[1], c3[2]);
+            };
+            // split fluxes along the pencil, cells -3 .. nd+2
+            for (int m = -NG; m < nd + NG; ++m) {
+              double u[9], f[9];
+              const size_t o = cell(m);
+              for (int v = 0; v < nv; ++v) u[v] = U[b][v * q.ncell + o];
+              Prim<double> w;
+              cons_to_prim(G.ph, u, w);
+              phys_flux(G.ph, d, u, w, f);
+              for (int v = 0; v < nv; ++v) {
+                Fp[v * len + m + NG] = 0.5 * (f[v] + c * u[v]);
+                Fm[v * len + m + NG] = 0.5 * (f[v] - c * u[v]);
+              }
+            }
+            std::fill(lp.begin(), lp.end(), 0.0);
+            std::fill(lm.begin(), lm.end(), 0.0);
+            // interfaces s+1/2, s = -1 .. nd-1: lamFhat and the reconstruction
+            // weights (dual numbers, one tangent per stencil value)
+            for (int v = 0; v < nv; ++v) {
+              auto muv = [&](int m) { return (m >= 0 && m < nd) ? mu[b][v * q.ncell + cell(m)] : 0.0; };
+              const double* p = &Fp[v * len + NG];
+              const double* mneg = &Fm[v * len + NG];
+              for (int sI = -1; sI < nd; ++sI) {
+                const double lf = (muv(sI + 1) - muv(sI)) / q.dx[d];
+                if (lf == 0.0) continue;
+                if (g_recon == 1) {
+                  DualN<3> a[3], bm[3];
+                  for (int t = 0; t < 3; ++t) {
+                    a[t] = seed<3>(p[sI - 1 + t], t);
+                    bm[t] = seed<3>(mneg[sI + 2 - t], t);
+                  }
+                  DualN<3> rp = lim03(a[0], a[1], a[2], q.dx[d]);
+                  DualN<3> rm = lim03(bm[0], bm[1], bm[2], q.dx[d]);
+                  for (int t = 0; t < 3; ++t) {
+                    lp[v * len + (sI - 1 + t) + NG] += lf * rp.d[t];
+                    lm[v * len + (sI + 2 - t) + NG] += lf * rm.d[t];
+                  }
+                } else {
+                  DualN<5> a[5], bm[5];
+                  for (int t = 0; t < 5; ++t) {
+                    a[t] = seed<5>(p[sI - 2 + t], t);
+                    bm[t] = seed<5>(mneg[sI + 3 - t], t);
+                  }
+                  DualN<5> rp = mp5(a[0], a[1], a[2], a[3], a[4], eps);
+                  DualN<5> rm = mp5(bm[0], bm[1], bm[2], bm[3], bm[4], eps);
+                  for (int t = 0; t < 5; ++t) {
+                    lp[v * len + (sI - 2 + t) + NG] += lf * rp.d[t];
+                    lm[v * len + (sI + 3 - t) + NG] += lf * rm.d[t];
+                  }
+                }
+              }
+            }
+            // split adjoint: flux Jacobian of each cell by dual numbers
+            for (int m = -NG; m < nd + NG; ++m) {
+              const size_t o = cell(m);
+              bool any = false;
+              for (int v = 0; v < nv; ++v) any = any || lp[v * len + m + NG] != 0.0 || lm[v * len + m + NG] != 0.0;
+              if (!any) continue;
+              DualN<9> u[9], f[9];
+              for (int v = 0; v < nv; ++v) u[v] = seed<9>(U[b][v * q.ncell + o], v);
+              Prim<DualN<9>> w;
+              cons_to_prim(G.ph, u, w);
+              phys_flux(G.ph, d, u, w, f);
+              for (int t = 0; t < nv; ++t) {
+                double g = 0.0;
+                for (int v = 0; v < nv; ++v) {
+                  const double a = lp[v * len + m + NG], bmv = lm[v * len + m + NG];
+                  // d(F+-_v)/dU_t = (dF_v/dU_t +- c delta_vt) / 2
+                  g += a * 0.5 * (f[v].d[t] + (v == t ? c : 0.0)) + bmv * 0.5 * (f[v].d[t] - (v == t ? c : 0.0));
+                }
+                acc[b][t * q.ncell + o] += scale * g;
+              }
+              for (int v = 0; v < nv; ++v)
+                lamc[3 * b + d] += 0.5 * U[b][v * q.ncell + o] * (lp[v * len + m + NG] - lm[v * len + m + NG]);
+            }
+          }
+    }
+  }
+  // ghost adjoints: periodic faces to the neighbour's interior cell the ghost
+  // copies, fixed faces to the boundary-data adjoint
+  for (int b = 0; b < nb; ++b) {
+    const Geom& q = G.g[b];
+    for (int k = -q.G[2]; k < q.n[2] + q.G[2]; ++k)
+      for (int j = -q.G[1]; j < q.n[1] + q.G[1]; ++j)
+        for (int i = -q.G[0]; i < q.n[0] + q.G[0]; ++i) {
+          int c3[3] = {i, j, k};
+          int out = 0, od = -1;
+          for (int d = 0; d < 3; ++d)
+            if (c3[d] < 0 || c3[d] >= q.n[d]) { ++out; od = d; }
+          const size_t o = q.idx(i, j, k);
+          if (out == 0) {
+            for (int v = 0; v < nv; ++v) lam[b][v * q.ncell + o] += acc[b][v * q.ncell + o];
+            continue;
+          }
+          if (out > 1) continue;   // edge and corner ghosts are never read
+          const int side = c3[od] < 0 ? 0 : 1;
+          const int nbk = q.nbr[2 * od + side];
+          if (nbk < 0) {
+            for (int v = 0; v < nv; ++v) gadj[b][v * q.ncell + o] += acc[b][v * q.ncell + o];
+            continue;
+          }
+          const Geom& r = G.g[nbk];
+          int s3[3] = {i, j, k};
+          s3[od] = side == 0 ? c3[od] + r.n[od] : c3[od] - q.n[od];
+          const size_t os = r.idx(s3[0], s3[1], s3[2]);
+          for (int v = 0; v < nv; ++v) lam[nbk][v * r.ncell + os] += acc[b][v * q.ncell + o];
+        }
+  }
+  // c_max: lam_c (summed over blocks in order) times the derivative of the
+  // maximising cell's |v_d| + c_f,d
+  for (int d = 0; d < G.ph.ndim; ++d) {
+    double lc = 0.0;
+    for (int b = 0; b < nb; ++b) lc += lamc[3 * b + d];
+    if (lc == 0.0) continue;
+    const int b = (int)(arg[d] >> 32);
+    const size_t o = (size_t)(arg[d] & 0xffffffffull);
+    const Geom& q = G.g[b];
+    DualN<9> u[9];
+    for (int v = 0; v < nv; ++v) u[v] = seed<9>(U[b][v * q.ncell + o], v);
+    Prim<DualN<9>> w;
+    if (!cons_to_prim(G.ph, u, w)) return ORC_ERR_NONPHYSICAL;
+    DualN<9> sp = absv(w.v[d]) + fast_speed(G.ph, d, w);
+    for (int t = 0; t < nv; ++t) lam[b][t * q.ncell + o] += scale * lc * sp.d[t];
+  }
+  return ORC_OK;
+}
+
+// Reverse of one step from U^n (ghosts as given) at fixed dt: lam holds
+// dJ/dU^{n+1} on entry (interior) and dJ/dU^n on return; gadj accumulates
+// the boundary-data adjoint.  The stage states are recomputed from U^n.
+static int ssprk_step_vjp(const Grid& G, const Scheme& S, const State<double>& Un, double dt, double eps,
+                          State<double>& lam, State<double>& gadj) {
+  const int nv = G.ph.nvar();
+  std::vector<State<double>> Us(S.s + 1), Ls(S.s);
+  std::vector<std::array<double, 3>> cms(S.s);
+  std::vector<std::array<uint64_t, 3>> args(S.s);
+  Us[0] = Un;
+  for (int i = 1; i <= S.s; ++i) {
+    const int k = i - 1;
+    fill_ghosts(G, Us[k]);
+    double cm[3];
+    uint64_t ag[3];
+    int st = global_cmax(G, Us[k], cm, ag);
+    if (st) return st;
+    for (int d = 0; d < 3; ++d) { cms[k][d] = cm[d]; args[k][d] = ag[d]; }
+    if (i == S.s) break;   // U(s) is not needed
+    alloc_state(G, Ls[k]);
+    st = rhs(G, Us[k], cm, Ls[k], eps);
+    if (st) return st;
+    Us[i] = Us[0];
+    for (size_t b = 0; b < G.g.size(); ++b) {
+      const Geom& q = G.g[b];
+      for (int kk = 0; kk < q.n[2]; ++kk)
+        for (int j = 0; j < q.n[1]; ++j)
+          for (int ii = 0; ii < q.n[0]; ++ii) {
+            const size_t c = q.idx(ii, j, kk);
+            for (int v = 0; v < nv; ++v) {
+              const size_t o = v * q.ncell + c;
+              double a = 0.0;
+              for (int m = 0; m < i; ++m) {
+                if (S.alpha[i][m] != 0.0) a += S.alpha[i][m] * Us[m][b][o];
+                if (S.beta[i][m] != 0.0) a += dt * S.beta[i][m] * Ls[m][b][o];
+              }
+              Us[i][b][o] = a;
+            }
+          }
+    }
+  }
+  // lam(s) = lam; lam(k) = sum_{i>k} alpha_ik lam(i) + dt J_L(U(k))^T sum_{i>k} beta_ik lam(i)
+  std::vector<State<double>> La(S.s + 1);
+  La[S.s] = lam;
+  for (int k = S.s - 1; k >= 0; --k) {
+    alloc_state(G, La[k]);
+    State<double> mu;
+    alloc_state(G, mu);
+    bool any_mu = false;
+    for (size_t b = 0; b < G.g.size(); ++b)
+      for (size_t o = 0; o < La[k][b].size(); ++o) {
+        double a = 0.0, m = 0.0;
+        for (int i = k + 1; i <= S.s; ++i) {
+          if (S.alpha[i][k] != 0.0) a += S.alpha[i][k] * La[i][b][o];
+          if (S.beta[i][k] != 0.0) m += S.beta[i][k] * La[i][b][o];
+        }
+        La[k][b][o] = a;
+        mu[b][o] = m;
+      }
+    for (int i = k + 1; i <= S.s; ++i) any_mu = any_mu || S.beta[i][k] != 0.0;
+    if (any_mu) {
+      const double cm[3] = {cms[k][0], cms[k][1], cms[k][2]};
+      const uint64_t ag[3] = {args[k][0], args[k][1], args[k][2]};
+      int st = rhs_vjp(G, Us[k], cm, ag, mu, dt, eps, La[k], gadj);
+      if (st) return st;
+    }
+  }
+  lam = La[0];
   return ORC_OK;
 }
 
@@ -986,6 +1303,53 @@ int orc_run_jvp(int ndim, int mhd, double gamma, double eps, int nb, const int* 
   fill_ghosts(G, U);
   for (int b = 0; b < nb; ++b)
     for (size_t o = 0; o < U[b].size(); ++o) { u[b][o] = U[b][o].v; du[b][o] = U[b][o].d; }
+  return ORC_OK;
+}
+
+// Reverse mode (vector-Jacobian product) of nsteps steps at fixed dt from
+// U_0 = u (padded blocks, read only): lam (padded blocks) holds dJ/dU_N on
+// entry (ghost entries ignored) and on return dJ/dU_0 in the interiors, the
+// adjoint of the boundary data in the face ghosts of fixed faces (nbr < 0),
+// and 0 in every other ghost entry.  All stage states of every step are
+// recomputed from stored step states.  Ideal hydro and MHD, MP5 or LIM03;
+// GLM, Hall MHD and passive blocks are refused.
+int orc_run_vjp(int ndim, int mhd, double gamma, double eps, int nb, const int* n, const double* dx,
+                const int* nbr, int scheme, double dt, int nsteps, double* const* u, double* const* lam) {
+  Grid G;
+  int st = build_grid(G, ndim, mhd, gamma, nb, n, dx, nbr);
+  if (st) return st;
+  if (scheme < 0 || scheme > 2 || !(dt > 0.0) || nsteps < 0 || mhd == 2 || G.ph.eta_h != 0.0 ||
+      !G.active.empty())
+    return ORC_ERR_INVALID;
+  Scheme S = make_scheme(scheme);
+  std::vector<State<double>> Ustep(nsteps);
+  State<double> U;
+  load_state(G, U, u);
+  for (int it = 0; it < nsteps; ++it) {
+    Ustep[it] = U;
+    st = ssprk_step(G, S, U, 0.0, dt, eps, nullptr);
+    if (st) return st;
+  }
+  State<double> L, gadj;
+  alloc_state(G, L);
+  alloc_state(G, gadj);
+  for (int b = 0; b < nb; ++b) {
+    const Geom& q = G.g[b];
+    for (int k = 0; k < q.n[2]; ++k)
+      for (int j = 0; j < q.n[1]; ++j)
+        for (int i = 0; i < q.n[0]; ++i)
+          for (int v = 0; v < G.ph.nvar(); ++v) {
+            const size_t o = v * q.ncell + q.idx(i, j, k);
+            L[b][o] = lam[b][o];
+          }
+  }
+  for (int it = nsteps - 1; it >= 0; --it) {
+    st = ssprk_step_vjp(G, S, Ustep[it], dt, eps, L, gadj);
+    if (st) return st;
+    Ustep[it].clear();
+  }
+  for (int b = 0; b < nb; ++b)
+    for (size_t o = 0; o < L[b].size(); ++o) lam[b][o] = L[b][o] + gadj[b][o];
   return ORC_OK;
 }
 
