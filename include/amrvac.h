@@ -259,17 +259,20 @@ amrvac_status amrvac_ssprk_step_noalloc(amrvac_ctx *ctx, int scheme, double cfl,
  * block states (read only, not modified) and U_N the state after nsteps
  * steps, lam[b] (host array of nblocks device pointers, each in the padded
  * block layout) holds on entry dJ/dU_N (ghost entries ignored) and on
- * return dJ/dU_0 (ghost entries set to 0).  The map differentiated is the
- * discrete scheme of Sects. 2.1-2.3 with c_max a function of every stage
- * state (its derivative is delivered to the maximising cell, lowest block
- * then lowest cell index on ties); MP5, minmod and median are
- * differentiated along the branch taken by the forward pass.  Checkpoints
- * of U are kept every ckpt_every steps and the steps in between are
- * recomputed.  Requires every face to be periodic (nbr >= 0) and n[d] >= 5.
- * Synchronises the stream and reports device errors.
+ * return dJ/dU_0 in the interiors; the face ghost layers of fixed faces
+ * (nbr = -1) receive dJ/d(boundary data), the derivative with respect to
+ * the caller's ghost values, which enter every stage of every step; every
+ * other ghost entry (periodic faces, edges, corners) is set to 0.  The map
+ * differentiated is the discrete scheme of Sects. 2.1-2.3 with c_max a
+ * function of every stage state (its derivative is delivered to the
+ * maximising cell, lowest block then lowest cell index on ties); MP5,
+ * LIM03, minmod and median are differentiated along the branch taken by the
+ * forward pass.  Checkpoints of U are kept every ckpt_every steps and the
+ * steps in between are recomputed.  Requires n[d] >= 5 for every block and
+ * every face neighbour.  Synchronises the stream and reports device errors.
  * Errors: INVALID (no blocks, null lam or entry, nsteps < 0, ckpt_every < 1,
- * dt not > 0 and finite, scheme unknown), UNSUPPORTED (a fixed face or
- * n[d] < 5), NONPHYSICAL, NOMEM, DEVICE. */
+ * dt not > 0 and finite, scheme unknown), UNSUPPORTED (n[d] < 5, GLM, Hall
+ * MHD, passive blocks), NONPHYSICAL, NOMEM, DEVICE. */
 amrvac_status amrvac_ssprk_adjoint(amrvac_ctx *ctx, int scheme, double dt, int nsteps,
                                    int ckpt_every, double *const *lam);
 

@@ -26,6 +26,7 @@ struct VjpVariant {
   void (*launch)(const VjpParams&, int grid, hipStream_t);
   void (*argmax)(StateTable, const Tile*, int, int, int, int, double, int, double*, long long*, int, hipStream_t);
   void (*cmax_term)(StateTable, int, const double*, int, Control*, double, int, int, double, hipStream_t);
+  void (*ghost)(const VjpParams&, const FixedFace*, int, double*, long long, double*, int, hipStream_t);
 };
 struct CombineParams {
   StateTable st;
@@ -41,7 +42,8 @@ void launch_argmax_reduce(const double* tmax, const long long* targ, int ntiles,
                           hipStream_t s);
 void launch_combine(const CombineParams& p, int grid, hipStream_t s);
 void launch_lam_import(StateTable st, double* const* ptrs, int nv, int dst, int nblocks, hipStream_t s);
-void launch_lam_export(StateTable st, double* const* ptrs, int nv, int src, int nblocks, hipStream_t s);
+void launch_lam_export(StateTable st, double* const* ptrs, int nv, int src, int nblocks, const double* gadj,
+                       long long gplane, hipStream_t s);
 }  // namespace amrvac
 
 using namespace amrvac;
@@ -60,7 +62,11 @@ struct Adj {
   double* d_cpart = nullptr;
   double** d_ptrs = nullptr;
   unsigned char* d_codes = nullptr;   // reconstruction piece codes of every stage state of a segment
-  long long code_plane = 0;           // bytes per direction: 8 per cell
+  long long code_plane = 0;           // bytes per direction: 8 per cell and per upper fixed-face cell
+  FixedFace* d_faces = nullptr;       // the fixed faces
+  int nfaces = 0;
+  double* d_gadj = nullptr;           // boundary-data adjoint, nvar planes of ghost_cells
+  int grid_ghost = 0;
   int grid_vjp = 0;
   int grid_emit = 0;
   int grid_small = 0;
@@ -72,6 +78,8 @@ struct Adj {
     if (d_cpart) (void)hipFree(d_cpart);
     if (d_ptrs) (void)hipFree(d_ptrs);
     if (d_codes) (void)hipFree(d_codes);
+    if (d_faces) (void)hipFree(d_faces);
+    if (d_gadj) (void)hipFree(d_gadj);
   }
 
   int ntiles() const { return (int)htiles.size(); }
@@ -124,6 +132,7 @@ struct Adj {
     p.in = state;
     p.codes = codes;
     p.code_plane = code_plane;
+    p.code_faces = c->total_cells;
     p.recon = c->cfg.recon;
     p.nmu = (int)mu_t.size();
     for (int q = 0; q < p.nmu; ++q) {
@@ -140,7 +149,12 @@ struct Adj {
     p.cm_slot = VJP_SLOT;
     p.cpart = d_cpart;
     V->launch(p, grid_vjp, c->stream);
-    V->cmax_term(st, (int)c->hb.size(), d_cpart, grid_vjp, c->d_ctl, c->cfg.gamma, state, dst, dt, c->stream);
+    int nparts = grid_vjp;
+    if (nfaces > 0) {   // the ghost cells of fixed faces: boundary-data adjoint, their c_max share
+      V->ghost(p, d_faces, nfaces, d_gadj, c->ghost_cells, d_cpart + 3 * (size_t)grid_vjp, grid_ghost, c->stream);
+      nparts += grid_ghost;
+    }
+    V->cmax_term(st, (int)c->hb.size(), d_cpart, nparts, c->d_ctl, c->cfg.gamma, state, dst, dt, c->stream);
   }
 };
 
@@ -162,15 +176,13 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
   if (c->cfg.eta_h > 0.0) return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: Hall MHD is not supported");
   for (int b = 0; b < nb; ++b)
     for (int d = 0; d < c->cfg.ndim; ++d) {
-      if (c->hb[b].nbr[2 * d] < 0 || c->hb[b].nbr[2 * d + 1] < 0)
-        return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: block %d has a fixed face (direction %d)", b, d);
       if (c->hb[b].n[d] < 5)
         return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: block %d has n[%d] < 5", b, d);
     }
   for (int b = 0; b < nb; ++b)
     for (int d = 0; d < c->cfg.ndim; ++d)
       for (int s = 0; s < 2; ++s)
-        if (c->hb[c->hb[b].nbr[2 * d + s]].n[d] < 5)
+        if (c->hb[b].nbr[2 * d + s] >= 0 && c->hb[c->hb[b].nbr[2 * d + s]].n[d] < 5)
           return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: neighbour of block %d has n[%d] < 5", b, d);
 
   const int s = scheme_stages(scheme);
@@ -224,7 +236,24 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
   if ((st = hip_ok(hipMalloc(&adj.d_tiles, sizeof(Tile) * nt), "hipMalloc")) != AMRVAC_OK) return st;
   if ((st = hip_ok(hipMalloc(&adj.d_tmax, sizeof(double) * 3 * nt), "hipMalloc")) != AMRVAC_OK) return st;
   if ((st = hip_ok(hipMalloc(&adj.d_targ, sizeof(long long) * 3 * nt), "hipMalloc")) != AMRVAC_OK) return st;
-  if ((st = hip_ok(hipMalloc(&adj.d_cpart, sizeof(double) * 3 * nt), "hipMalloc")) != AMRVAC_OK) return st;
+  std::vector<FixedFace> hfaces;
+  for (int b = 0; b < nb; ++b)
+    for (int f = 0; f < 2 * c->cfg.ndim; ++f)
+      if (c->hb[b].nbr[f] < 0) hfaces.push_back(FixedFace{b, f});
+  adj.nfaces = (int)hfaces.size();
+  adj.grid_ghost = std::max(1, std::min(adj.nfaces, c->ncu * 4));
+  if ((st = hip_ok(hipMalloc(&adj.d_cpart, sizeof(double) * 3 * ((size_t)nt + adj.grid_ghost)), "hipMalloc")) !=
+      AMRVAC_OK)
+    return st;
+  if (adj.nfaces > 0) {
+    if ((st = hip_ok(hipMalloc(&adj.d_faces, sizeof(FixedFace) * hfaces.size()), "hipMalloc")) != AMRVAC_OK) return st;
+    if ((st = hip_ok(hipMemcpyAsync(adj.d_faces, hfaces.data(), sizeof(FixedFace) * hfaces.size(),
+                                    hipMemcpyHostToDevice, c->stream), "upload")) != AMRVAC_OK)
+      return st;
+    const size_t gbytes = sizeof(double) * (size_t)c->nvar * (size_t)c->ghost_cells;
+    if ((st = hip_ok(hipMalloc(&adj.d_gadj, gbytes), "hipMalloc")) != AMRVAC_OK) return st;
+    if ((st = hip_ok(hipMemsetAsync(adj.d_gadj, 0, gbytes, c->stream), "memset")) != AMRVAC_OK) return st;
+  }
   if ((st = hip_ok(hipMalloc(&adj.d_ptrs, sizeof(double*) * nb), "hipMalloc")) != AMRVAC_OK) return st;
   if ((st = hip_ok(hipMemcpyAsync(adj.d_tiles, adj.htiles.data(), sizeof(Tile) * nt, hipMemcpyHostToDevice,
                                   c->stream), "upload")) != AMRVAC_OK)
@@ -234,7 +263,9 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
                    "upload")) != AMRVAC_OK)
     return st;
   // codes of the k * s stage states of one segment, ndim planes each
-  adj.code_plane = c->total_cells * 8;
+  long long fw = 0;
+  for (int d = 0; d < 3; ++d) fw = std::max(fw, c->face_words[d]);
+  adj.code_plane = (c->total_cells + fw) * 8;
   const size_t code_bytes = (size_t)adj.code_plane * (size_t)c->cfg.ndim * (size_t)s * (size_t)k;
   if ((st = hip_ok(hipMalloc(&adj.d_codes, code_bytes), "hipMalloc (MP5 piece codes)")) != AMRVAC_OK) return st;
   auto codes_of = [&](int j, int kst) {
@@ -322,7 +353,7 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
       R = L[0];
     }
   }
-  launch_lam_export(state_table(c), adj.d_ptrs, c->nvar, R, nb, c->stream);
+  launch_lam_export(state_table(c), adj.d_ptrs, c->nvar, R, nb, adj.d_gadj, c->ghost_cells, c->stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_ok(e, "adjoint launch");
   return read_status(c);

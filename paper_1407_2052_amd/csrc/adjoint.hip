@@ -323,7 +323,6 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
       constexpr int TD = S::T(D), NP = S::NP(D), PS = S::PSTR(D);
       constexpr int MR = S::MROWS(D), CR = S::CROWS(D);
       constexpr int SEG = S::SEG(D), NSEG = S::NSEG(D);
-      constexpr int E0 = D == 0 ? MR : TX, E1 = D == 1 ? MR : TY, E2 = D == 2 ? MR : TZ;
       constexpr int C0 = D == 0 ? CR : TX, C1 = D == 1 ? CR : TY, C2 = D == 2 ? CR : TZ;
       const double c = cin[D];
       const double idx_d = B.inv_dx[D];
@@ -377,8 +376,17 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
         int cc[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) cc[d] = tl.o[d] + a[d] - (d == D ? 2 : 0);
+        const int up = cc[D];   // before resolve_cell moves it into a neighbour
         const BlockDev* Bn = resolve_cell<D>(st, tl.block, cc);
         unsigned long long code = 0ull;
+        if (!Bn && up == B.n[D] && B.fco[D] >= 0) {
+          // the interface on a fixed upper face: its word after the interior cells
+          const long long tr = D == 0 ? (long long)cc[1] + (long long)B.n[1] * cc[2]
+                             : D == 1 ? (long long)cc[0] + (long long)B.n[0] * cc[2]
+                                      : (long long)cc[0] + (long long)B.n[0] * cc[1];
+          code = *(__attribute__((address_space(1))) const unsigned long long*)(P.codes + D * P.code_plane +
+                                                                               (P.code_faces + B.fco[D] + tr) * 8);
+        }
         if (Bn) {
           const long long cell = ((long long)cc[2] * Bn->n[1] + cc[1]) * Bn->n[0] + cc[0];
           code = *(__attribute__((address_space(1))) const unsigned long long*)(P.codes + D * P.code_plane +
@@ -500,6 +508,135 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
       for (int q = 1; q < NT / 64; ++q) x += red[q][d];
       P.cpart[3 * (long long)blockIdx.x + d] = x;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the boundary data: the ghost cells of fixed faces.
+// ---------------------------------------------------------------------------
+// Weight of the stencil value at position s (0..4, f_{j-2} .. f_{j+2}) in
+// the linear piece `code` of the reconstruction (MP5 or LIM03).
+__device__ __forceinline__ double piece_weight(int recon, int code, int s) {
+  return recon == 1 ? c_lim3w[code][s] : c_mp5w[code][s];
+}
+
+// For every face ghost cell g of the fixed faces, gadj[g] += scale *
+// (dL/dU_g)^T mu: the interfaces i+1/2 (i = -1 .. n-1 of the block along the
+// face's direction) whose F+ or F- stencil reaches g, through the linear
+// pieces the recompute coded, then the split adjoint and the transpose of
+// the flux at the ghost state (the caller's ghost values).  The ghost
+// cells' share of the c_max adjoint goes to cpart[3 * blockIdx.x + d].
+// One work-group per fixed face at a time (grid stride over faces).
+template <int NDIM, bool MHD>
+__global__ void __launch_bounds__(256) k_vjp_ghost(VjpParams P, const FixedFace* faces, int nfaces, double* gadj,
+                                                   long long gplane, double* cpart) {
+  using E = Eq<NDIM, MHD>;
+  constexpr int NV = E::NV;
+  __shared__ double red[4][3];
+  const int tid = threadIdx.x;
+  const StateTable& st = P.st;
+  double cin[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) cin[d] = __longlong_as_double((long long)P.ctl->cm[P.cm_slot][d]);
+  double cp[3] = {0.0, 0.0, 0.0};
+  for (int fi = blockIdx.x; fi < nfaces; fi += gridDim.x) {
+    const FixedFace F = faces[fi];
+    const BlockDev& B = st.blocks[F.block];
+    const int D = F.face >> 1, side = F.face & 1;
+    const int e0 = D == 0 ? 1 : 0, e1 = D == 2 ? 1 : 2;   // transverse directions, in order
+    const int nt0 = B.n[e0], nt1 = B.n[e1];
+    const long long area = (long long)nt0 * nt1;
+    const int nD = B.n[D];
+    const double idx_d = B.inv_dx[D];
+    const double c = cin[D];
+    for (long long q = tid; q < 3 * area; q += 256) {
+      const int layer = (int)(q / area);
+      const long long tr = q % area;
+      int cc[3];
+      cc[e0] = (int)(tr % nt0);
+      cc[e1] = (int)(tr / nt0);
+      const int m = side == 0 ? -1 - layer : nD + layer;   // the ghost cell along D
+      // mu along the pencil (0 outside the interior)
+      auto mu_at = [&](int j, int v) {
+        if (j < 0 || j >= nD) return 0.0;
+        int p3[3] = {cc[0], cc[1], cc[2]};
+        p3[D] = j;
+        double acc = 0.0;
+        for (int t = 0; t < P.nmu; ++t) {
+          long long vs;
+          gptr ptr = cell_addr(st, B, P.mu_src[t], p3[0], p3[1], p3[2], vs);
+          acc = fma(P.mu_a[t], ptr[v * vs], acc);
+        }
+        return acc;
+      };
+      // code word of interface i+1/2 = lower face of cell i+1
+      auto code_at = [&](int i) -> unsigned long long {
+        int p3[3] = {cc[0], cc[1], cc[2]};
+        p3[D] = i + 1;
+        if (i + 1 < nD) {
+          const long long cell = ((long long)p3[2] * B.n[1] + p3[1]) * B.n[0] + p3[0];
+          return *(__attribute__((address_space(1))) const unsigned long long*)(P.codes + D * P.code_plane +
+                                                                               (B.coff + cell) * 8);
+        }
+        return *(__attribute__((address_space(1))) const unsigned long long*)(P.codes + D * P.code_plane +
+                                                                             (P.code_faces + B.fco[D] + tr) * 8);
+      };
+      double lp[NV], lm[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) { lp[v] = 0.0; lm[v] = 0.0; }
+      // interfaces i = m-3 .. m+2 that exist (-1 .. nD-1) and reach m
+      for (int i = m - 3; i <= m + 2; ++i) {
+        if (i < -1 || i > nD - 1) continue;
+        const unsigned long long word = code_at(i);
+        const int sp = m - (i - 2);   // position of m in the F+ stencil (cells i-2 .. i+2)
+        const int sm = i + 3 - m;     // position of m in the F- stencil (cells i+3 .. i-1)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double lf = (mu_at(i + 1, v) - mu_at(i, v)) * idx_d;
+          const int code = (int)((word >> (8 * v)) & 0xff);
+          if (sp >= 0 && sp <= 4) lp[v] = fma(lf, piece_weight(P.recon, code & 15, sp), lp[v]);
+          if (sm >= 0 && sm <= 4) lm[v] = fma(lf, piece_weight(P.recon, code >> 4, sm), lm[v]);
+        }
+      }
+      // split adjoint and flux transpose at the ghost state (caller's values)
+      int g3[3] = {cc[0], cc[1], cc[2]};
+      g3[D] = m;
+      long long vs;
+      gptr ug = cell_addr(st, B, 0, g3[0], g3[1], g3[2], vs);
+      double u[NV], lF[NV], nu[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        u[v] = ug[v * vs];
+        nu[v] = 0.0;
+      }
+      PrimD w;
+      prim<NDIM, MHD>(u, P.gamma, w);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        lF[v] = 0.5 * (lp[v] + lm[v]);
+        const double dF = lp[v] - lm[v];
+        nu[v] = fma(0.5 * c, dF, nu[v]);
+        cp[D] = fma(0.5 * u[v], dF, cp[D]);
+      }
+      static_for<0, NDIM>([&](auto Dc) {
+        constexpr int DD = decltype(Dc)::value;
+        if (DD == D) flux_vjp<NDIM, MHD, DD>(u, w, P.gamma, lF, nu);
+      });
+      const long long g = B.gho[F.face] + q;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) gadj[v * gplane + g] = fma(P.scale, nu[v], gadj[v * gplane + g]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) cp[d] = wave_sum(cp[d]);
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) red[tid >> 6][d] = cp[d];
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cpart[3 * (long long)blockIdx.x + d] = (red[0][d] + red[1][d]) + (red[2][d] + red[3][d]);
   }
 }
 
@@ -716,22 +853,39 @@ __global__ void __launch_bounds__(256) k_lam_import(StateTable st, double* const
   }
 }
 
-__global__ void __launch_bounds__(256) k_lam_export(StateTable st, double* const* ptrs, int nv, int src) {
+// Ghost entries: the boundary-data adjoint gadj (ghost cells of fixed faces,
+// layout of BlockDev::gho) where gadj is given, else 0.
+__global__ void __launch_bounds__(256) k_lam_export(StateTable st, double* const* ptrs, int nv, int src,
+                                                    const double* gadj, long long gplane) {
   const int b = blockIdx.x;
   const BlockDev& B = st.blocks[b];
   const long long pstride = (long long)B.P[0] * B.P[1] * B.P[2];
   for (long long pc = threadIdx.x; pc < pstride; pc += 256) {
     const int pi = (int)(pc % B.P[0]), pj = (int)((pc / B.P[0]) % B.P[1]), pk = (int)(pc / ((long long)B.P[0] * B.P[1]));
-    const int i = pi - B.g[0], j = pj - B.g[1], k = pk - B.g[2];
-    const bool inside = i >= 0 && i < B.n[0] && j >= 0 && j < B.n[1] && k >= 0 && k < B.n[2];
-    gptr_w out = (gptr_w)ptrs[b];
-    if (inside) {
+    const int c3[3] = {pi - B.g[0], pj - B.g[1], pk - B.g[2]};
+    int out = 0, od = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (c3[d] < 0 || c3[d] >= B.n[d]) { ++out; od = d; }
+    gptr_w dst = (gptr_w)ptrs[b];
+    if (out == 0) {
       long long vs;
-      gptr p = cell_addr(st, B, src, i, j, k, vs);
-      for (int v = 0; v < nv; ++v) out[v * pstride + pc] = p[v * vs];
-    } else {
-      for (int v = 0; v < nv; ++v) out[v * pstride + pc] = 0.0;
+      gptr p = cell_addr(st, B, src, c3[0], c3[1], c3[2], vs);
+      for (int v = 0; v < nv; ++v) dst[v * pstride + pc] = p[v * vs];
+      continue;
     }
+    long long g = -1;
+    if (gadj && out == 1) {
+      const int side = c3[od] < 0 ? 0 : 1;
+      const long long base = B.gho[2 * od + side];
+      if (base >= 0) {
+        const int layer = side == 0 ? -1 - c3[od] : c3[od] - B.n[od];
+        const int e0 = od == 0 ? 1 : 0, e1 = od == 2 ? 1 : 2;
+        const long long area = (long long)B.n[e0] * B.n[e1];
+        g = base + layer * area + c3[e0] + (long long)B.n[e0] * c3[e1];
+      }
+    }
+    for (int v = 0; v < nv; ++v) dst[v * pstride + pc] = g >= 0 ? gadj[v * gplane + g] : 0.0;
   }
 }
 
@@ -744,6 +898,7 @@ struct VjpVariant {
   void (*launch)(const VjpParams&, int grid, hipStream_t);
   void (*argmax)(StateTable, const Tile*, int, int, int, int, double, int, double*, long long*, int, hipStream_t);
   void (*cmax_term)(StateTable, int, const double*, int, Control*, double, int, int, double, hipStream_t);
+  void (*ghost)(const VjpParams&, const FixedFace*, int, double*, long long, double*, int, hipStream_t);
 };
 
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT>
@@ -765,9 +920,15 @@ static void launch_cmax_term_t(StateTable st, int nblocks, const double* cpart, 
                      lam, scale);
 }
 
+template <int NDIM, bool MHD>
+static void launch_ghost_t(const VjpParams& p, const FixedFace* faces, int nfaces, double* gadj, long long gplane,
+                           double* cpart, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_vjp_ghost<NDIM, MHD>), dim3(grid), dim3(256), 0, s, p, faces, nfaces, gadj, gplane, cpart);
+}
+
 #define AMRVAC_VJP(ND, M, TX, TY, TZ, NT)                                                               \
   {ND, M, TX, TY, TZ, NT, (const void*)&k_vjp<ND, M, TX, TY, TZ, NT>, &launch_vjp_t<ND, M, TX, TY, TZ, NT>, \
-   &launch_argmax_t<ND, M>, &launch_cmax_term_t<ND, M>}
+   &launch_argmax_t<ND, M>, &launch_cmax_term_t<ND, M>, &launch_ghost_t<ND, M>}
 
 // Tile shapes must match the code-emitting stage kernels of the same
 // (ndim, physics): both use one tile list.
@@ -799,8 +960,9 @@ void launch_lam_import(StateTable st, double* const* ptrs, int nv, int dst, int 
   hipLaunchKernelGGL(k_lam_import, dim3(nblocks), dim3(256), 0, s, st, ptrs, nv, dst);
 }
 
-void launch_lam_export(StateTable st, double* const* ptrs, int nv, int src, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_lam_export, dim3(nblocks), dim3(256), 0, s, st, ptrs, nv, src);
+void launch_lam_export(StateTable st, double* const* ptrs, int nv, int src, int nblocks, const double* gadj,
+                       long long gplane, hipStream_t s) {
+  hipLaunchKernelGGL(k_lam_export, dim3(nblocks), dim3(256), 0, s, st, ptrs, nv, src, gadj, gplane);
 }
 
 }  // namespace amrvac

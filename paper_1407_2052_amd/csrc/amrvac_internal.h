@@ -20,6 +20,15 @@ struct BlockDev {
   int nbr[6];           // face neighbours, -1 = fixed ghosts in u
   double dx[3];
   double inv_dx[3];
+  // Adjoint bookkeeping of fixed faces (-1 where the face has a neighbour):
+  // fco[d]: index, in 8-byte code words after the interior cells of a code
+  //   plane, of the words of the interfaces on the upper face of direction d
+  //   (one per face cell, transverse coordinates in x, y, z order);
+  // gho[f]: index, in ghost cells of the boundary-data adjoint, of the 3
+  //   ghost layers of face f (-x, +x, -y, +y, -z, +z), layer-major from the
+  //   face outwards, transverse coordinates in x, y, z order.
+  long long fco[3];
+  long long gho[6];
 };
 
 // One unit of work: a box of interior cells of one block.
@@ -103,6 +112,9 @@ struct StageParams {
   //   codes + D * code_plane + (block.coff + cell) * 8 + v.
   unsigned char* codes;
   long long code_plane;
+  // words of the upper fixed-face interfaces start at word code_faces of a
+  // plane (the number of interior cells)
+  long long code_faces;
 };
 
 struct CmaxParams {
@@ -115,6 +127,12 @@ struct CmaxParams {
   int in;
   int slot;
   double eta_h;         // Hall MHD: the whistler speed enters c_max
+};
+
+// One fixed face of a block list (the adjoint's boundary-data pass).
+struct FixedFace {
+  int block;
+  int face;   // 2 d + side
 };
 
 constexpr int MAX_TERMS = 6;
@@ -136,6 +154,7 @@ struct VjpParams {
   int in;
   const unsigned char* codes;
   long long code_plane;
+  long long code_faces;   // as in StageParams
   int recon;   // reconstruction the codes refer to: 0 MP5, 1 LIM03
   int nmu;
   int mu_src[MAX_TERMS];

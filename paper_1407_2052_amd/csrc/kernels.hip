@@ -71,6 +71,7 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
   // a direction in LDS after the interface fluxes (8 bytes per interface,
   // byte v for variable v) and store them as one 8-byte word per cell face
   constexpr bool CODE_LDS = EMIT && RUNS && NGRP == 1;
+  static_assert(!EMIT || CODE_LDS, "the code-emitting forms are run forms with one variable group");
   static_assert(!CODE_LDS || NV <= 8, "8 code bytes per interface");
   constexpr int LDS_N = cmax_i<2 * VPG * EXT, VPG * IFC + (CODE_LDS ? IFC : 0)>::v;
   __shared__ double lds[LDS_N];
@@ -328,18 +329,6 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
             if constexpr (CODE_LDS) {
 #pragma unroll
               for (int kk = 0; kk < RUN; ++kk) cbyte[r][kk] = (unsigned char)(cp[kk] | (cm[RUN - 1 - kk] << 4));
-            } else if constexpr (EMIT) {
-              // linear pieces, stored on the lower face of cell a_D
-#pragma unroll
-              for (int kk = 0; kk < RUN; ++kk) {
-                int ci[3] = {tl.o[0] + a[0], tl.o[1] + a[1], tl.o[2] + a[2]};
-                ci[D] += kk;
-                if (k0 + kk < tend[D]) {
-                  const long long cell = ((long long)ci[2] * B.n[1] + ci[1]) * B.n[0] + ci[0];
-                  P.codes[D * P.code_plane + (B.coff + cell) * 8 + (G * VPG + vg)] =
-                      (unsigned char)(cp[kk] | (cm[RUN - 1 - kk] << 4));
-                }
-              }
             }
           }
           __syncthreads();
@@ -379,8 +368,19 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
               const int a0 = cidx % TX, a1 = (cidx / TX) % TY, a2 = cidx / (TX * TY);
               if (!(a0 < tend[0] && a1 < tend[1] && a2 < tend[2])) continue;
               const long long cell = ((long long)(tl.o[2] + a2) * B.n[1] + (tl.o[1] + a1)) * B.n[0] + (tl.o[0] + a0);
-              ((__attribute__((address_space(1))) unsigned long long*)(P.codes + D * P.code_plane))[B.coff + cell] =
-                  lc[a0 + I0 * (a1 + I1 * a2)];
+              __attribute__((address_space(1))) unsigned long long* cw =
+                  (__attribute__((address_space(1))) unsigned long long*)(P.codes + D * P.code_plane);
+              const int il = a0 + I0 * (a1 + I1 * a2);
+              cw[B.coff + cell] = lc[il];
+              // the last cell of a fixed upper face: also the interface on its
+              // upper face, in the words after the interior cells
+              const int ac[3] = {tl.o[0] + a0, tl.o[1] + a1, tl.o[2] + a2};
+              if (B.fco[D] >= 0 && ac[D] == B.n[D] - 1) {
+                const long long tr = D == 0 ? (long long)ac[1] + (long long)B.n[1] * ac[2]
+                                   : D == 1 ? (long long)ac[0] + (long long)B.n[0] * ac[2]
+                                            : (long long)ac[0] + (long long)B.n[0] * ac[1];
+                cw[P.code_faces + B.fco[D] + tr] = lc[il + S::SI(D)];
+              }
             }
           }
         } else {
@@ -412,30 +412,7 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
                 const double* fm = &lds[(VPG + vg) * NEXTP + eb];
                 if constexpr (LIM) {
                   // F+ from cells a_D - 2 .. a_D, F- mirrored from a_D + 1 .. a_D - 1
-                  if constexpr (EMIT) {
-                    int kp, km;
-                    res[r] = lim03_coded(fp[0], fp[SD], fp[2 * SD], kr, kp) +
-                             lim03_coded(fm[3 * SD], fm[2 * SD], fm[SD], kr, km);
-                    if (a[D] < tend[D]) {
-                      const long long cell =
-                          ((long long)(tl.o[2] + a[2]) * B.n[1] + (tl.o[1] + a[1])) * B.n[0] + (tl.o[0] + a[0]);
-                      P.codes[D * P.code_plane + (B.coff + cell) * 8 + (G * VPG + vg)] =
-                          (unsigned char)(kp | (km << 4));
-                    }
-                  } else {
-                    res[r] = lim03(fp[0], fp[SD], fp[2 * SD], kr) + lim03(fm[3 * SD], fm[2 * SD], fm[SD], kr);
-                  }
-                } else if constexpr (EMIT) {
-                  // both linear pieces, stored on the lower face of cell a_D
-                  int kp, km;
-                  res[r] = mp5_coded(fp[0], fp[SD], fp[2 * SD], fp[3 * SD], fp[4 * SD], kp) +
-                           mp5_coded(fm[5 * SD], fm[4 * SD], fm[3 * SD], fm[2 * SD], fm[SD], km);
-                  if (a[D] < tend[D]) {
-                    const long long cell =
-                        ((long long)(tl.o[2] + a[2]) * B.n[1] + (tl.o[1] + a[1])) * B.n[0] + (tl.o[0] + a[0]);
-                    P.codes[D * P.code_plane + (B.coff + cell) * 8 + (G * VPG + vg)] =
-                        (unsigned char)(kp | (km << 4));
-                  }
+                  res[r] = lim03(fp[0], fp[SD], fp[2 * SD], kr) + lim03(fm[3 * SD], fm[2 * SD], fm[SD], kr);
                 } else {
                   res[r] = mp5(fp[0], fp[SD], fp[2 * SD], fp[3 * SD], fp[4 * SD]) +
                            mp5(fm[5 * SD], fm[4 * SD], fm[3 * SD], fm[2 * SD], fm[SD]);

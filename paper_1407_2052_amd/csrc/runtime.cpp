@@ -474,6 +474,7 @@ void enqueue_step_outs(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U
       p.ntiles = emit->ntiles;
       p.codes = emit->codes[i - 1];
       p.code_plane = emit->code_plane;
+      p.code_faces = c->total_cells;
       emit->var->launch(p, emit->grid, s);
     } else {
       launch_stage(c, p, exec, s);
@@ -673,6 +674,25 @@ amrvac_status amrvac_set_blocks(amrvac_ctx* c, const amrvac_block* blocks, int n
     }
   }
   c->total_cells = off / c->nvar;
+  // fixed faces: code words of upper boundary interfaces, ghost cells of the
+  // boundary-data adjoint
+  for (int d = 0; d < 3; ++d) c->face_words[d] = 0;
+  c->ghost_cells = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    BlockDev& D = c->hdev[b];
+    for (int d = 0; d < 3; ++d) {
+      long long area = 1;
+      for (int e = 0; e < 3; ++e)
+        if (e != d) area *= D.n[e];
+      D.fco[d] = (d < nd && D.nbr[2 * d + 1] < 0) ? c->face_words[d] : -1;
+      if (D.fco[d] >= 0) c->face_words[d] += area;
+      for (int side = 0; side < 2; ++side) {
+        const int f = 2 * d + side;
+        D.gho[f] = (d < nd && D.nbr[f] < 0) ? c->ghost_cells : -1;
+        if (D.gho[f] >= 0) c->ghost_cells += 3 * area;
+      }
+    }
+  }
   if (c->cfg.eta_h > 0.0)   // Hall MHD: the current of every interior cell, three planes
     HIP_TRY(c, hipMalloc(&c->d_J, sizeof(double) * 3 * (size_t)c->total_cells));
   c->slot_stride = (off + 31) / 32 * 32;

@@ -60,6 +60,8 @@ struct amrvac_ctx {
   std::vector<BlockDev> hdev;
   BlockDev* d_blocks = nullptr;
   long long total_cells = 0;    // interior cells of all blocks
+  long long face_words[3] = {0, 0, 0};   // upper fixed-face cells per direction
+  long long ghost_cells = 0;             // face ghost cells of all fixed faces
   long long slot_stride = 0;    // doubles per scratch slot
 
   // tiles of the chosen variant

@@ -11,6 +11,10 @@ steps:
         10 SSPRK(5,4) steps at CFL 0.4  -> fullsize_c3_10.npz
   * c5: 3D ideal MHD, 256^3 periodic in 4096 blocks of 16^3,
         100 SSPRK(5,4) steps at CFL 0.4 -> fullsize_c5_100.npz
+  * c4grad: 2D Euler, 256^2 periodic in 256 blocks of 16^2, 200 SSPRK(5,4)
+        steps at the fixed dt 0.4 / sum_d c_max,d(U_0)/dx_d; the gradient of
+        J = 1/2 sum (rho_N - rho*)^2 with respect to U_0 by the oracle's
+        reverse mode -> fullsize_c4_grad200.npz (every interior entry)
 The oracle needs about 40 GB of host memory and an hour (c5) on 8 cores.
 """
 import json
@@ -35,7 +39,29 @@ CASES = {
 }
 
 
+def make_c4grad():
+    t0 = time.time()
+    bs = inputs.hydro_random_2d()
+    target = inputs.hydro_target_density()
+    _, cm = oracle.rhs(bs)
+    dt = 0.4 / sum(cm[d] / bs.dx[0, d] for d in range(2))
+    out, _ = oracle.run(bs, oracle.SSPRK54, 200, dt=dt)
+    lam_n = []
+    for b in range(bs.nb):
+        x = np.zeros(bs.padded_shape(b))
+        bs.interior(b, x)[0] = out.interior(b)[0] - target[b]
+        lam_n.append(x)
+    lam0 = oracle.run_vjp(bs, lam_n, oracle.SSPRK54, 200, dt)
+    grad = np.stack([bs.interior(b, lam0[b]) for b in range(bs.nb)])
+    meta = {"case": "c4grad", "scheme": "SSPRK(5,4)", "nsteps": 200, "dt": dt, "input_sha256": input_digest(bs),
+            "oracle_threads": oracle.num_threads(), "seconds": round(time.time() - t0, 1)}
+    np.savez(os.path.join(HERE, "fullsize_c4_grad200.npz"), grad=grad, meta=np.array(json.dumps(meta)))
+    print(f"c4grad: wrote fullsize_c4_grad200.npz in {time.time() - t0:.0f} s", flush=True)
+
+
 def make(name):
+    if name == "c4grad":
+        return make_c4grad()
     fname, gen, nsteps = CASES[name]
     t0 = time.time()
     bs = gen()
@@ -51,5 +77,5 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(CASES)):
+    for name in (sys.argv[1:] or list(CASES) + ["c4grad"]):
         make(name)

@@ -8,6 +8,7 @@ tiny grid equals the brute-force oracle Jacobian (one JVP per input) to
 gradients match central differences of the GPU forward map to 1e-6.
 """
 import math
+import os
 import sys
 
 import numpy as np
@@ -147,13 +148,6 @@ def test_zero_steps_is_identity():
 
 
 def test_unsupported_inputs_are_reported():
-    bs = inputs.sod(64)   # fixed faces
-    ctx, flat, views = A.context_for(bs)
-    lam = [torch.zeros_like(v) for v in views]
-    with pytest.raises(A.AmrvacError) as ei:
-        ctx.ssprk_adjoint(oracle.SSPRK54, 1e-3, 1, 1, lam)
-    assert ei.value.status == A.ERR_UNSUPPORTED
-    ctx.close()
     n, dx, xlo, nbr, _ = inputs.uniform_blocks(1, [16], [4])   # blocks of 4 < 5 cells
     bs = inputs.sample_blocks(1, False, 1.4, n, dx, xlo, nbr, smooth_fields(1, False, 0))
     ctx, flat, views = A.context_for(bs)
@@ -216,3 +210,120 @@ def test_hydro_density_gradient_matches_central_differences_full_size():
     # the two step sizes agree (non-kinked) and the adjoint matches them
     assert abs(fds[0] - fds[1]) <= 1e-7 * abs(an)
     assert abs(an - fds[1]) <= 1e-6 * abs(an), (an, fds)
+
+
+# ---------------------------------------------------------------- fixed faces
+from test_oracle_vjp import face_ghost_mask, mhd2d_mixed_faces, random_with_ghosts, sod_like  # noqa: E402
+
+
+def fixed_uneven3d():
+    # 3D MHD blocks of 32^3 / 16^3 / 8^3 (1:2:4), every face fixed
+    return inputs.uneven_3d(nblocks=7, seed=3, N=64)
+
+
+FIXED = [
+    ("hydro1d_mp5", sod_like, oracle.SSPRK54, 4, 2, A.MP5),
+    ("hydro1d_lim03_rk3", sod_like, oracle.RK3, 4, 3, A.LIM03),
+    ("mhd2d_mixed", mhd2d_mixed_faces, oracle.SSPRK54, 3, 2, A.MP5),
+    ("mhd3d_uneven", fixed_uneven3d, oracle.SSPRK54, 2, 1, A.MP5),
+]
+
+
+def gpu_adjoint_recon(bs, scheme, dt, nsteps, ckpt, lam_n, recon):
+    ctx, flat, views = A.context_for(bs, recon=recon)
+    lam = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in lam_n]
+    ctx.ssprk_adjoint(scheme, dt, nsteps, ckpt, lam)
+    out = [x.cpu().numpy() for x in lam]
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("case,gen,scheme,nsteps,ckpt,recon", FIXED, ids=[c[0] for c in FIXED])
+def test_fixed_faces_against_oracle_reverse_mode_and_jvp(case, gen, scheme, nsteps, ckpt, recon):
+    """Fixed faces: lam_0 element by element against the oracle's reverse
+    mode, the boundary-data adjoint in the fixed ghost layers included, and
+    <lam_0, dU_0> against the oracle JVP with tangents in those ghost layers."""
+    say(f"[adjoint fixed faces] {case}")
+    bs = gen()
+    with oracle.use_recon(recon):
+        dt = fixed_dt(bs)
+        lam_n = random_cotangent(bs, 31)
+        ref = oracle.run_vjp(bs, lam_n, scheme, nsteps, dt)
+        tang = random_with_ghosts(bs, 32)
+        _, du = oracle.run_jvp(bs, tang, scheme, nsteps, dt)
+    got = gpu_adjoint_recon(bs, scheme, dt, nsteps, ckpt, lam_n, recon)
+    scale = max(float(np.abs(r).max()) for r in ref)
+    worst = max(float(np.abs(g - r).max()) for g, r in zip(got, ref))
+    say(f"  max |gpu - oracle| / max |oracle| = {worst / scale:.2e}")
+    assert worst <= 1e-10 * scale
+    gh = max(float(np.abs(got[b][:, face_ghost_mask(bs, b)]).max()) for b in range(bs.nb))
+    assert gh > 0.0   # the boundary data do enter
+    lhs = math.fsum(float(np.vdot(g, t)) for g, t in zip(got, tang))
+    rhs = interior_dot(bs, lam_n, du)
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs), (lhs, rhs)
+
+
+@pytest.mark.timeout(300)
+def test_hydro2d_256_full_gradient_against_stored_oracle_reverse_mode():
+    """The 2D Euler workload's full gradient (256^2, 200 SSPRK(5,4) steps,
+    checkpoints every 20; J = 1/2 sum (rho_N - rho*)^2) element by element
+    against the oracle's reverse mode (tests/golden/make_fullsize.py)."""
+    import json
+    from conftest import golden
+    path = golden("fullsize_c4_grad200.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle gradient not written yet (tests/golden/make_fullsize.py c4grad)")
+    ref = np.load(path)
+    meta = json.loads(str(ref["meta"]))
+    say("[adjoint full gradient] 2D Euler 256^2, 200 steps")
+    bs = inputs.hydro_random_2d()
+    target = inputs.hydro_target_density()
+    _, cm = oracle.rhs(bs)
+    dt = 0.4 / sum(cm[d] / bs.dx[0, d] for d in range(2))
+    assert dt == meta["dt"]
+    ctx, flat, views = A.context_for(bs)
+    ctx.ssprk_step(oracle.SSPRK54, 200, dt=dt, t=0.0)
+    lam_n = []
+    for b, v in enumerate(views):
+        x = np.zeros(bs.padded_shape(b))
+        bs.interior(b, x)[0] = bs.interior(b, v.cpu().numpy())[0] - target[b]
+        lam_n.append(x)
+    ctx.close()
+    got = gpu_adjoint(bs, oracle.SSPRK54, dt, 200, 20, lam_n)
+    g = np.stack([bs.interior(b, got[b]) for b in range(bs.nb)])
+    r = ref["grad"]
+    for v in range(bs.nvar):
+        sc = float(np.abs(r[:, v]).max())
+        er = float(np.abs(g[:, v] - r[:, v]).max())
+        say(f"  var {v}: max |gpu - oracle| {er:.3e}, max |oracle| {sc:.3e}")
+    # the density component is dJ/drho_0 at fixed v = 0, p = 1 (dm/drho = v
+    # = 0 and dE/drho = v^2/2 = 0), the gradient this workload defines.  With
+    # v = 0 and p = 1 the momentum and energy split fluxes of U_0 are uniform,
+    # so their reconstructions sit on MP5's kink and the momentum and energy
+    # components are one-sided derivatives that depend on the last bit of
+    # the fifth-order value in each implementation: not compared.
+    scale = float(np.abs(r[:, 0]).max())
+    err = float(np.abs(g[:, 0] - r[:, 0]).max())
+    say(f"  density: max |gpu - oracle| / max |oracle| = {err / scale:.2e}")
+    assert err <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("case", ["hydro2d_64_200", "mhd3d_16_4"])
+def test_full_gradient_against_oracle_reverse_mode(case):
+    """Every component of lam_0, element by element, against the oracle's
+    reverse mode on states where no reconstruction sits on a kink (smooth
+    random fields, nonzero velocities): 2D Euler 64^2 in 16^2 blocks over 200
+    SSPRK(5,4) steps, 3D MHD 16^3 in 8^3 blocks over 4 steps."""
+    say(f"[adjoint full gradient] {case}")
+    if case == "hydro2d_64_200":
+        bs, scheme, nsteps, ckpt = periodic_state(2, False, 64, 16, seed=12), oracle.SSPRK54, 200, 20
+    else:
+        bs, scheme, nsteps, ckpt = periodic_state(3, True, 16, 8, seed=13), oracle.SSPRK54, 4, 2
+    dt = fixed_dt(bs)
+    lam_n = random_cotangent(bs, 14)
+    ref = oracle.run_vjp(bs, lam_n, scheme, nsteps, dt)
+    got = gpu_adjoint(bs, scheme, dt, nsteps, ckpt, lam_n)
+    scale = max(float(np.abs(r).max()) for r in ref)
+    err = max(float(np.abs(a - b).max()) for a, b in zip(got, ref))
+    say(f"  max |gpu - oracle| / max |oracle| = {err / scale:.2e}")
+    assert err <= 1e-10 * scale
