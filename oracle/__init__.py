@@ -68,6 +68,10 @@ def lib():
         L.orc_run_vjp.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_int, ip, dp, ip, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int, dpp, dpp]
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.orc_count_ops.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int, ip, dp, ip, dpp, ctypes.c_int, ctypes.c_int, u64p, u64p, u64p]
+        L.orc_set_mp5_median.argtypes = [ctypes.c_int]
         L.orc_branch_hash_end.restype = ctypes.c_uint64
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_active.argtypes = [ctypes.POINTER(ctypes.c_ubyte), ctypes.c_int]
@@ -309,6 +313,40 @@ def run_vjp(bs, lam_n: Sequence[np.ndarray], scheme: int, nsteps: int, dt: float
                            scheme, float(dt), nsteps, _ptrs(u), _ptrs(lam))
     _check(st, "vjp")
     return lam
+
+
+OP_CATEGORIES = ("other", "flux", "recon", "diff", "cmax", "stage")
+
+
+def count_ops(bs, scheme: int = SSPRK54, median_form: bool = False, eps: float = 0.0):
+    """Operation counts of one step (CFL 0.4) on the block list, single
+    threaded: per category (OP_CATEGORIES) the arithmetic operations, the
+    comparisons and selections, and the units they were spent on."""
+    n, dx, nbr = _geom(bs)
+    u = [np.ascontiguousarray(x, np.float64) for x in bs.u]
+    nops = np.zeros(6, np.uint64)
+    ncmp = np.zeros(6, np.uint64)
+    units = np.zeros(6, np.uint64)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    st = lib().orc_count_ops(bs.ndim, int(bs.mhd), bs.gamma, eps, bs.nb, _ip(n), _dp(dx), _ip(nbr), _ptrs(u),
+                             scheme, int(median_form), nops.ctypes.data_as(u64p), ncmp.ctypes.data_as(u64p),
+                             units.ctypes.data_as(u64p))
+    _check(st, "count_ops")
+    return {c: {"ops": int(a), "cmp": int(b), "units": int(k)}
+            for c, a, b, k in zip(OP_CATEGORIES, nops, ncmp, units)}
+
+
+class mp5_median_form:
+    """Context manager: MP5 without its early exit (the median form) in the
+    oracle's later calls; restored on exit."""
+
+    def __enter__(self):
+        lib().orc_set_mp5_median(1)
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_mp5_median(0)
+        return False
 
 
 def num_threads() -> int:

@@ -93,6 +93,56 @@ static inline void hash_mix(uint64_t x) {
   g_hash ^= x + 0x9e3779b97f4a7c15ull + (g_hash << 6) + (g_hash >> 2);
 }
 
+// Operation counter (for the roofline figures of the measurement, not for
+// results): Counted is a scalar that counts its arithmetic (+, -, *, /, sqrt,
+// exp: one operation each; the oracle forms no fused multiply-add) into the
+// current category, and count_cmp counts the comparisons and selections of
+// min, max, minmod, median, |x| and the tests that pick a branch.  Units
+// (flux evaluations, reconstructions, cells) are counted per category so
+// that per-unit averages can be formed.  Enabled by orc_count_ops only
+// (single-threaded); otherwise every hook is a no-op.
+enum { CAT_OTHER = 0, CAT_FLUX = 1, CAT_RECON = 2, CAT_DIFF = 3, CAT_CMAX = 4, CAT_STAGE = 5, NCAT = 6 };
+static bool g_count_on = false;
+static int g_cat = CAT_OTHER;
+static uint64_t g_nops[NCAT], g_ncmp[NCAT], g_units[NCAT];
+static inline void count_cmp(int k = 1) {
+  if (g_count_on) g_ncmp[g_cat] += (uint64_t)k;
+}
+static inline void count_unit(int cat, uint64_t k = 1) {
+  if (g_count_on) g_units[cat] += k;
+}
+static inline void set_cat(int c) {
+  if (g_count_on) g_cat = c;
+}
+// MP5 without its early exit (the median form: the same value for eps = 0);
+// a counting option only.
+static bool g_mp5_median = false;
+
+struct Counted {
+  double v;
+  Counted() : v(0.0) {}
+  Counted(double x) : v(x) {}
+};
+static inline Counted cop(double x) {
+  if (g_count_on) ++g_nops[g_cat];
+  return Counted(x);
+}
+static inline Counted operator+(Counted a, Counted b) { return cop(a.v + b.v); }
+static inline Counted operator-(Counted a, Counted b) { return cop(a.v - b.v); }
+static inline Counted operator-(Counted a) { return Counted(-a.v); }
+static inline Counted operator*(Counted a, Counted b) { return cop(a.v * b.v); }
+static inline Counted operator/(Counted a, Counted b) { return cop(a.v / b.v); }
+static inline Counted& operator+=(Counted& a, Counted b) { a = a + b; return a; }
+static inline Counted& operator-=(Counted& a, Counted b) { a = a - b; return a; }
+static inline Counted sqrt_(Counted a) { return cop(std::sqrt(a.v)); }
+static inline Counted exp_(Counted a) { return cop(std::exp(a.v)); }
+static inline double val(Counted a) { return a.v; }
+static inline bool finite_(Counted a) { return std::isfinite(a.v); }
+static inline Counted absv(Counted x) {
+  count_cmp();
+  return Counted(std::fabs(x.v));
+}
+
 // ---------------------------------------------------------------------------
 // Forward-mode dual number: value v and one tangent d.
 // ---------------------------------------------------------------------------
@@ -202,8 +252,14 @@ static inline Dual absv(Dual x) {
 }
 
 // min / max returning the first argument on ties.
-template <class T> static inline T min2(T a, T b) { return (val(b) < val(a)) ? b : a; }
-template <class T> static inline T max2(T a, T b) { return (val(b) > val(a)) ? b : a; }
+template <class T> static inline T min2(T a, T b) {
+  count_cmp();
+  return (val(b) < val(a)) ? b : a;
+}
+template <class T> static inline T max2(T a, T b) {
+  count_cmp();
+  return (val(b) > val(a)) ? b : a;
+}
 template <class T> static inline T min3(T a, T b, T c) { return min2(min2(a, b), c); }
 template <class T> static inline T max3(T a, T b, T c) { return max2(max2(a, b), c); }
 
@@ -215,12 +271,14 @@ static const double MP5_ALPHA = 4.0;
 // minmod(x, y): 0 unless x and y share a strict sign, else the argument of
 // smaller magnitude (first argument on equal magnitudes).
 template <class T> static inline T minmod2(T x, T y) {
+  count_cmp(2);   // the sign test and the magnitude comparison
   if (val(x) * val(y) <= 0.0) return T(0.0);
   return (std::fabs(val(y)) < std::fabs(val(x))) ? y : x;
 }
 
 // minmod of four: sign * min |.| when all four share a strict sign, else 0.
 template <class T> static inline T minmod4(T w, T x, T y, T z) {
+  count_cmp(8);   // the common-sign tests
   bool pos = val(w) > 0.0 && val(x) > 0.0 && val(y) > 0.0 && val(z) > 0.0;
   bool neg = val(w) < 0.0 && val(x) < 0.0 && val(y) < 0.0 && val(z) < 0.0;
   if (pos) return min2(min2(min2(w, x), y), z);
@@ -230,6 +288,7 @@ template <class T> static inline T minmod4(T w, T x, T y, T z) {
 
 // Median of three; x is returned when it equals one of the bounds.
 template <class T> static inline T median3(T x, T lo, T hi) {
+  count_cmp(2);
   // lo <= hi holds for the MP5 bounds (both bracket the centre value).
   if (val(x) < val(lo)) return lo;
   if (val(x) > val(hi)) return hi;
@@ -241,12 +300,15 @@ template <class T> static inline T median3(T x, T lo, T hi) {
 template <class T> static T mp5(T a, T b, T c, T d, T e, double eps) {
   // fifth-order linear interface value
   T fL = (T(2.0) * a - T(13.0) * b + T(47.0) * c + T(27.0) * d - T(3.0) * e) / T(60.0);
-  // monotonicity-preserving bound
-  T fMP = c + minmod2(d - c, T(MP5_ALPHA) * (c - b));
-  if (val((fL - c) * (fL - fMP)) <= eps) {   // linear piece 1: fL
-    bool flat = val(a) == val(c) && val(b) == val(c) && val(d) == val(c) && val(e) == val(c);
-    hash_mix(flat ? 0 : 1);
-    return fL;
+  if (!g_mp5_median) {
+    // monotonicity-preserving bound
+    T fMP = c + minmod2(d - c, T(MP5_ALPHA) * (c - b));
+    count_cmp();
+    if (val((fL - c) * (fL - fMP)) <= eps) {   // linear piece 1: fL
+      bool flat = val(a) == val(c) && val(b) == val(c) && val(d) == val(c) && val(e) == val(c);
+      hash_mix(flat ? 0 : 1);
+      return fL;
+    }
   }
   // curvatures at j-1, j, j+1
   T dm = a - T(2.0) * b + c;
@@ -304,10 +366,12 @@ template <class T> static T lim03(T a, T b, T c, double dx) {
   T dp = c - b;   // f_{j+1} - f_j
   const double rdx = LIM03_RADIUS * dx;
   T eta = (dm * dm + dp * dp) / T(rdx * rdx);
+  count_cmp();
   if (val(eta) <= 1.0) {   // asymptotic region: third-order formula
     hash_mix(0x45);
     return b + T(0.5) * ((T(2.0) * dp + dm) / T(3.0));
   }
+  count_cmp();
   if (val(dp) == 0.0) {
     hash_mix(0x40);
     return b;
@@ -421,6 +485,7 @@ static T fast_speed(const Phys& ph, int d, const Prim<T>& w) {
   T bd2 = w.B[d] * w.B[d] / w.rho;
   T s = a2 + b2;
   T disc = s * s - T(4.0) * a2 * bd2;
+  count_cmp();
   if (val(disc) < 0.0) disc = T(0.0);   // rounding guard; >= 0 analytically
   T cf2 = T(0.5) * (s + sqrt_(disc));
   return sqrt_(cf2);
@@ -578,6 +643,8 @@ static int global_cmax(const Grid& G, const State<T>& U, T cmax[3], uint64_t* ar
           T u[9];
           size_t c = q.idx(i, j, k);
           for (int v = 0; v < nv; ++v) u[v] = U[b][v * q.ncell + c];
+          set_cat(CAT_CMAX);
+          count_unit(CAT_CMAX);
           Prim<T> w;
           if (!cons_to_prim(G.ph, u, w)) return ORC_ERR_NONPHYSICAL;
           for (int d = 0; d < G.ph.ndim; ++d) {
@@ -591,6 +658,7 @@ static int global_cmax(const Grid& G, const State<T>& U, T cmax[3], uint64_t* ar
               if (val(wh) > val(cf)) cf = wh;
             }
             T s = absv(w.v[d]) + cf;
+            count_cmp();
             if (first || val(s) > val(cmax[d])) { cmax[d] = s; arg[d] = ((uint64_t)b << 32) | c; }
           }
           first = false;
@@ -676,7 +744,9 @@ static int rhs(const Grid& G, const State<T>& U, const T cmax[3], State<T>& L, d
         for (int j = lo[1]; j < hi[1]; ++j)
           for (int i = lo[0]; i < hi[0]; ++i) {
             // split fluxes along the pencil, cells -3 .. nd+2
+            set_cat(CAT_FLUX);
             for (int m = -NG; m < nd + NG; ++m) {
+              count_unit(CAT_FLUX);
               int c3[3] = {i, j, k};
               c3[d] = m;
               size_t c = q.idx(c3[0], c3[1], c3[2]);
@@ -697,6 +767,8 @@ static int rhs(const Grid& G, const State<T>& U, const T cmax[3], State<T>& L, d
               }
             }
             // interface fluxes at i+1/2 for i = -1 .. nd-1
+            set_cat(CAT_RECON);
+            count_unit(CAT_RECON, 2 * (uint64_t)nv * (nd + 1));
             for (int v = 0; v < nv; ++v) {
               const T* p = &Fp[v * len + NG];
               const T* mneg = &Fm[v * len + NG];
@@ -713,6 +785,8 @@ static int rhs(const Grid& G, const State<T>& U, const T cmax[3], State<T>& L, d
               }
             }
             // conservative difference
+            set_cat(CAT_DIFF);
+            count_unit(CAT_DIFF, (uint64_t)nv * nd);
             for (int s = 0; s < nd; ++s) {
               int c3[3] = {i, j, k};
               c3[d] = s;
@@ -774,9 +848,11 @@ static int ssprk_step(const Grid& G, const Scheme& S, State<T>& U, double cfl, d
     st = rhs(G, Us[k], cm, Ls[k], eps);
     if (st) return st;
     Us[i] = Us[0];   // ghost layers: fixed faces keep U^n's values; passive blocks keep U^n
+    set_cat(CAT_STAGE);
     for (size_t b = 0; b < G.g.size(); ++b) {
       if (!G.is_active(b)) continue;
       const Geom& q = G.g[b];
+      count_unit(CAT_STAGE, (uint64_t)q.n[0] * q.n[1] * q.n[2]);
       for (int kk = 0; kk < q.n[2]; ++kk)
         for (int j = 0; j < q.n[1]; ++j)
           for (int ii = 0; ii < q.n[0]; ++ii) {
@@ -1352,6 +1428,51 @@ int orc_run_vjp(int ndim, int mhd, double gamma, double eps, int nb, const int* 
     for (size_t o = 0; o < L[b].size(); ++o) lam[b][o] = L[b][o] + gadj[b][o];
   return ORC_OK;
 }
+
+// Operation counts of one step of `scheme` (CFL 0.4) on the given blocks,
+// single-threaded: per category (0 other, 1 primitive recovery + flux +
+// split of one cell along one direction, 2 reconstructions (two per
+// interface and variable, with the sum of the pair), 3 conservative
+// difference (per cell, variable and direction), 4 c_max (per cell, every
+// direction), 5 stage combination (per cell and stage)) the arithmetic
+// operations nops, the comparisons and selections ncmp, and the units.
+// median_form != 0 evaluates MP5 without its early exit.
+int orc_count_ops(int ndim, int mhd, double gamma, double eps, int nb, const int* n, const double* dx,
+                  const int* nbr, const double* const* u, int scheme, int median_form, uint64_t* nops,
+                  uint64_t* ncmp, uint64_t* units) {
+  Grid G;
+  int st = build_grid(G, ndim, mhd, gamma, nb, n, dx, nbr);
+  if (st) return st;
+  if (scheme < 0 || scheme > 2) return ORC_ERR_INVALID;
+  Scheme S = make_scheme(scheme);
+  State<Counted> U;
+  alloc_state(G, U);
+  for (int b = 0; b < nb; ++b)
+    for (size_t o = 0; o < U[b].size(); ++o) U[b][o] = Counted(u[b][o]);
+#ifdef _OPENMP
+  const int threads = omp_get_max_threads();
+  omp_set_num_threads(1);
+#endif
+  for (int c = 0; c < NCAT; ++c) g_nops[c] = g_ncmp[c] = g_units[c] = 0;
+  g_mp5_median = median_form != 0;
+  g_count_on = true;
+  g_cat = CAT_OTHER;
+  st = ssprk_step(G, S, U, 0.4, -1.0, eps, nullptr);
+  g_count_on = false;
+  g_mp5_median = false;
+#ifdef _OPENMP
+  omp_set_num_threads(threads);
+#endif
+  for (int c = 0; c < NCAT; ++c) {
+    nops[c] = g_nops[c];
+    ncmp[c] = g_ncmp[c];
+    units[c] = g_units[c];
+  }
+  return st;
+}
+
+// Test hook: MP5 without its early exit (the median form) in later calls.
+void orc_set_mp5_median(int on) { g_mp5_median = on != 0; }
 
 // Branch fingerprint: orc_branch_hash_begin() enables collection (and
 // forces one thread), orc_branch_hash_end() returns the fingerprint.

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_1407_2052_amd import inputs
 
 
 def cell_average(coeffs, a, b):
@@ -138,3 +139,39 @@ def test_unlimited_gradient_is_the_linear_formula():
     _, g = oracle.mp5_grad([1.0, 2.0, 3.0, 4.0, 5.0])
     np.testing.assert_allclose(g * 60.0, [2, -13, 47, 27, -3], atol=1e-12)
     assert abs(g.sum() - 1.0) < 1e-15
+
+
+def test_median_form_equals_the_early_exit_bitwise():
+    """With eps = 0 the early exit returns a value inside both bounds, so
+    MP5 without it (the median form, an option of the oracle's operation
+    counter) gives the same bits: random tuples, monotone runs, extrema,
+    flat stencils and one-sided kinks."""
+    rng = np.random.default_rng(5)
+    cases = [rng.normal(size=5) for _ in range(20000)]
+    cases += [np.sort(rng.normal(size=5)) for _ in range(2000)]
+    cases += [np.array([0.0, 1.0, 2.0, 1.0, 0.0]), np.full(5, 0.7), np.array([1.0, 1.0, 1.0, 2.0, 3.0]),
+              np.array([0.0, 0.0, 1.0, 1.0, 1.0]), np.array([3.0, 1.0, 0.0, 1.0, 3.0])]
+    ref = [oracle.mp5(f) for f in cases]
+    with oracle.mp5_median_form():
+        got = [oracle.mp5(f) for f in cases]
+    assert got == ref
+
+
+def test_operation_counter_units_and_a_hand_count():
+    """orc_count_ops: the units match the loops of one SSPRK(5,4) step, and
+    one hydro 1D flux unit (primitive recovery 6, flux 4, split 3 x 2 x 3)
+    costs 28 arithmetic operations."""
+    bs = inputs.density_wave_1d(64, nblocks=2)
+    c = oracle.count_ops(bs, oracle.SSPRK54)
+    st = 5
+    assert c["flux"]["units"] == st * 2 * (32 + 6)
+    assert c["recon"]["units"] == st * 2 * 2 * 3 * 33
+    assert c["diff"]["units"] == st * 2 * 3 * 32
+    assert c["stage"]["units"] == st * 64
+    assert c["cmax"]["units"] == st * 64
+    assert c["flux"]["ops"] == 28 * c["flux"]["units"]
+    assert c["flux"]["cmp"] == 0
+    # the median form costs more arithmetic per reconstruction
+    m = oracle.count_ops(bs, oracle.SSPRK54, median_form=True)
+    assert m["recon"]["ops"] > c["recon"]["ops"]
+    assert m["flux"]["ops"] == c["flux"]["ops"]
