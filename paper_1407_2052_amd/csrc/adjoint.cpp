@@ -24,7 +24,6 @@ struct VjpVariant {
   int ndim, mhd, tx, ty, tz, nt;
   const void* fn;
   void (*launch)(const VjpParams&, int grid, hipStream_t);
-  void (*argmax)(StateTable, const Tile*, int, int, int, int, double, int, double*, long long*, int, hipStream_t);
   void (*cmax_term)(StateTable, int, const double*, int, Control*, double, int, int, double, hipStream_t);
   void (*ghost)(const VjpParams&, const FixedFace*, int, double*, long long, double*, int, hipStream_t);
 };
@@ -38,8 +37,6 @@ struct CombineParams {
   int dst;
 };
 const VjpVariant* vjp_variant(int ndim, int mhd);
-void launch_argmax_reduce(const double* tmax, const long long* targ, int ntiles, Control* ctl, int slot,
-                          hipStream_t s);
 void launch_combine(const CombineParams& p, int grid, hipStream_t s);
 void launch_lam_import(StateTable st, double* const* ptrs, int nv, int dst, int nblocks, hipStream_t s);
 void launch_lam_export(StateTable st, double* const* ptrs, int nv, int src, int nblocks, const double* gadj,
@@ -50,15 +47,12 @@ using namespace amrvac;
 
 namespace {
 
-constexpr int VJP_SLOT = MAX_SLOTS - 1;   // c_max slot used by the reverse pass
-
 struct Adj {
   amrvac_ctx* c;
   const VjpVariant* V;
   std::vector<Tile> htiles;
   Tile* d_tiles = nullptr;
-  double* d_tmax = nullptr;
-  long long* d_targ = nullptr;
+  double* d_hist = nullptr;   // c_max of every stage state of a segment, 3 per state
   double* d_cpart = nullptr;
   double** d_ptrs = nullptr;
   unsigned char* d_codes = nullptr;   // reconstruction piece codes of every stage state of a segment
@@ -73,8 +67,7 @@ struct Adj {
 
   ~Adj() {
     if (d_tiles) (void)hipFree(d_tiles);
-    if (d_tmax) (void)hipFree(d_tmax);
-    if (d_targ) (void)hipFree(d_targ);
+    if (d_hist) (void)hipFree(d_hist);
     if (d_cpart) (void)hipFree(d_cpart);
     if (d_ptrs) (void)hipFree(d_ptrs);
     if (d_codes) (void)hipFree(d_codes);
@@ -116,13 +109,11 @@ struct Adj {
   }
 
   // dst = sum lam_t + dt * J_L(state)^T (sum mu_t), including the c_max
-  // term; `codes` are the reconstruction pieces of L(state) from the recompute
-  void vjp(int state, const unsigned char* codes, const std::vector<std::pair<int, double>>& mu_t,
+  // term; `codes` are the reconstruction pieces of L(state) and cm its c_max,
+  // both from the recompute
+  void vjp(int state, const unsigned char* codes, const double* cm, const std::vector<std::pair<int, double>>& mu_t,
            const std::vector<std::pair<int, double>>& lam_t, int dst, double dt) {
     StateTable st = state_table(c);
-    V->argmax(st, d_tiles, ntiles(), V->tx, V->ty, V->tz, c->cfg.gamma, state, d_tmax, d_targ, grid_small,
-              c->stream);
-    launch_argmax_reduce(d_tmax, d_targ, grid_small, c->d_ctl, VJP_SLOT, c->stream);
     VjpParams p{};
     p.st = st;
     p.tiles = d_tiles;
@@ -146,7 +137,7 @@ struct Adj {
     }
     p.dst = dst;
     p.scale = dt;
-    p.cm_slot = VJP_SLOT;
+    p.cm_in = cm;
     p.cpart = d_cpart;
     V->launch(p, grid_vjp, c->stream);
     int nparts = grid_vjp;
@@ -234,8 +225,11 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
                     hipGetErrorString(e));
   };
   if ((st = hip_ok(hipMalloc(&adj.d_tiles, sizeof(Tile) * nt), "hipMalloc")) != AMRVAC_OK) return st;
-  if ((st = hip_ok(hipMalloc(&adj.d_tmax, sizeof(double) * 3 * nt), "hipMalloc")) != AMRVAC_OK) return st;
-  if ((st = hip_ok(hipMalloc(&adj.d_targ, sizeof(long long) * 3 * nt), "hipMalloc")) != AMRVAC_OK) return st;
+  if ((st = hip_ok(hipMalloc(&adj.d_hist, sizeof(double) * 3 * (size_t)s * (size_t)k), "hipMalloc")) != AMRVAC_OK)
+    return st;
+  // the maximiser keys start above every valid key (the VJPs lower them)
+  if ((st = hip_ok(hipMemsetAsync(c->d_ctl->arg, 0x7f, sizeof(c->d_ctl->arg), c->stream), "memset")) != AMRVAC_OK)
+    return st;
   std::vector<FixedFace> hfaces;
   for (int b = 0; b < nb; ++b)
     for (int f = 0; f < 2 * c->cfg.ndim; ++f)
@@ -324,7 +318,10 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
       plan.tiles = adj.d_tiles;
       plan.ntiles = nt;
       plan.grid = adj.grid_emit;
-      for (int i = 0; i < s; ++i) plan.codes[i] = codes_of(j, i);
+      for (int i = 0; i < s; ++i) {
+        plan.codes[i] = codes_of(j, i);
+        plan.cm_hist[i] = adj.d_hist + 3 * ((size_t)j * s + i);
+      }
       plan.code_plane = adj.code_plane;
       enqueue_step_outs(c, scheme, exec, c->stream, X[j][0], outs, S, &plan);
     }
@@ -348,7 +345,7 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
         if (mu_t.empty())
           adj.combine(L[kst], lam_t);
         else
-          adj.vjp(X[j][kst], codes_of(j, kst), mu_t, lam_t, L[kst], dt);
+          adj.vjp(X[j][kst], codes_of(j, kst), adj.d_hist + 3 * ((size_t)j * s + kst), mu_t, lam_t, L[kst], dt);
       }
       R = L[0];
     }

@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
   }
   double cin[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) cin[d] = __longlong_as_double((long long)P.ctl->cm[P.cm_slot][d]);
+  for (int d = 0; d < 3; ++d) cin[d] = P.cm_in[d];
   __syncthreads();
 
   // c_max adjoint sums of this work-group's tiles (taken in the fixed tile
@@ -306,6 +306,16 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
         uo[r][E::IE] = 1.0;
       }
       prim<NDIM, MHD>(uo[r], gamma, wo[r]);
+      if (own[r]) {
+        // the cells that realise c_max (bitwise the speed the recompute
+        // folded into it): the lowest key wins
+        const long long key =
+            ((long long)tl.block << 32) | (((long long)(tl.o[2] + a2) * B.n[1] + (tl.o[1] + a1)) * B.n[0] + (tl.o[0] + a0));
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d)
+          if (fabs(wo[r].v[d]) + fast_speed<MHD>(wo[r], d, gamma) == cin[d])
+            atomicMin(reinterpret_cast<unsigned long long*>(&P.ctl->arg[d]), (unsigned long long)key);
+      }
 #pragma unroll
       for (int v = 0; v < NV; ++v) muo[r][v] = 0.0;
       if (own[r]) {
@@ -537,7 +547,7 @@ __global__ void __launch_bounds__(256) k_vjp_ghost(VjpParams P, const FixedFace*
   const StateTable& st = P.st;
   double cin[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) cin[d] = __longlong_as_double((long long)P.ctl->cm[P.cm_slot][d]);
+  for (int d = 0; d < 3; ++d) cin[d] = P.cm_in[d];
   double cp[3] = {0.0, 0.0, 0.0};
   for (int fi = blockIdx.x; fi < nfaces; fi += gridDim.x) {
     const FixedFace F = faces[fi];
@@ -640,113 +650,6 @@ __global__ void __launch_bounds__(256) k_vjp_ghost(VjpParams P, const FixedFace*
   }
 }
 
-// ---------------------------------------------------------------------------
-// c_max with its maximising cell: per tile, then one work-group.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool better(double v, long long k, double bv, long long bk) {
-  return v > bv || (v == bv && k < bk);
-}
-
-// (value, key) maximum over the 64 lanes of a wave (largest value, then
-// lowest key): the result is the same whatever the order.
-__device__ __forceinline__ void argmax_wave(double& v, long long& k) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const double ov = __shfl_xor(v, m, 64);
-    const long long ok = __shfl_xor(k, m, 64);
-    if (better(ov, ok, v, k)) { v = ov; k = ok; }
-  }
-}
-
-// Per work-group: the largest |v_d| + c_f,d over the work-group's tiles and
-// its lowest (block, cell) key, into tmax / targ[3 * blockIdx.x + d].
-template <int NDIM, bool MHD>
-__global__ void __launch_bounds__(256) k_argmax_tiles(StateTable st, const Tile* tiles, int ntiles, int tx, int ty,
-                                                      int tz, double gamma, int in, double* tmax, long long* targ) {
-  using E = Eq<NDIM, MHD>;
-  __shared__ double sv[4][3];
-  __shared__ long long sk[4][3];
-  const int tid = threadIdx.x;
-  const int tcells = tx * ty * tz;
-  double bv[3] = {-1.0, -1.0, -1.0};
-  long long bk[3] = {0x7fffffffffffffffll, 0x7fffffffffffffffll, 0x7fffffffffffffffll};
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const Tile tl = tiles[t];
-    const BlockDev& B = st.blocks[tl.block];
-    for (int c = tid; c < tcells; c += 256) {
-      const int i = tl.o[0] + c % tx, j = tl.o[1] + (c / tx) % ty, k = tl.o[2] + c / (tx * ty);
-      if (i >= B.n[0] || j >= B.n[1] || k >= B.n[2]) continue;
-      long long vs;
-      gptr p = cell_addr(st, B, in, i, j, k, vs);
-      double u[E::NV];
-#pragma unroll
-      for (int v = 0; v < E::NV; ++v) u[v] = p[v * vs];
-      PrimD w;
-      prim<NDIM, MHD>(u, gamma, w);
-      const long long key = ((long long)tl.block << 32) | (long long)(((long long)k * B.n[1] + j) * B.n[0] + i);
-#pragma unroll
-      for (int d = 0; d < NDIM; ++d) {
-        const double s = fabs(w.v[d]) + fast_speed<MHD>(w, d, gamma);
-        if (better(s, key, bv[d], bk[d])) { bv[d] = s; bk[d] = key; }
-      }
-    }
-  }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) argmax_wave(bv[d], bk[d]);
-  if ((tid & 63) == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) { sv[tid >> 6][d] = bv[d]; sk[tid >> 6][d] = bk[d]; }
-  }
-  __syncthreads();
-  if (tid == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double v = sv[0][d];
-      long long k = sk[0][d];
-      for (int q = 1; q < 4; ++q)
-        if (better(sv[q][d], sk[q][d], v, k)) { v = sv[q][d]; k = sk[q][d]; }
-      tmax[3 * (long long)blockIdx.x + d] = v;
-      targ[3 * (long long)blockIdx.x + d] = k;
-    }
-  }
-}
-
-// The global maximum and its key from the n per-work-group results (one
-// work-group of 1024 threads); the order of the reduction does not matter
-// (largest value, then lowest key).
-__global__ void __launch_bounds__(1024) k_argmax_reduce(const double* tmax, const long long* targ, int n,
-                                                        Control* ctl, int slot) {
-  __shared__ double sv[16][3];
-  __shared__ long long sk[16][3];
-  const int tid = threadIdx.x;
-  double bv[3] = {-1.0, -1.0, -1.0};
-  long long bk[3] = {0x7fffffffffffffffll, 0x7fffffffffffffffll, 0x7fffffffffffffffll};
-  for (int t = tid; t < n; t += 1024)
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      if (better(tmax[3 * (long long)t + d], targ[3 * (long long)t + d], bv[d], bk[d])) {
-        bv[d] = tmax[3 * (long long)t + d];
-        bk[d] = targ[3 * (long long)t + d];
-      }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) argmax_wave(bv[d], bk[d]);
-  if ((tid & 63) == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) { sv[tid >> 6][d] = bv[d]; sk[tid >> 6][d] = bk[d]; }
-  }
-  __syncthreads();
-  if (tid == 0)
-    for (int d = 0; d < 3; ++d) {
-      double v = sv[0][d];
-      long long k = sk[0][d];
-      for (int q = 1; q < 16; ++q)
-        if (better(sv[q][d], sk[q][d], v, k)) { v = sv[q][d]; k = sk[q][d]; }
-      const double m = v < 0.0 ? 0.0 : v;
-      ctl->cm[slot][d] = (unsigned long long)__double_as_longlong(m);
-      ctl->arg[d] = k;
-    }
-}
-
 // Sum of the per-work-group c_max adjoints (fixed order: strided per
 // thread, then a fixed butterfly per wave, then the 16 waves in order), then
 // lam[argmax_d] += scale * lamc_d * d(|v_d| + c_f,d)/dU at the maximiser.
@@ -783,12 +686,12 @@ __global__ void __launch_bounds__(1024) k_vjp_cmax(StateTable st, int nblocks, c
     // no cell had a finite speed (non-physical state): report, never index
     if (key < 0 || b < 0 || b >= nblocks) {
       atomicOr(&ctl->err, 1);
-      return;
+      break;
     }
     const BlockDev& B = st.blocks[b];
     if (cell >= B.cells) {
       atomicOr(&ctl->err, 1);
-      return;
+      break;
     }
     const int i = (int)(cell % B.n[0]), j = (int)((cell / B.n[0]) % B.n[1]), k = (int)(cell / ((long long)B.n[0] * B.n[1]));
     long long vs, ws;
@@ -802,6 +705,8 @@ __global__ void __launch_bounds__(1024) k_vjp_cmax(StateTable st, int nblocks, c
     gptr_w q = (gptr_w)(cell_addr(st, B, lam, i, j, k, ws));
     for (int v = 0; v < E::NV; ++v) q[v * ws] = fma(scale, lu[v], q[v * ws]);
   }
+  // the keys are consumed: ready for the next VJP's atomicMin
+  for (int d = 0; d < 3; ++d) ctl->arg[d] = 0x7fffffffffffffffll;
 }
 
 // dst = sum_j a[j] * src[j] over the interiors (up to 6 terms; dst may be a
@@ -896,7 +801,6 @@ struct VjpVariant {
   int ndim, mhd, tx, ty, tz, nt;
   const void* fn;
   void (*launch)(const VjpParams&, int grid, hipStream_t);
-  void (*argmax)(StateTable, const Tile*, int, int, int, int, double, int, double*, long long*, int, hipStream_t);
   void (*cmax_term)(StateTable, int, const double*, int, Control*, double, int, int, double, hipStream_t);
   void (*ghost)(const VjpParams&, const FixedFace*, int, double*, long long, double*, int, hipStream_t);
 };
@@ -906,12 +810,6 @@ static void launch_vjp_t(const VjpParams& p, int grid, hipStream_t s) {
   hipLaunchKernelGGL((k_vjp<NDIM, MHD, TX, TY, TZ, NT>), dim3(grid), dim3(NT), 0, s, p);
 }
 
-template <int NDIM, bool MHD>
-static void launch_argmax_t(StateTable st, const Tile* tiles, int ntiles, int tx, int ty, int tz, double gamma,
-                            int in, double* tmax, long long* targ, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_argmax_tiles<NDIM, MHD>), dim3(grid), dim3(256), 0, s, st, tiles, ntiles, tx, ty, tz, gamma,
-                     in, tmax, targ);
-}
 
 template <int NDIM, bool MHD>
 static void launch_cmax_term_t(StateTable st, int nblocks, const double* cpart, int ntiles, Control* ctl, double gamma,
@@ -928,7 +826,7 @@ static void launch_ghost_t(const VjpParams& p, const FixedFace* faces, int nface
 
 #define AMRVAC_VJP(ND, M, TX, TY, TZ, NT)                                                               \
   {ND, M, TX, TY, TZ, NT, (const void*)&k_vjp<ND, M, TX, TY, TZ, NT>, &launch_vjp_t<ND, M, TX, TY, TZ, NT>, \
-   &launch_argmax_t<ND, M>, &launch_cmax_term_t<ND, M>, &launch_ghost_t<ND, M>}
+   &launch_cmax_term_t<ND, M>, &launch_ghost_t<ND, M>}
 
 // Tile shapes must match the code-emitting stage kernels of the same
 // (ndim, physics): both use one tile list.
@@ -947,10 +845,6 @@ const VjpVariant* vjp_variant(int ndim, int mhd) {
   return nullptr;
 }
 
-void launch_argmax_reduce(const double* tmax, const long long* targ, int ntiles, Control* ctl, int slot,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_argmax_reduce, dim3(1), dim3(1024), 0, s, tmax, targ, ntiles, ctl, slot);
-}
 
 void launch_combine(const CombineParams& p, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_combine, dim3(grid), dim3(256), 0, s, p);

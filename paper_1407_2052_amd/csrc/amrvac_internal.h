@@ -115,6 +115,19 @@ struct StageParams {
   // words of the upper fixed-face interfaces start at word code_faces of a
   // plane (the number of interior cells)
   long long code_faces;
+  // Optional (the adjoint's recompute): the c_max of this stage's input
+  // state (slot cm_in as read at launch) is copied to cm_hist[0..2]
+  double* cm_hist;
+};
+
+// One compiled form of the fused stage kernel (a tile shape and its
+// options): its table entry, shared by the kernel file that instantiates it
+// and the runtime that selects it.
+struct StageVariant {
+  int ndim, mhd, rec, hall, tx, ty, tz, nt, ngrp, wpe;   // mhd: physics code; rec: 0 MP5, 1 LIM03
+  const void* fn;
+  void (*launch)(const StageParams&, int grid, hipStream_t);
+  const char* name;
 };
 
 struct CmaxParams {
@@ -164,7 +177,10 @@ struct VjpParams {
   double lam_a[MAX_TERMS];
   int dst;
   double scale;
-  int cm_slot;
+  // c_max of the state `in` per direction, as its recompute recorded it; the
+  // VJP marks the maximising cells (lowest (block, cell) key, atomicMin into
+  // ctl->arg, which the c_max term then consumes and resets)
+  const double* cm_in;
   double* cpart;
 };
 

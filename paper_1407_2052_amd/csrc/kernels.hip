@@ -100,6 +100,10 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
   const double psi_decay = (GLM && P.decay_psi) ? ctl->psi_decay : 1.0;
   const double dtb = dt * P.b;
   const double dtsb = dt * P.sb;
+  if (EMIT && P.cm_hist && blockIdx.x == 0 && tid == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) P.cm_hist[d] = __longlong_as_double((long long)ctl->cm[P.cm_in][d]);
+  }
   if (P.cm_reset >= 0 && blockIdx.x == 0 && tid == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) ctl->cm[P.cm_reset][d] = 0ull;
@@ -809,12 +813,6 @@ __global__ void k_clear_slot(Control* ctl, int slot) {
 // ---------------------------------------------------------------------------
 // Variant table.
 // ---------------------------------------------------------------------------
-struct StageVariant {
-  int ndim, mhd, rec, hall, tx, ty, tz, nt, ngrp, wpe;
-  const void* fn;
-  void (*launch)(const StageParams&, int grid, hipStream_t);
-  const char* name;
-};
 
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
           bool RUNS = false, bool LIM = false, bool GLM = false, bool HALL = false, bool CORE = false>

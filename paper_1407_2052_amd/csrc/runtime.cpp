@@ -475,6 +475,7 @@ void enqueue_step_outs(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U
       p.codes = emit->codes[i - 1];
       p.code_plane = emit->code_plane;
       p.code_faces = c->total_cells;
+      p.cm_hist = emit->cm_hist[i - 1];
       emit->var->launch(p, emit->grid, s);
     } else {
       launch_stage(c, p, exec, s);

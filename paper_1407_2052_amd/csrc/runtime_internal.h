@@ -10,12 +10,6 @@
 
 namespace amrvac {
 
-struct StageVariant {
-  int ndim, mhd, rec, hall, tx, ty, tz, nt, ngrp, wpe;   // mhd: physics code; rec: 0 MP5, 1 LIM03
-  const void* fn;
-  void (*launch)(const StageParams&, int grid, hipStream_t);
-  const char* name;
-};
 const StageVariant* stage_variants(int* count);
 // Code-emitting stage kernel for (ndim, physics), or nullptr.
 const StageVariant* emit_variant(int ndim, int mhd, int rec);
@@ -121,6 +115,7 @@ struct EmitPlan {
   int grid;
   unsigned char* codes[6];
   long long code_plane;
+  double* cm_hist[6];   // c_max of stage i's input state is written to cm_hist[i - 1]
 };
 void enqueue_step_outs(amrvac_ctx* c, int scheme, int exec, hipStream_t s, int U, const int* outs, int S,
                        const EmitPlan* emit = nullptr);
