@@ -139,8 +139,8 @@ static const StageVariant* pick_variant(const amrvac_ctx* c, int want) {
 static amrvac_status select_variant(amrvac_ctx* c, int i);
 
 // Build the tile list of the current variant: blocks ordered largest first,
-// then along a Morton curve of their origins; tiles of a block contiguous and
-// Morton-ordered.
+// then along a Morton curve of their origins, dealt out to the eight XCD
+// chunks class by class; tiles of a block contiguous and Morton-ordered.
 static amrvac_status build_tiles(amrvac_ctx* c) {
   const StageVariant* V = c->var;
   const int T[3] = {V->tx, V->ty, V->tz};
@@ -164,6 +164,30 @@ static amrvac_status build_tiles(amrvac_ctx* c) {
     if (cells[a] != cells[b]) return cells[a] > cells[b];
     return key[a] < key[b];
   });
+  // XCD balance: the persistent schedule gives XCD x the x-th eighth of the
+  // tile list, and tiles of small blocks cost more per cell (their halos are
+  // larger), so the blocks of every size class are dealt out in 8 Morton-
+  // contiguous groups and the list is group 0 of every class, then group 1
+  // of every class, ...: every eighth holds an eighth of each class.  A
+  // block's tiles stay contiguous.
+  {
+    std::vector<int> dealt;
+    dealt.reserve(nb);
+    size_t a = 0;
+    std::vector<std::pair<size_t, size_t>> classes;   // [begin, end) in order
+    while (a < order.size()) {
+      size_t e = a;
+      while (e < order.size() && cells[order[e]] == cells[order[a]]) ++e;
+      classes.push_back({a, e});
+      a = e;
+    }
+    for (int g = 0; g < 8; ++g)
+      for (auto& cl : classes) {
+        const size_t n = cl.second - cl.first;
+        for (size_t q = cl.first + n * g / 8; q < cl.first + n * (g + 1) / 8; ++q) dealt.push_back(order[q]);
+      }
+    order.swap(dealt);
+  }
   c->htiles.clear();
   c->hptiles.clear();
   c->blk_tile_begin.assign(nb, 0);
