@@ -26,7 +26,9 @@ class OracleError(RuntimeError):
 def lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liborc.so")
+        # AMRVAC_ORACLE_LIB: another build of the same source (the
+        # sanitizer test's)
+        path = os.environ.get("AMRVAC_ORACLE_LIB") or os.path.join(_HERE, "liborc.so")
         if not os.path.exists(path):
             from . import build as _b  # noqa: F401
             _b.build()

@@ -190,6 +190,23 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
     for (int i = 0; i < s; ++i) X[j][i] = next++;
   std::vector<int> Lm(s + 1);
   for (int i = 0; i <= s; ++i) Lm[i] = next++;
+  // memory: state slots (the context keeps them for later calls) and the
+  // piece codes of one segment (freed on return); both grow with the
+  // checkpoint interval k, as (5 + segments + k s + s) slots and k s ndim
+  // code planes.  Refuse up front, with the figures, what cannot fit.
+  {
+    long long fw = 0;
+    for (int d = 0; d < 3; ++d) fw = std::max(fw, c->face_words[d]);
+    const double slot_bytes = 8.0 * (double)c->slot_stride;
+    const double grow = next - 1 > c->nslots ? slot_bytes * (double)(next - 1 - c->nslots) : 0.0;
+    const double codes = 8.0 * (double)(c->total_cells + fw) * c->cfg.ndim * s * (double)k;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && grow + codes > 0.97 * (double)free_b)
+      return ctx_fail(c, AMRVAC_ERR_NOMEM,
+                      "ssprk_adjoint: checkpoints every %d steps need %.1f GB more device memory (%d state slots, "
+                      "%.1f GB of piece codes) than the %.1f GB free; use a smaller ckpt_every",
+                      k, (grow + codes) / 1e9, next - 1, codes / 1e9, (double)free_b / 1e9);
+  }
   amrvac_status st = ensure_slots(c, next - 1);
   if (st != AMRVAC_OK) return st;
 
