@@ -327,6 +327,36 @@ def stage_roofline(key, cells, stage_s, bytes_per_cell_step):
             "hbm_target_met": hbm / PEAK_HBM_GBS >= 0.6}
 
 
+def class_sweep(bs, amrvac):
+    """Autotune each size class of a block list whose faces are all fixed
+    (so every class is a valid list on its own) and print the per-shape step
+    times per class and summed over the classes."""
+    import numpy as np
+    if np.any(bs.nbr >= 0):
+        print("bench: class sweep skipped (the list has block neighbours)", file=sys.stderr, flush=True)
+        return
+    total = {}
+    best_sum = 0.0
+    for size in sorted({int(n) for n in bs.n[:, 0]}, reverse=True):
+        idx = [i for i in range(bs.nb) if int(bs.n[i, 0]) == size]
+        sub = bs.copy()
+        sub.u = [bs.u[i] for i in idx]
+        sub.n, sub.dx, sub.xlo, sub.nbr = bs.n[idx], bs.dx[idx], bs.xlo[idx], bs.nbr[idx]
+        ctx, flat, views = amrvac.context_for(sub, amrvac.EXEC_BATCHED)
+        _, ms = ctx.autotune(amrvac.SSPRK54, 2)
+        for name, m in zip(ctx.variants(), ms):
+            if m >= 0:
+                total[name] = total.get(name, 0.0) + m
+                print(f"bench: class-sweep {size}^3 ({len(idx)} blocks) {name} {m:.3f} ms/step",
+                      file=sys.stderr, flush=True)
+        best_sum += min(m for m in ms if m >= 0)
+        ctx.close()
+        del flat, views
+    for name, m in sorted(total.items(), key=lambda kv: kv[1]):
+        print(f"bench: class-sweep sum {name} {m:.3f} ms/step", file=sys.stderr, flush=True)
+    print(f"bench: class-sweep sum best-per-class {best_sum:.3f} ms/step", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +380,9 @@ def main():
                     help="skip the GLM-MHD leg on the same block list")
     ap.add_argument("--no-lim03", action="store_true",
                     help="skip the RK3 + LIM03 leg on the same block list")
+    ap.add_argument("--class-sweep", action="store_true",
+                    help="also run the autotuner on each block-size class of the uneven list on its own "
+                         "(per-class tile-shape times on stderr)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run one plain device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -372,6 +405,9 @@ def main():
     for name, ms in zip(ctx.variants(), tune_ms):
         if ms >= 0:
             print(f"bench: autotune {name} {ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    if args.class_sweep:
+        class_sweep(bs, amrvac)
 
     def timed(nsteps, warmup):
         if warmup:

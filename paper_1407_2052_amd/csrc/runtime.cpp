@@ -139,12 +139,23 @@ static const StageVariant* pick_variant(const amrvac_ctx* c, int want) {
 static amrvac_status select_variant(amrvac_ctx* c, int i);
 
 // Build the tile list of the current variant: blocks ordered largest first,
-// then along a Morton curve of their origins, dealt out to the eight XCD
-// chunks class by class; tiles of a block contiguous and Morton-ordered.
+// then along a Morton curve of their origins; tiles of a block contiguous and
+// Morton-ordered.  The list is cut into launch groups of whole size classes
+// (blocks of equal cell count), one stage launch per group.
 static amrvac_status build_tiles(amrvac_ctx* c) {
   const StageVariant* V = c->var;
   const int T[3] = {V->tx, V->ty, V->tz};
   const int nb = (int)c->hb.size();
+  int per_cu = 0;
+  HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V->fn, V->nt, 0));
+  if (per_cu < 1) return fail(c, AMRVAC_ERR_DEVICE, "stage kernel cannot be resident");
+  const long long resident = (long long)per_cu * c->ncu;
+  auto active_tiles = [&](int b) -> long long {
+    if (!(c->active.empty() || c->active[b])) return 0;
+    long long k = 1;
+    for (int d = 0; d < 3; ++d) k *= (c->hb[b].n[d] + T[d] - 1) / T[d];
+    return k;
+  };
   std::vector<int> order(nb);
   std::vector<uint64_t> key(nb);
   std::vector<long long> cells(nb);
@@ -164,35 +175,65 @@ static amrvac_status build_tiles(amrvac_ctx* c) {
     if (cells[a] != cells[b]) return cells[a] > cells[b];
     return key[a] < key[b];
   });
-  // XCD balance: the persistent schedule gives XCD x the x-th eighth of the
-  // tile list, and tiles of small blocks cost more per cell (their halos are
-  // larger), so the blocks of every size class are dealt out in 8 Morton-
-  // contiguous groups and the list is group 0 of every class, then group 1
-  // of every class, ...: every eighth holds an eighth of each class.  A
-  // block's tiles stay contiguous.
+  // Launch groups.  The persistent schedule gives XCD x the x-th eighth of a
+  // launch's tiles, and a tile of a small block costs more than one of a
+  // large block (larger halo per cell, more fixed faces), so a launch over
+  // mixed classes loads the XCDs unevenly; one launch per class keeps every
+  // launch uniform and the tiles an XCD shares its L2 over compact in space.
+  // A class too small to fill the chip twice over joins the next one (a
+  // trailing one the previous group); inside a group of several classes each
+  // class is dealt out in 8 Morton-contiguous parts, part x of every class in
+  // the x-th eighth, so every XCD holds an eighth of each class.
+  std::vector<std::pair<size_t, size_t>> groups;   // [begin, end) in `order`
   {
-    std::vector<int> dealt;
-    dealt.reserve(nb);
-    size_t a = 0;
-    std::vector<std::pair<size_t, size_t>> classes;   // [begin, end) in order
-    while (a < order.size()) {
+    std::vector<std::pair<size_t, size_t>> classes;
+    std::vector<long long> ctiles;
+    for (size_t a = 0; a < order.size();) {
       size_t e = a;
-      while (e < order.size() && cells[order[e]] == cells[order[a]]) ++e;
+      long long k = 0;
+      while (e < order.size() && cells[order[e]] == cells[order[a]]) k += active_tiles(order[e++]);
       classes.push_back({a, e});
+      ctiles.push_back(k);
       a = e;
     }
-    for (int g = 0; g < 8; ++g)
-      for (auto& cl : classes) {
-        const size_t n = cl.second - cl.first;
-        for (size_t q = cl.first + n * g / 8; q < cl.first + n * (g + 1) / 8; ++q) dealt.push_back(order[q]);
+    std::vector<std::vector<size_t>> gcls;   // classes of each group
+    long long acc = 0;
+    for (size_t k = 0; k < classes.size(); ++k) {
+      if (gcls.empty() || acc >= 2 * resident) {
+        gcls.push_back({});
+        acc = 0;
       }
+      gcls.back().push_back(k);
+      acc += ctiles[k];
+    }
+    if (gcls.size() > 1 && acc < 2 * resident) {
+      for (size_t k : gcls.back()) gcls[gcls.size() - 2].push_back(k);
+      gcls.pop_back();
+    }
+    std::vector<int> dealt;
+    dealt.reserve(nb);
+    for (auto& g : gcls) {
+      const size_t begin = dealt.size();
+      for (int part = 0; part < 8; ++part)
+        for (size_t k : g) {
+          const size_t n = classes[k].second - classes[k].first;
+          for (size_t q = classes[k].first + n * part / 8; q < classes[k].first + n * (part + 1) / 8; ++q)
+            dealt.push_back(order[q]);
+        }
+      groups.push_back({begin, dealt.size()});
+    }
     order.swap(dealt);
   }
   c->htiles.clear();
   c->hptiles.clear();
   c->blk_tile_begin.assign(nb, 0);
   c->blk_tile_count.assign(nb, 0);
-  for (int b : order) {
+  c->launch_groups.clear();
+  size_t gi = 0;
+  for (size_t oi = 0; oi < order.size(); ++oi) {
+    const int b = order[oi];
+    if (oi == groups[gi].first) c->launch_groups.push_back({(int)c->htiles.size(), 0, 0});
+    if (oi + 1 == groups[gi].second) ++gi;
     const amrvac_block& q = c->hb[b];
     const bool act = c->active.empty() || c->active[b];
     int nt[3];
@@ -234,10 +275,18 @@ static amrvac_status build_tiles(amrvac_ctx* c) {
     HIP_TRY(c, hipMemcpyAsync(c->d_ptiles, c->hptiles.data(), sizeof(Tile) * c->hptiles.size(),
                               hipMemcpyHostToDevice, c->stream));
   }
-  int per_cu = 0;
-  HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V->fn, V->nt, 0));
-  if (per_cu < 1) return fail(c, AMRVAC_ERR_DEVICE, "stage kernel cannot be resident");
-  c->grid_batched = (int)std::min<long long>((long long)per_cu * c->ncu, (long long)c->htiles.size());
+  c->grid_batched = (int)std::min<long long>(resident, (long long)c->htiles.size());
+  {
+    std::vector<LaunchGroup> kept;
+    for (size_t g = 0; g < c->launch_groups.size(); ++g) {
+      LaunchGroup L = c->launch_groups[g];
+      const int end = g + 1 < c->launch_groups.size() ? c->launch_groups[g + 1].tile_begin : (int)c->htiles.size();
+      L.ntiles = end - L.tile_begin;
+      L.grid = (int)std::min<long long>(resident, (long long)L.ntiles);
+      if (L.ntiles > 0) kept.push_back(L);
+    }
+    c->launch_groups.swap(kept);
+  }
   // the tile list is copied from host memory that lives in the context
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return AMRVAC_OK;
@@ -437,7 +486,13 @@ static void launch_current_of(amrvac_ctx* c, int buf, hipStream_t s) {
 static void launch_stage(amrvac_ctx* c, StageParams p, int exec, hipStream_t s) {
   launch_current_of(c, p.in, s);
   if (exec == AMRVAC_EXEC_BATCHED) {
-    c->var->launch(p, c->grid_batched, s);
+    for (size_t g = 0; g < c->launch_groups.size(); ++g) {
+      StageParams q = p;
+      q.tile_begin = c->launch_groups[g].tile_begin;
+      q.ntiles = c->launch_groups[g].ntiles;
+      if (g > 0) q.cm_reset = -1;   // the slot reset runs in the first launch only
+      c->var->launch(q, c->launch_groups[g].grid, s);
+    }
     return;
   }
   const int nb = (int)c->hb.size();

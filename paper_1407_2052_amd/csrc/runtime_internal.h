@@ -25,6 +25,11 @@ void launch_set_control(Control* ctl, double dt_fixed, double cfl, double t, hip
 void launch_copy_interior(const StateTable& st, const Tile* tiles, int ntiles, int tx, int ty, int tz, int nv,
                           int src, int dst, int grid, hipStream_t s);
 
+// A range of the tile list that one batched stage launch covers.
+struct LaunchGroup {
+  int tile_begin, ntiles, grid;
+};
+
 struct GraphEntry {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -71,6 +76,7 @@ struct amrvac_ctx {
   std::vector<Tile> hptiles;   // tiles of the passive blocks
   Tile* d_ptiles = nullptr;
   int grid_batched = 0;
+  std::vector<amrvac::LaunchGroup> launch_groups;   // batched stage: one launch per group of size classes
 
   // scratch
   double* d_scr = nullptr;
