@@ -19,29 +19,6 @@
 #include <cmath>
 #include <vector>
 
-namespace amrvac {
-struct VjpVariant {
-  int ndim, mhd, tx, ty, tz, nt;
-  const void* fn;
-  void (*launch)(const VjpParams&, int grid, hipStream_t);
-  void (*cmax_term)(StateTable, int, const double*, int, Control*, double, int, int, double, hipStream_t);
-  void (*ghost)(const VjpParams&, const FixedFace*, int, double*, long long, double*, int, hipStream_t);
-};
-struct CombineParams {
-  StateTable st;
-  const Tile* tiles;
-  int ntiles, tx, ty, tz, nv;
-  int n;
-  int src[6];
-  double a[6];
-  int dst;
-};
-const VjpVariant* vjp_variant(int ndim, int mhd);
-void launch_combine(const CombineParams& p, int grid, hipStream_t s);
-void launch_lam_import(StateTable st, double* const* ptrs, int nv, int dst, int nblocks, hipStream_t s);
-void launch_lam_export(StateTable st, double* const* ptrs, int nv, int src, int nblocks, const double* gadj,
-                       long long gplane, hipStream_t s);
-}  // namespace amrvac
 
 using namespace amrvac;
 

@@ -711,15 +711,6 @@ __global__ void __launch_bounds__(1024) k_vjp_cmax(StateTable st, int nblocks, c
 
 // dst = sum_j a[j] * src[j] over the interiors (up to 6 terms; dst may be a
 // source).
-struct CombineParams {
-  StateTable st;
-  const Tile* tiles;
-  int ntiles, tx, ty, tz, nv;
-  int n;
-  int src[6];
-  double a[6];
-  int dst;
-};
 
 __global__ void __launch_bounds__(256) k_combine(CombineParams P) {
   const int tcells = P.tx * P.ty * P.tz;
@@ -797,13 +788,6 @@ __global__ void __launch_bounds__(256) k_lam_export(StateTable st, double* const
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-struct VjpVariant {
-  int ndim, mhd, tx, ty, tz, nt;
-  const void* fn;
-  void (*launch)(const VjpParams&, int grid, hipStream_t);
-  void (*cmax_term)(StateTable, int, const double*, int, Control*, double, int, int, double, hipStream_t);
-  void (*ghost)(const VjpParams&, const FixedFace*, int, double*, long long, double*, int, hipStream_t);
-};
 
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT>
 static void launch_vjp_t(const VjpParams& p, int grid, hipStream_t s) {

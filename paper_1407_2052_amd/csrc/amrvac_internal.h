@@ -181,7 +181,35 @@ struct VjpParams {
   // VJP marks the maximising cells (lowest (block, cell) key, atomicMin into
   // ctl->arg, which the c_max term then consumes and resets)
   const double* cm_in;
-  double* cpart;
+  double* cpart;    // per-work-group c_max adjoint partials, 3 per work-group
 };
+
+// A VJP kernel (tile shape as the code-emitting stage kernel of the same
+// ndim and physics), its c_max-term kernel and its fixed-face ghost kernel.
+struct VjpVariant {
+  int ndim, mhd, tx, ty, tz, nt;
+  const void* fn;
+  void (*launch)(const VjpParams&, int grid, hipStream_t);
+  // the c_max term: sum of the partials, applied at the maximising cell
+  void (*cmax_term)(StateTable, int, const double*, int, Control*, double, int, int, double, hipStream_t);
+  void (*ghost)(const VjpParams&, const FixedFace*, int, double*, long long, double*, int, hipStream_t);
+};
+
+// dst = sum_j a[j] * src[j] over the interiors (up to 6 terms).
+struct CombineParams {
+  StateTable st;
+  const Tile* tiles;
+  int ntiles, tx, ty, tz, nv;
+  int n;
+  int src[6];
+  double a[6];
+  int dst;
+};
+
+const VjpVariant* vjp_variant(int ndim, int mhd);
+void launch_combine(const CombineParams& p, int grid, hipStream_t s);
+void launch_lam_import(StateTable st, double* const* ptrs, int nv, int dst, int nblocks, hipStream_t s);
+void launch_lam_export(StateTable st, double* const* ptrs, int nv, int src, int nblocks, const double* gadj,
+                       long long gplane, hipStream_t s);
 
 }  // namespace amrvac
