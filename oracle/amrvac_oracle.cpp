@@ -48,7 +48,7 @@
 //       and H = 0 when eta > 1 and dp = 0 (the limit of both one-sided
 //       branches).  The radius is r = 1; the switch is sharp (the published
 //       smoothing band of width 2 epsilon around eta = 1 is taken with
-//       epsilon -> 0).  Sect. 5.1 reports third order in both norms for
+//       epsilon -> 0).  Sect. 4.5.1 reports third order in both norms for
 //       RK3 + LIM03 on the Alfven wave: the limited function alone does not
 //       reach it at smooth extrema, and r = 1 does at the resolutions of
 //       that test (smaller radii only asymptotically).

@@ -26,10 +26,13 @@
 //      interfaces per pencil, into registers, then LDS,
 //   C) accumulates -(Fhat_{i+1/2} - Fhat_{i-1/2}) / dx_d into per-thread
 //      register accumulators of the cells it owns.
-// The stage update reads its sources once per cell and writes the result;
-// the traffic beyond the algorithmic state passes is the re-reading of each
-// tile's extended boxes, which L2 serves only in part (the more tiles are in
-// flight per XCD, the less), and the spills of the 4-wave shapes.
+// The stage update reads its sources once per cell and writes the result.
+// The owned-cell (CORE) forms load the tile's own cells once per tile into
+// registers; phase A of each direction then loads only the halo planes of the
+// extended box along d, and the stage update takes the source that equals
+// the stage input from the same registers.  The traffic beyond the
+// algorithmic state passes is the re-reading of those halo planes, which L2
+// serves only in part (the more tiles are in flight per XCD, the less).
 //
 // Floating point: automatic FMA contraction is off for this file (the build
 // passes -ffp-contract=off) and every fused multiply-add is written
