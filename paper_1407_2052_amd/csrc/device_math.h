@@ -257,14 +257,17 @@ __device__ __forceinline__ int minmod4_arg(double m, double w, double x, double 
 // d, the fifth-order value fL, c - b and the two curvature limiters.
 struct Mp5Parts {
   double fUL, fMD, fLC, fmn, fmx;
+  double amn, amx;   // the (c, d, fMD) halves of fmn and fmx
 };
 __device__ __forceinline__ double mp5_tail(double c, double d, double fL, double cb, double m4p, double m4m,
                                            Mp5Parts& q) {
   q.fUL = fma(4.0, cb, c);
   q.fMD = fma(-0.5, m4p, 0.5 * (c + d));
   q.fLC = fma(4.0 / 3.0, m4m, fma(0.5, cb, c));
-  q.fmn = fmax(fmin(fmin(c, d), q.fMD), fmin(fmin(c, q.fUL), q.fLC));
-  q.fmx = fmin(fmax(fmax(c, d), q.fMD), fmax(fmax(c, q.fUL), q.fLC));
+  q.amn = fmin(fmin(c, d), q.fMD);
+  q.amx = fmax(fmax(c, d), q.fMD);
+  q.fmn = fmax(q.amn, fmin(fmin(c, q.fUL), q.fLC));
+  q.fmx = fmin(q.amx, fmax(fmax(c, q.fUL), q.fLC));
   return fmin(fmax(fL, q.fmn), q.fmx);
 }
 
@@ -276,20 +279,18 @@ __device__ __forceinline__ double mp5_tail(double c, double d, double fL, double
 //   arguments ordered (4d_j - d_{j+1}, 4d_{j+1} - d_j, d_j, d_{j+1}) for fMD
 //   at j+1/2 and (4d_j - d_{j-1}, 4d_{j-1} - d_j, d_j, d_{j-1}) for fLC at
 //   j-1/2.  The piece is fL when fmin <= fL <= fmax; else the candidate that
-//   realised fmin (fL < fmin) or fmax (fL > fmax), searched as a minimum
-//   over sigma * candidate with sigma = +1 or -1 (ties to the earlier
-//   candidate, as in the min/max chains).
+//   realised the bound r the value was clamped to (fmin when fL < fmin, fmax
+//   when fL > fmax).  The bound is the max (min) of two chains, (c, d, fMD)
+//   and (c, fUL, fLC), and the first chain wins ties, so r comes from the
+//   second chain exactly when it differs from the first chain's value; in
+//   that chain the piece is the first candidate equal to r, which is the
+//   earlier-wins tie rule of the min/max chains.
 __device__ __forceinline__ int mp5_piece(double c, double d, double fL, const Mp5Parts& q, int kp, int km) {
   const bool lo = fL < q.fmn, hi = fL > q.fmx;
-  const double sg = hi ? -1.0 : 1.0;
-  const double sc = sg * c, sd = sg * d, sMD = sg * q.fMD, sUL = sg * q.fUL, sLC = sg * q.fLC;
-  double t1 = sc, t2 = sc;
-  int k1 = 1, k2 = 1;
-  if (sd < t1) { t1 = sd; k1 = 2; }
-  if (sMD < t1) { t1 = sMD; k1 = 4 + kp; }
-  if (sUL < t2) { t2 = sUL; k2 = 3; }
-  if (sLC < t2) { t2 = sLC; k2 = 9 + km; }
-  return (lo || hi) ? (t2 > t1 ? k2 : k1) : 0;
+  const double r = lo ? q.fmn : q.fmx;
+  const bool second = r != (lo ? q.amn : q.amx);
+  const int k = c == r ? 1 : second ? (q.fUL == r ? 3 : 9 + km) : (d == r ? 2 : 4 + kp);
+  return (lo || hi) ? k : 0;
 }
 
 // MP5 (Suresh & Huynh 1997, alpha = 4, eps = 0, median form) of RUN

@@ -204,6 +204,35 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
           }
         };
         if constexpr (CORE) {
+          // the 2 HG halo planes along D from memory (plane p < HG is
+          // extended-box row p, plane p >= HG row tend_D + p): every load of
+          // this thread is issued first, and the owned cells, which come from
+          // registers, are converted while the loads are in flight
+          constexpr int H0 = D == 0 ? 2 * HG : TX, H1 = D == 1 ? 2 * HG : TY, H2 = D == 2 ? 2 * HG : TZ;
+          constexpr int NH = H0 * H1 * H2;
+          constexpr int HPT = (NH + NT - 1) / NT;
+          double hu[HPT][NV];
+          int ha[HPT][3];
+          bool hok[HPT];
+#pragma unroll
+          for (int r = 0; r < HPT; ++r) {
+            const int h = tid + r * NT;
+            ha[r][0] = h % H0;
+            ha[r][1] = (h / H0) % H1;
+            ha[r][2] = h / (H0 * H1);
+            bool valid = h < NH;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+              if (d != D) valid = valid && (ha[r][d] < tend[d]);
+            if (ha[r][D] >= HG) ha[r][D] += tend[D];
+            hok[r] = valid;
+            if (valid) {
+              int cc[3];
+#pragma unroll
+              for (int d = 0; d < 3; ++d) cc[d] = tl.o[d] + ha[r][d] - (d == D ? HG : 0);
+              load_cell<NV, D>(st, tl.block, P.in, cc[0], cc[1], cc[2], hu[r]);
+            }
+          }
           // owned cells from registers
 #pragma unroll
           for (int r = 0; r < CPT; ++r) {
@@ -215,23 +244,13 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
               split_to_lds(uc[r], a, cc);
             }
           }
-          // the 2 HG halo planes along D from memory: plane p < HG is
-          // extended-box row p, plane p >= HG row tend_D + p
-          constexpr int H0 = D == 0 ? 2 * HG : TX, H1 = D == 1 ? 2 * HG : TY, H2 = D == 2 ? 2 * HG : TZ;
-          for (int h = tid; h < H0 * H1 * H2; h += NT) {
-            int a[3] = {h % H0, (h / H0) % H1, h / (H0 * H1)};
-            bool valid = true;
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
-              if (d != D) valid = valid && (a[d] < tend[d]);
-            if (!valid) continue;
-            if (a[D] >= HG) a[D] += tend[D];
+          for (int r = 0; r < HPT; ++r) {
+            if (!hok[r]) continue;
             int cc[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) cc[d] = tl.o[d] + a[d] - (d == D ? HG : 0);
-            double u[NV];
-            load_cell<NV, D>(st, tl.block, P.in, cc[0], cc[1], cc[2], u);
-            split_to_lds(u, a, cc);
+            for (int d = 0; d < 3; ++d) cc[d] = tl.o[d] + ha[r][d] - (d == D ? HG : 0);
+            split_to_lds(hu[r], ha[r], cc);
           }
         } else {
           for (int e = tid; e < NEXT_D; e += NT) {
