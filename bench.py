@@ -73,11 +73,11 @@ def kernel_source_hash(read=None):
 
 
 def measured_traffic(variant):
-    """HBM bytes per stage launch from committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (calibrated against a plain copy), if they were taken on
-    the current kernel source and include the tile shape that is being timed
-    (the autotuner launches every shape on the same list, so one run covers
-    them all)."""
+    """HBM bytes per stage (the stage's launches together: one per block-size
+    class) from committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (calibrated
+    against a plain copy), if they were taken on the current kernel source
+    and include the tile shape that is being timed (the autotuner launches
+    every shape on the same list, so one run covers them all)."""
     path = os.path.join(ROOT, "profiles", "stage_kernel_mhd3d_uneven4096_traffic.json")
     if not os.path.exists(path):
         return None
@@ -86,8 +86,8 @@ def measured_traffic(variant):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     if rec.get("variant") == variant:
-        return rec.get("bytes_per_launch")
-    return rec.get("variants", {}).get(variant, {}).get("bytes_per_launch")
+        return rec.get("bytes_per_stage")
+    return rec.get("variants", {}).get(variant, {}).get("bytes_per_stage")
 
 
 def cpu_model():
