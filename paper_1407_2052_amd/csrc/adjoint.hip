@@ -338,7 +338,75 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
       const double idx_d = B.inv_dx[D];
 
       // A) mu on the extended box (owned cells from registers, the 3 + 3
-      // halo rows along D from memory), codes on the interface box
+      // halo rows along D from memory), codes on the interface box.  Every
+      // load of this thread is issued first (codes, then the halo rows' mu,
+      // term by term over all of this thread's halo cells); the owned cells'
+      // mu goes to LDS while they are in flight.
+      constexpr int NCB = C0 * C1 * C2, CPTC = (NCB + NT - 1) / NT;
+      unsigned long long cw[CPTC];
+      int cpos[CPTC];
+#pragma unroll
+      for (int r = 0; r < CPTC; ++r) {
+        const int e = tid + r * NT;
+        const int a[3] = {e % C0, (e / C0) % C1, e / (C0 * C1)};
+        bool valid = e < NCB;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) valid = valid && a[d] < tend[d] + (d == D ? 5 : 0);
+        cw[r] = 0ull;
+        cpos[r] = valid ? a[D] * PS + S::PENC(D, a[0], a[1], a[2]) : -1;
+        if (!valid) continue;
+        int cc[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cc[d] = tl.o[d] + a[d] - (d == D ? 2 : 0);
+        const int up = cc[D];   // before resolve_cell moves it into a neighbour
+        const BlockDev* Bn = resolve_cell<D>(st, tl.block, cc);
+        if (!Bn && up == B.n[D] && B.fco[D] >= 0) {
+          // the interface on a fixed upper face: its word after the interior cells
+          const long long tr = D == 0 ? (long long)cc[1] + (long long)B.n[1] * cc[2]
+                             : D == 1 ? (long long)cc[0] + (long long)B.n[0] * cc[2]
+                                      : (long long)cc[0] + (long long)B.n[0] * cc[1];
+          cw[r] = *(__attribute__((address_space(1))) const unsigned long long*)(P.codes + D * P.code_plane +
+                                                                                (P.code_faces + B.fco[D] + tr) * 8);
+        }
+        if (Bn) {
+          const long long cell = ((long long)cc[2] * Bn->n[1] + cc[1]) * Bn->n[0] + cc[0];
+          cw[r] = *(__attribute__((address_space(1))) const unsigned long long*)(P.codes + D * P.code_plane +
+                                                                                (Bn->coff + cell) * 8);
+        }
+      }
+      constexpr int H0 = D == 0 ? 6 : TX, H1 = D == 1 ? 6 : TY, H2 = D == 2 ? 6 : TZ;
+      constexpr int NHB = H0 * H1 * H2, HPTM = (NHB + NT - 1) / NT;
+      double hm[HPTM][NV];
+      int hrow[HPTM], hpen[HPTM];
+      const BlockDev* hB[HPTM];
+      int hc[HPTM][3];
+#pragma unroll
+      for (int r = 0; r < HPTM; ++r) {
+        const int e = tid + r * NT;
+        int a[3] = {e % H0, (e / H0) % H1, e / (H0 * H1)};
+        bool valid = e < NHB;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (d != D) valid = valid && a[d] < tend[d];
+        if (a[D] >= 3) a[D] += tend[D];   // rows 0..2 below the tile, tend+3 .. tend+5 above
+#pragma unroll
+        for (int d = 0; d < 3; ++d) hc[r][d] = tl.o[d] + a[d] - (d == D ? 3 : 0);
+        hB[r] = valid ? resolve_cell<D>(st, tl.block, hc[r]) : nullptr;
+        hrow[r] = valid ? a[D] : -1;
+        hpen[r] = S::PENC(D, a[0], a[1], a[2]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) hm[r][v] = 0.0;
+      }
+      for (int q = 0; q < P.nmu; ++q) {
+#pragma unroll
+        for (int r = 0; r < HPTM; ++r) {
+          if (!hB[r]) continue;
+          long long vs;
+          gptr p = cell_addr(st, *hB[r], P.mu_src[q], hc[r][0], hc[r][1], hc[r][2], vs);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) hm[r][v] = fma(P.mu_a[q], p[v * vs], hm[r][v]);
+        }
+      }
 #pragma unroll
       for (int r = 0; r < CPT; ++r) {
         if (!own[r]) continue;
@@ -349,61 +417,15 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) sMu[(v * MR + row) * PS + pen] = muo[r][v];
       }
-      constexpr int H0 = D == 0 ? 6 : TX, H1 = D == 1 ? 6 : TY, H2 = D == 2 ? 6 : TZ;
-      for (int e = tid; e < H0 * H1 * H2; e += NT) {
-        int a[3] = {e % H0, (e / H0) % H1, e / (H0 * H1)};
-        bool valid = true;
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-          if (d != D) valid = valid && a[d] < tend[d];
-        if (!valid) continue;
-        if (a[D] >= 3) a[D] += tend[D];   // rows 0..2 below the tile, tend+3 .. tend+5 above
-        int cc[3];
+      for (int r = 0; r < HPTM; ++r) {
+        if (hrow[r] < 0) continue;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) cc[d] = tl.o[d] + a[d] - (d == D ? 3 : 0);
-        const BlockDev* Bn = resolve_cell<D>(st, tl.block, cc);
-        double mu[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) mu[v] = 0.0;
-        if (Bn) {
-          for (int q = 0; q < P.nmu; ++q) {
-            long long vs;
-            gptr p = cell_addr(st, *Bn, P.mu_src[q], cc[0], cc[1], cc[2], vs);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) mu[v] = fma(P.mu_a[q], p[v * vs], mu[v]);
-          }
-        }
-        const int row = a[D], pen = S::PENC(D, a[0], a[1], a[2]);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sMu[(v * MR + row) * PS + pen] = mu[v];
+        for (int v = 0; v < NV; ++v) sMu[(v * MR + hrow[r]) * PS + hpen[r]] = hm[r][v];
       }
-      for (int e = tid; e < C0 * C1 * C2; e += NT) {
-        const int a[3] = {e % C0, (e / C0) % C1, e / (C0 * C1)};
-        bool valid = true;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) valid = valid && a[d] < tend[d] + (d == D ? 5 : 0);
-        if (!valid) continue;
-        int cc[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) cc[d] = tl.o[d] + a[d] - (d == D ? 2 : 0);
-        const int up = cc[D];   // before resolve_cell moves it into a neighbour
-        const BlockDev* Bn = resolve_cell<D>(st, tl.block, cc);
-        unsigned long long code = 0ull;
-        if (!Bn && up == B.n[D] && B.fco[D] >= 0) {
-          // the interface on a fixed upper face: its word after the interior cells
-          const long long tr = D == 0 ? (long long)cc[1] + (long long)B.n[1] * cc[2]
-                             : D == 1 ? (long long)cc[0] + (long long)B.n[0] * cc[2]
-                                      : (long long)cc[0] + (long long)B.n[0] * cc[1];
-          code = *(__attribute__((address_space(1))) const unsigned long long*)(P.codes + D * P.code_plane +
-                                                                               (P.code_faces + B.fco[D] + tr) * 8);
-        }
-        if (Bn) {
-          const long long cell = ((long long)cc[2] * Bn->n[1] + cc[1]) * Bn->n[0] + cc[0];
-          code = *(__attribute__((address_space(1))) const unsigned long long*)(P.codes + D * P.code_plane +
-                                                                               (Bn->coff + cell) * 8);
-        }
-        sCode[a[D] * PS + S::PENC(D, a[0], a[1], a[2])] = code;
-      }
+      for (int r = 0; r < CPTC; ++r)
+        if (cpos[r] >= 0) sCode[cpos[r]] = cw[r];
       __syncthreads();
 
       // B) sweeps
