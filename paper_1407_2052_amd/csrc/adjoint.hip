@@ -281,23 +281,34 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
       const int rem = B.n[d] - tl.o[d];
       tend[d] = rem < S::T(d) ? rem : S::T(d);
     }
-    // owned cells: state, primitives, accumulators, and mu (formed once per
-    // tile; each direction then loads only the halo rows of mu)
+    // owned cells: state, primitives, accumulators, mu (formed once per
+    // tile; each direction then loads only the halo rows of mu) and the
+    // lambda combination of the output.  Every load is issued first, term by
+    // term over the thread's cells; primitives and the maximiser test follow.
     double uo[CPT][NV];
     PrimD wo[CPT];
     double nu[CPT][NV];
     double muo[CPT][NV];
+    double acc[CPT][NV];
     bool own[CPT];
+    int oc[CPT][3];
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
       const int cidx = tid + r * NT;
       const int a0 = cidx % TX, a1 = (cidx / TX) % TY, a2 = cidx / (TX * TY);
       own[r] = cidx < TC && a0 < tend[0] && a1 < tend[1] && a2 < tend[2];
+      oc[r][0] = tl.o[0] + a0;
+      oc[r][1] = tl.o[1] + a1;
+      oc[r][2] = tl.o[2] + a2;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) nu[r][v] = 0.0;
+      for (int v = 0; v < NV; ++v) {
+        nu[r][v] = 0.0;
+        muo[r][v] = 0.0;
+        acc[r][v] = 0.0;
+      }
       if (own[r]) {
         long long vs;
-        gptr p = cell_addr(st, B, P.in, tl.o[0] + a0, tl.o[1] + a1, tl.o[2] + a2, vs);
+        gptr p = cell_addr(st, B, P.in, oc[r][0], oc[r][1], oc[r][2], vs);
 #pragma unroll
         for (int v = 0; v < NV; ++v) uo[r][v] = p[v * vs];
       } else {
@@ -305,26 +316,39 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
         for (int v = 0; v < NV; ++v) uo[r][v] = (v == 0) ? 1.0 : 0.0;
         uo[r][E::IE] = 1.0;
       }
+    }
+    for (int q = 0; q < P.nmu; ++q) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        if (!own[r]) continue;
+        long long vs;
+        gptr p = cell_addr(st, B, P.mu_src[q], oc[r][0], oc[r][1], oc[r][2], vs);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) muo[r][v] = fma(P.mu_a[q], p[v * vs], muo[r][v]);
+      }
+    }
+    for (int q = 0; q < P.nlam; ++q) {
+#pragma unroll
+      for (int r = 0; r < CPT; ++r) {
+        if (!own[r]) continue;
+        long long vs;
+        gptr p = cell_addr(st, B, P.lam_src[q], oc[r][0], oc[r][1], oc[r][2], vs);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[r][v] = fma(P.lam_a[q], p[v * vs], acc[r][v]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
       prim<NDIM, MHD>(uo[r], gamma, wo[r]);
       if (own[r]) {
         // the cells that realise c_max (bitwise the speed the recompute
         // folded into it): the lowest key wins
         const long long key =
-            ((long long)tl.block << 32) | (((long long)(tl.o[2] + a2) * B.n[1] + (tl.o[1] + a1)) * B.n[0] + (tl.o[0] + a0));
+            ((long long)tl.block << 32) | (((long long)oc[r][2] * B.n[1] + oc[r][1]) * B.n[0] + oc[r][0]);
 #pragma unroll
         for (int d = 0; d < NDIM; ++d)
           if (fabs(wo[r].v[d]) + fast_speed<MHD>(wo[r], d, gamma) == cin[d])
             atomicMin(reinterpret_cast<unsigned long long*>(&P.ctl->arg[d]), (unsigned long long)key);
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) muo[r][v] = 0.0;
-      if (own[r]) {
-        for (int q = 0; q < P.nmu; ++q) {
-          long long vs;
-          gptr p = cell_addr(st, B, P.mu_src[q], tl.o[0] + a0, tl.o[1] + a1, tl.o[2] + a2, vs);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) muo[r][v] = fma(P.mu_a[q], p[v * vs], muo[r][v]);
-        }
       }
     }
 
@@ -508,21 +532,10 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
       if (!own[r]) continue;
-      const int cidx = tid + r * NT;
-      const int i = tl.o[0] + cidx % TX, j = tl.o[1] + (cidx / TX) % TY, k = tl.o[2] + cidx / (TX * TY);
-      double acc[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-      for (int q = 0; q < P.nlam; ++q) {
-        long long vs;
-        gptr p = cell_addr(st, B, P.lam_src[q], i, j, k, vs);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = fma(P.lam_a[q], p[v * vs], acc[v]);
-      }
       long long ws;
-      gptr_w p = cell_addr_w(st, B, P.dst, i, j, k, ws);
+      gptr_w p = cell_addr_w(st, B, P.dst, oc[r][0], oc[r][1], oc[r][2], ws);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) p[v * ws] = fma(P.scale, nu[r][v], acc[v]);
+      for (int v = 0; v < NV; ++v) p[v * ws] = fma(P.scale, nu[r][v], acc[r][v]);
     }
   }
   // per-work-group c_max adjoint sums
