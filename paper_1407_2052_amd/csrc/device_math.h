@@ -42,6 +42,14 @@ __device__ __forceinline__ int opaque_uniform(int x) {
   return x;
 }
 
+// The same value, hidden from common-subexpression elimination (no
+// instruction): a recomputation from it is not merged with an earlier one,
+// so the earlier results need not stay live in registers until then.
+__device__ __forceinline__ double opaque_value(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // Pointers into global memory (address space 1).  Block states and scratch
 // slots are reached through pointers read from the block table, which the
 // compiler would otherwise treat as generic: generic accesses compile to
@@ -307,28 +315,60 @@ __device__ __forceinline__ void mp5_run(const double* f, double* out, int* code)
   double m4[RUN + 1];   // limiter of the pair (j + 1, j + 2)
 #pragma unroll
   for (int j = 0; j < RUN + 1; ++j) m4[j] = m4pair(dc[j], dc[j + 1]);
-  // With CODES, the argument each pair limiter returned, in the two orders
-  // its interfaces number them: (4x - y, 4y - x, x, y) where it is the
-  // limiter at j+1/2 (fMD of interface kk = pair - 1), and (4y - x, 4x - y,
-  // y, x) where it is the limiter at j-1/2 (fLC of interface kk = pair).
-  int kpp[CODES ? RUN + 1 : 1], kmp[CODES ? RUN + 1 : 1];
+  auto fifth = [&](int kk) {
+    return fma(2.0, f[kk], fma(-13.0, f[kk + 1], fma(47.0, f[kk + 2], fma(27.0, f[kk + 3], -3.0 * f[kk + 4])))) *
+           (1.0 / 60.0);
+  };
+  bool clamped = false;
+#pragma unroll
+  for (int kk = 0; kk < RUN; ++kk) {
+    const double fL = fifth(kk);
+    Mp5Parts q;
+    out[kk] = mp5_tail(f[kk + 2], f[kk + 3], fL, f[kk + 2] - f[kk + 1], m4[kk + 1], m4[kk], q);
+    if constexpr (CODES) clamped = clamped || fL < q.fmn || fL > q.fmx;
+  }
   if constexpr (CODES) {
+    // every piece is fL (code 0) unless the value was clamped; a wave in
+    // which no lane clamped any interface of its run skips the search
+    if (__ballot(clamped) == 0) {
+#pragma unroll
+      for (int kk = 0; kk < RUN; ++kk) code[kk] = 0;
+      return;
+    }
+    // Recomputed from the stencil values (passed through opaque_value, so
+    // that nothing of the first pass stays live for this rare path): the
+    // same operations on the same inputs give the same curvatures, limiters,
+    // fifth-order values and bounds.
+    double g[RUN + 4];
+#pragma unroll
+    for (int j = 0; j < RUN + 4; ++j) g[j] = opaque_value(f[j]);
+    double gc[RUN + 2];
+#pragma unroll
+    for (int j = 0; j < RUN + 2; ++j) gc[j] = fma(-2.0, g[j + 1], g[j]) + g[j + 2];
+    // the argument each pair limiter returned, in the two orders its
+    // interfaces number them: (4x - y, 4y - x, x, y) where it is the limiter
+    // at j+1/2 (fMD of interface kk = pair - 1), and (4y - x, 4x - y, y, x)
+    // where it is the limiter at j-1/2 (fLC of interface kk = pair)
+    double gm[RUN + 1];
+    int kpp[RUN + 1], kmp[RUN + 1];
 #pragma unroll
     for (int j = 0; j < RUN + 1; ++j) {
-      const double x = dc[j], y = dc[j + 1], m = m4[j];
+      const double x = gc[j], y = gc[j + 1];
+      const double m = m4pair(x, y);
+      gm[j] = m;
       const bool z = m == 0.0, e1 = fma(4.0, x, -y) == m, e2 = fma(4.0, y, -x) == m, e3 = x == m, e4 = y == m;
       kpp[j] = z ? 0 : e1 ? 1 : e2 ? 2 : e3 ? 3 : 4;
       kmp[j] = z ? 0 : e2 ? 1 : e1 ? 2 : e4 ? 3 : 4;
     }
-  }
 #pragma unroll
-  for (int kk = 0; kk < RUN; ++kk) {
-    const double a = f[kk], b = f[kk + 1], c = f[kk + 2], d = f[kk + 3], e = f[kk + 4];
-    const double fL = fma(2.0, a, fma(-13.0, b, fma(47.0, c, fma(27.0, d, -3.0 * e)))) * (1.0 / 60.0);
-    const double cb = c - b;
-    Mp5Parts q;
-    out[kk] = mp5_tail(c, d, fL, cb, m4[kk + 1], m4[kk], q);
-    if constexpr (CODES) code[kk] = mp5_piece(c, d, fL, q, kpp[kk + 1], kmp[kk]);
+    for (int kk = 0; kk < RUN; ++kk) {
+      const double fL =
+          fma(2.0, g[kk], fma(-13.0, g[kk + 1], fma(47.0, g[kk + 2], fma(27.0, g[kk + 3], -3.0 * g[kk + 4])))) *
+          (1.0 / 60.0);
+      Mp5Parts q;
+      (void)mp5_tail(g[kk + 2], g[kk + 3], fL, g[kk + 2] - g[kk + 1], gm[kk + 1], gm[kk], q);
+      code[kk] = mp5_piece(g[kk + 2], g[kk + 3], fL, q, kpp[kk + 1], kmp[kk]);
+    }
   }
 }
 
