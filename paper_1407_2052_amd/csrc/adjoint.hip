@@ -267,6 +267,14 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) cin[d] = P.cm_in[d];
   __syncthreads();
+  // the piece almost every interface takes (MP5: the fifth-order value, code
+  // 0; LIM03: the third-order formula, code 1), its weights in registers: a
+  // wave whose interfaces all took it on both sides skips the table
+  const int pc = P.recon == 1 ? 1 : 0;
+  const int ccom = pc | (pc << 4);
+  double wc[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) wc[q] = sW[pc * 5 + q];
 
   // c_max adjoint sums of this work-group's tiles (taken in the fixed tile
   // order of the schedule, then a fixed butterfly: deterministic)
@@ -467,25 +475,50 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
           const int g = item / (NP * NV);
           const double* mu = &sMu[(v * MR) * PS + pen];
           const unsigned char* cd = reinterpret_cast<const unsigned char*>(&sCode[pen]) + v;
+          // every interface of the window on the common piece on both
+          // sides, in every lane of the wave: the register weights serve
+          bool common = true;
+#pragma unroll
+          for (int kk = 0; kk < SEG + 5; ++kk) common = common && cd[(g * SEG + kk) * PS * 8] == ccom;
           double mprev = mu[(g * SEG) * PS];
+          if (__ballot(!common) == 0) {
 #pragma unroll
-          for (int kk = 0; kk < SEG + 5; ++kk) {
-            const int k = g * SEG + kk;
-            const double mnext = mu[(k + 1) * PS];
-            const double lf = (mnext - mprev) * idx_d;
-            mprev = mnext;
-            const int code = cd[k * PS * 8];
-            const double* wp = &sW[(code & 15) * 5];
-            const double* wm = &sW[(code >> 4) * 5];
+            for (int kk = 0; kk < SEG + 5; ++kk) {
+              const int k = g * SEG + kk;
+              const double mnext = mu[(k + 1) * PS];
+              const double lf = (mnext - mprev) * idx_d;
+              mprev = mnext;
 #pragma unroll
-            for (int s = 0; s < 5; ++s) {
-              const int j = kk - 5 + s;   // F+ stencil: cell i-2+s
-              if (j >= 0 && j < SEG) rp[r][j] = fma(lf, wp[s], rp[r][j]);
+              for (int s = 0; s < 5; ++s) {
+                const int j = kk - 5 + s;   // F+ stencil: cell i-2+s
+                if (j >= 0 && j < SEG) rp[r][j] = fma(lf, wc[s], rp[r][j]);
+              }
+#pragma unroll
+              for (int s = 0; s < 5; ++s) {
+                const int j = kk - s;       // F- stencil: cell i+3-s
+                if (j >= 0 && j < SEG) rm[r][j] = fma(lf, wc[s], rm[r][j]);
+              }
             }
+          } else {
 #pragma unroll
-            for (int s = 0; s < 5; ++s) {
-              const int j = kk - s;       // F- stencil: cell i+3-s
-              if (j >= 0 && j < SEG) rm[r][j] = fma(lf, wm[s], rm[r][j]);
+            for (int kk = 0; kk < SEG + 5; ++kk) {
+              const int k = g * SEG + kk;
+              const double mnext = mu[(k + 1) * PS];
+              const double lf = (mnext - mprev) * idx_d;
+              mprev = mnext;
+              const int code = cd[k * PS * 8];
+              const double* wp = &sW[(code & 15) * 5];
+              const double* wm = &sW[(code >> 4) * 5];
+#pragma unroll
+              for (int s = 0; s < 5; ++s) {
+                const int j = kk - 5 + s;
+                if (j >= 0 && j < SEG) rp[r][j] = fma(lf, wp[s], rp[r][j]);
+              }
+#pragma unroll
+              for (int s = 0; s < 5; ++s) {
+                const int j = kk - s;
+                if (j >= 0 && j < SEG) rm[r][j] = fma(lf, wm[s], rm[r][j]);
+              }
             }
           }
         }
