@@ -719,17 +719,46 @@ __global__ void __launch_bounds__(256) k_vjp_ghost(VjpParams P, const FixedFace*
 }
 
 // Sum of the per-work-group c_max adjoints (fixed order: strided per
-// thread, then a fixed butterfly per wave, then the 16 waves in order), then
-// lam[argmax_d] += scale * lamc_d * d(|v_d| + c_f,d)/dU at the maximiser.
+// thread, then a fixed butterfly per wave, then the 4 waves in order), then
+// lam[argmax_d] += scale * lamc_d * d(|v_d| + c_f,d)/dU at the maximiser, for
+// d in order.  Thread 0 issues the loads of the maximisers' keys, block
+// entries, states and lambda values first, so they overlap the sum.
 template <int NDIM, bool MHD>
-__global__ void __launch_bounds__(1024) k_vjp_cmax(StateTable st, int nblocks, const double* cpart, int nparts,
-                                                   Control* ctl, double gamma, int in, int lam, double scale) {
+__global__ void __launch_bounds__(256) k_vjp_cmax(StateTable st, int nblocks, const double* cpart, int nparts,
+                                                  Control* ctl, double gamma, int in, int lam, double scale) {
   using E = Eq<NDIM, MHD>;
-  __shared__ double s[1][3];
-  __shared__ double ws[16][3];
+  constexpr int NV = E::NV;
+  __shared__ double ws[4][3];
   const int tid = threadIdx.x;
+  bool ok[NDIM];
+  int bk[NDIM];
+  long long ck[NDIM], wst[NDIM];
+  double u[NDIM][NV], lv[NDIM][NV];
+  gptr_w qd[NDIM];
+  if (tid == 0) {
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+      const long long key = ctl->arg[d];
+      bk[d] = (int)(key >> 32);
+      ck[d] = key & 0xffffffffll;
+      // no cell had a finite speed (non-physical state): reported below, never indexed
+      ok[d] = !(key < 0 || bk[d] < 0 || bk[d] >= nblocks) && ck[d] < st.blocks[bk[d]].cells;
+      if (!ok[d]) continue;
+      const BlockDev& B = st.blocks[bk[d]];
+      const int i = (int)(ck[d] % B.n[0]), j = (int)((ck[d] / B.n[0]) % B.n[1]),
+                k = (int)(ck[d] / ((long long)B.n[0] * B.n[1]));
+      long long vs;
+      gptr p = cell_addr(st, B, in, i, j, k, vs);
+      qd[d] = (gptr_w)(cell_addr(st, B, lam, i, j, k, wst[d]));
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        u[d][v] = p[v * vs];
+        lv[d][v] = qd[d][v * wst[d]];
+      }
+    }
+  }
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int t = tid; t < nparts; t += 1024)
+  for (int t = tid; t < nparts; t += 256)
 #pragma unroll
     for (int d = 0; d < 3; ++d) acc[d] += cpart[3 * (long long)t + d];
 #pragma unroll
@@ -739,39 +768,34 @@ __global__ void __launch_bounds__(1024) k_vjp_cmax(StateTable st, int nblocks, c
     for (int d = 0; d < 3; ++d) ws[tid >> 6][d] = acc[d];
   }
   __syncthreads();
-  if (tid == 0) {
-    for (int d = 0; d < 3; ++d) {
-      double x = ws[0][d];
-      for (int q = 1; q < 16; ++q) x += ws[q][d];
-      s[0][d] = x;
-    }
-  }
   if (tid != 0) return;
+  double sd[3];
+  for (int d = 0; d < 3; ++d) sd[d] = ((ws[0][d] + ws[1][d]) + ws[2][d]) + ws[3][d];
+#pragma unroll
   for (int d = 0; d < NDIM; ++d) {
-    const long long key = ctl->arg[d];
-    const int b = (int)(key >> 32);
-    const long long cell = key & 0xffffffffll;
-    // no cell had a finite speed (non-physical state): report, never index
-    if (key < 0 || b < 0 || b >= nblocks) {
+    if (!ok[d]) {
       atomicOr(&ctl->err, 1);
       break;
     }
-    const BlockDev& B = st.blocks[b];
-    if (cell >= B.cells) {
-      atomicOr(&ctl->err, 1);
-      break;
+    // the current lambda at the cell: updated by an earlier direction with
+    // the same maximiser, else as loaded
+    double cur[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) cur[v] = lv[d][v];
+#pragma unroll
+    for (int e = 0; e < d; ++e)
+      if (bk[e] == bk[d] && ck[e] == ck[d])
+#pragma unroll
+        for (int v = 0; v < NV; ++v) cur[v] = lv[e][v];
+    double lu[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lu[v] = 0.0;
+    speed_vjp<NDIM, MHD>(u[d], gamma, d, sd[d], lu);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      lv[d][v] = fma(scale, lu[v], cur[v]);
+      qd[d][v * wst[d]] = lv[d][v];
     }
-    const int i = (int)(cell % B.n[0]), j = (int)((cell / B.n[0]) % B.n[1]), k = (int)(cell / ((long long)B.n[0] * B.n[1]));
-    long long vs, ws;
-    gptr p = cell_addr(st, B, in, i, j, k, vs);
-    double u[E::NV], lu[E::NV];
-    for (int v = 0; v < E::NV; ++v) {
-      u[v] = p[v * vs];
-      lu[v] = 0.0;
-    }
-    speed_vjp<NDIM, MHD>(u, gamma, d, s[0][d], lu);
-    gptr_w q = (gptr_w)(cell_addr(st, B, lam, i, j, k, ws));
-    for (int v = 0; v < E::NV; ++v) q[v * ws] = fma(scale, lu[v], q[v * ws]);
   }
   // the keys are consumed: ready for the next VJP's atomicMin
   for (int d = 0; d < 3; ++d) ctl->arg[d] = 0x7fffffffffffffffll;
@@ -866,7 +890,7 @@ static void launch_vjp_t(const VjpParams& p, int grid, hipStream_t s) {
 template <int NDIM, bool MHD>
 static void launch_cmax_term_t(StateTable st, int nblocks, const double* cpart, int ntiles, Control* ctl, double gamma,
                                int in, int lam, double scale, hipStream_t s) {
-  hipLaunchKernelGGL((k_vjp_cmax<NDIM, MHD>), dim3(1), dim3(1024), 0, s, st, nblocks, cpart, ntiles, ctl, gamma, in,
+  hipLaunchKernelGGL((k_vjp_cmax<NDIM, MHD>), dim3(1), dim3(256), 0, s, st, nblocks, cpart, ntiles, ctl, gamma, in,
                      lam, scale);
 }
 
