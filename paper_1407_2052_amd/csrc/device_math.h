@@ -325,7 +325,7 @@ __device__ __forceinline__ void mp5_run(const double* f, double* out, int* code)
     const double fL = fifth(kk);
     Mp5Parts q;
     out[kk] = mp5_tail(f[kk + 2], f[kk + 3], fL, f[kk + 2] - f[kk + 1], m4[kk + 1], m4[kk], q);
-    if constexpr (CODES) clamped = clamped || fL < q.fmn || fL > q.fmx;
+    if constexpr (CODES) clamped = clamped || out[kk] != fL;   // fL < fmin or fL > fmax
   }
   if constexpr (CODES) {
     // every piece is fL (code 0) unless the value was clamped; a wave in
