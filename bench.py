@@ -380,6 +380,8 @@ def main():
                     help="skip the GLM-MHD leg on the same block list")
     ap.add_argument("--no-lim03", action="store_true",
                     help="skip the RK3 + LIM03 leg on the same block list")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the leg that times one launch per stage over the whole list")
     ap.add_argument("--class-sweep", action="store_true",
                     help="also run the autotuner on each block-size class of the uneven list on its own "
                          "(per-class tile-shape times on stderr)")
@@ -435,6 +437,18 @@ def main():
         elp = timed(args.per_block_steps, 1)
         per_block = {"value": cells * args.per_block_steps / elp, "ms_per_step": 1e3 * elp / args.per_block_steps,
                      "steps": args.per_block_steps}
+        ctx.set_exec(amrvac.EXEC_BATCHED)
+
+    # the same batched kernels as one launch per stage over the whole list
+    # (its own autotuned tile shape), beside the one-launch-per-size-class form
+    single = None
+    if not args.no_single:
+        print("bench: batched, one launch per stage over the whole list", file=sys.stderr, flush=True)
+        ctx.set_exec(amrvac.EXEC_BATCHED_SINGLE)
+        svar, _ = ctx.autotune(amrvac.SSPRK54, 2)
+        els = timed(args.steps, args.warmup)
+        single = {"tile_shape": svar, "ms_per_step": 1e3 * els / args.steps, "value": cells * args.steps / els,
+                  "unit": "cell-updates/s"}
         ctx.set_exec(amrvac.EXEC_BATCHED)
     ctx.close()
     del flat, views
@@ -562,12 +576,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "3D ideal MHD, 4096 uneven blocks 32^3:16^3:8^3 (1:2:4), fixed ghosts "
                                "from a seeded 8-mode field, SSPRK(5,4)+MP5+global LF, CFL 0.4",
-                   "blocks": bs.nb, "cells": cells, "exec": "batched persistent, HIP graph per step",
+                   "blocks": bs.nb, "cells": cells, "exec": "batched persistent, one launch per block-size class and stage, HIP graph per step",
                    "tile_shape": variant,
                    "parallelism": "single GPU"},
         "per_stage": {"ms": 1e3 * stage_s, "cell_updates_per_s": cells / stage_s},
         "per_block": per_block,
         "batched_over_per_block": (value / per_block["value"]) if per_block else None,
+        "batched_single_launch": single,
         "adjoint_forward_ratio": adjoint["ratio"] if adjoint else None,
         "adjoint": adjoint,
         "adjoint_2d_euler": adjoint_2d,

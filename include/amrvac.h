@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define AMRVAC_ABI_VERSION 4
+#define AMRVAC_ABI_VERSION 5
 #define AMRVAC_NGHOST 3
 
 typedef enum {
@@ -84,9 +84,18 @@ typedef enum { AMRVAC_HD = 0, AMRVAC_MHD = 1, AMRVAC_GLM = 2 } amrvac_physics;
 /* Sect. 2.3: RK3 (Gottlieb & Shu 1998), SSPRK(4,3) and SSPRK(5,4) tables. */
 typedef enum { AMRVAC_RK3 = 0, AMRVAC_SSPRK43 = 1, AMRVAC_SSPRK54 = 2 } amrvac_scheme;
 
-/* Execution form of a stage: one launch per block, or one persistent fused
- * launch over the whole block list replayed from a HIP graph. */
-typedef enum { AMRVAC_EXEC_PER_BLOCK = 0, AMRVAC_EXEC_BATCHED = 1 } amrvac_exec;
+/* Execution form of a stage (every form gives bitwise the same result):
+ *  PER_BLOCK:       one launch per block and stage;
+ *  BATCHED:         persistent fused launches over the block list, one per
+ *                   block-size class (blocks of equal cell count; a class
+ *                   with fewer tiles than twice the resident work-groups
+ *                   joins the next), the step replayed from a HIP graph;
+ *  BATCHED_SINGLE:  one persistent fused launch per stage over the whole
+ *                   list (each XCD's share holds an eighth of every class),
+ *                   the step replayed from a HIP graph.
+ * Setting a batched form rebuilds the work list; the autotuner times tile
+ * shapes in the form that is set. */
+typedef enum { AMRVAC_EXEC_PER_BLOCK = 0, AMRVAC_EXEC_BATCHED = 1, AMRVAC_EXEC_BATCHED_SINGLE = 2 } amrvac_exec;
 
 /* Reconstruction of the split fluxes (Sect. 2.2).
  *  MP5:   Suresh & Huynh (1997) with alpha = 4 and eps = 0; 5-cell stencils,

@@ -19,10 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libamrvac.so")
 OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_NONPHYSICAL, ERR_UNSUPPORTED = range(6)
 HD, MHD, GLM = 0, 1, 2
 RK3, SSPRK43, SSPRK54 = 0, 1, 2
-EXEC_PER_BLOCK, EXEC_BATCHED = 0, 1
+EXEC_PER_BLOCK, EXEC_BATCHED, EXEC_BATCHED_SINGLE = 0, 1, 2
 MP5, LIM03 = 0, 1
 NGHOST = 3
-ABI_VERSION = 4
+ABI_VERSION = 5
 NOALLOC_MAX_DOUBLES = 8388608
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NONPHYSICAL", 5: "UNSUPPORTED"}
 

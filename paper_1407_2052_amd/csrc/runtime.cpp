@@ -199,7 +199,7 @@ static amrvac_status build_tiles(amrvac_ctx* c) {
     std::vector<std::vector<size_t>> gcls;   // classes of each group
     long long acc = 0;
     for (size_t k = 0; k < classes.size(); ++k) {
-      if (gcls.empty() || acc >= 2 * resident) {
+      if (gcls.empty() || (acc >= 2 * resident && !c->single_launch)) {
         gcls.push_back({});
         acc = 0;
       }
@@ -602,7 +602,8 @@ amrvac_status ctx_fail(amrvac_ctx* c, amrvac_status st, const char* fmt, ...) {
 static bool config_ok(const amrvac_config* cfg) {
   return cfg && cfg->ndim >= 1 && cfg->ndim <= 3 &&
          (cfg->physics == AMRVAC_HD || cfg->physics == AMRVAC_MHD || cfg->physics == AMRVAC_GLM) &&
-         (cfg->exec == AMRVAC_EXEC_PER_BLOCK || cfg->exec == AMRVAC_EXEC_BATCHED) &&
+         (cfg->exec == AMRVAC_EXEC_PER_BLOCK || cfg->exec == AMRVAC_EXEC_BATCHED ||
+          cfg->exec == AMRVAC_EXEC_BATCHED_SINGLE) &&
          (cfg->recon == AMRVAC_MP5 || cfg->recon == AMRVAC_LIM03) &&
          std::isfinite(cfg->eta_h) && cfg->eta_h >= 0.0 && (cfg->eta_h == 0.0 || cfg->physics == AMRVAC_MHD) &&
          std::isfinite(cfg->gamma) && cfg->gamma > 1.0;
@@ -668,7 +669,8 @@ amrvac_status amrvac_create(const amrvac_config* cfg, void* hip_stream, amrvac_c
   }
   amrvac_ctx* c = new amrvac_ctx();
   c->cfg = *cfg;
-  c->exec = cfg->exec;
+  c->exec = cfg->exec == AMRVAC_EXEC_BATCHED_SINGLE ? AMRVAC_EXEC_BATCHED : cfg->exec;
+  c->single_launch = cfg->exec == AMRVAC_EXEC_BATCHED_SINGLE;
   c->nvar = cfg->physics == AMRVAC_GLM ? 9 : cfg->physics == AMRVAC_MHD ? 8 : 2 + cfg->ndim;
   c->stream = (hipStream_t)hip_stream;
   c->var = pick_variant(c, 0);
@@ -797,9 +799,16 @@ amrvac_status amrvac_set_blocks(amrvac_ctx* c, const amrvac_block* blocks, int n
 
 amrvac_status amrvac_set_exec(amrvac_ctx* c, int exec) {
   if (!c) return AMRVAC_ERR_INVALID;
-  if (exec != AMRVAC_EXEC_PER_BLOCK && exec != AMRVAC_EXEC_BATCHED)
+  if (exec != AMRVAC_EXEC_PER_BLOCK && exec != AMRVAC_EXEC_BATCHED && exec != AMRVAC_EXEC_BATCHED_SINGLE)
     return fail(c, AMRVAC_ERR_INVALID, "set_exec: unknown execution form %d", exec);
-  c->exec = exec;
+  const bool single = exec == AMRVAC_EXEC_BATCHED_SINGLE;
+  c->exec = single ? AMRVAC_EXEC_BATCHED : exec;
+  if (exec != AMRVAC_EXEC_PER_BLOCK && single != c->single_launch) {
+    // the launch grouping is part of the work list
+    c->single_launch = single;
+    drop_graphs(c);
+    if (!c->hb.empty()) return build_tiles(c);
+  }
   return AMRVAC_OK;
 }
 
@@ -833,8 +842,8 @@ amrvac_status amrvac_autotune(amrvac_ctx* c, int scheme, int nsteps, double* ms_
   char key[256];
   hipDeviceProp_t prop;
   HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
-  snprintf(key, sizeof(key), "%s|%d|%d|%d|%zu|%lld|%d", prop.gcnArchName, c->cfg.ndim, c->cfg.physics,
-           c->cfg.recon, c->hb.size(), c->total_cells, scheme);
+  snprintf(key, sizeof(key), "%s|%d|%d|%d|%zu|%lld|%d|%d", prop.gcnArchName, c->cfg.ndim, c->cfg.physics,
+           c->cfg.recon, c->hb.size(), c->total_cells, scheme, c->single_launch ? 1 : 0);
   const char* cache = std::getenv("AMRVAC_TUNE_CACHE");
   if (cache && *cache) {
     std::ifstream in(cache);

@@ -77,6 +77,7 @@ struct amrvac_ctx {
   Tile* d_ptiles = nullptr;
   int grid_batched = 0;
   std::vector<amrvac::LaunchGroup> launch_groups;   // batched stage: one launch per group of size classes
+  bool single_launch = false;                       // BATCHED_SINGLE: one group holding every class
 
   // scratch
   double* d_scr = nullptr;

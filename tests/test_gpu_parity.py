@@ -167,14 +167,15 @@ def test_fixed_dt_steps_match_oracle():
 
 
 @pytest.mark.parametrize("case", ["ot2d", "uneven3d", "ragged3d_mhd", "dwave1d_8blk"])
-def test_per_block_launch_equals_batched_bitwise(case):
+def test_execution_forms_are_bitwise_identical(case):
     say(f"[exec] {case}")
     bs = CASES[case]()
     a, ta = gpu_run(bs, oracle.SSPRK54, 5, exec=A.EXEC_PER_BLOCK)
     b, tb = gpu_run(bs, oracle.SSPRK54, 5, exec=A.EXEC_BATCHED)
-    assert ta == tb
-    for x, y in zip(a.u, b.u):
-        assert np.array_equal(x, y)
+    c, tc = gpu_run(bs, oracle.SSPRK54, 5, exec=A.EXEC_BATCHED_SINGLE)
+    assert ta == tb == tc
+    for x, y, z in zip(a.u, b.u, c.u):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
 
 
 def test_runs_are_bitwise_deterministic():
@@ -256,11 +257,11 @@ def test_invalid_arguments_leave_state_untouched():
 
 
 def test_zero_steps_leave_state_and_time_untouched():
-    say("[edge] nsteps = 0, both execution forms and every scheme")
+    say("[edge] nsteps = 0, every execution form and every scheme")
     bs = uneven_small()
     ctx, flat, views = A.context_for(bs)
     before = flat.clone()
-    for exec in (A.EXEC_BATCHED, A.EXEC_PER_BLOCK):
+    for exec in (A.EXEC_BATCHED, A.EXEC_PER_BLOCK, A.EXEC_BATCHED_SINGLE):
         ctx.set_exec(exec)
         for scheme in (oracle.RK3, oracle.SSPRK43, oracle.SSPRK54):
             assert ctx.ssprk_step(scheme, 0, t=0.125) == 0.125
@@ -332,6 +333,11 @@ def test_full_size_uneven3d_10_steps_in_bench_configuration():
     ref, t_p = gpu_run(bs, oracle.SSPRK54, 10, exec=A.EXEC_PER_BLOCK)
     assert t_b == t_p
     for x, y in zip(out.u, ref.u):
+        assert np.array_equal(x, y)
+    say("[full] uneven3d 4096 blocks: 10 steps, one launch per stage over the whole list")
+    one, t_s = gpu_run(bs, oracle.SSPRK54, 10, exec=A.EXEC_BATCHED_SINGLE)
+    assert t_s == t_p
+    for x, y in zip(one.u, ref.u):
         assert np.array_equal(x, y)
     say("[full] uneven3d 4096 blocks: rhs of the stepped state, sampled blocks")
     Lg, cmg = gpu_rhs(out)
