@@ -37,7 +37,7 @@ METRIC = "MHD cell-updates/s (batched vs per-block, FP64) + adjoint/forward time
 OPCOUNT_RECORD = os.path.join("profiles", "oracle_op_count_mhd3d_uneven4096.json")
 # Algorithmic HBM bytes per cell per SSPRK(5,4) step: 17 state passes x 8
 # variables x 8 bytes (low-storage form: 2+3+4+5+3 passes).
-BYTES_PER_CELL_STEP_MHD3D = 17 * 8 * 8
+BYTES_PER_CELL_STEP_MHD3D = 17 * 8 * 8   # 8 variables (2D and 3D MHD alike)
 # 2D Euler: 17 passes x 4 variables x 8 bytes.
 BYTES_PER_CELL_STEP_EULER2D = 17 * 4 * 8
 # FP64 VALU: 256 CU x 4 SIMD x 16 FP64 lanes x 2.4 GHz, one operation (an
@@ -301,6 +301,32 @@ def adjoint_ratio_2d(nsteps=200, ckpt=20):
             "forward_cell_updates_per_s": cells * nsteps / fwd}
 
 
+def forward_mhd2d(nsteps, warmup):
+    """SSPRK(5,4) + MP5 forward steps of 2D ideal MHD on smooth Orszag-Tang
+    data, 512^2 periodic in 1024 blocks of 16^2 (autotuned, batched)."""
+    import torch
+    from paper_1407_2052_amd import amrvac, inputs
+    bs = inputs.orszag_tang_2d(512, 16)
+    cells = bs.interior_cells()
+    ctx, flat, views = amrvac.context_for(bs, amrvac.EXEC_BATCHED)
+    var, _ = ctx.autotune(amrvac.SSPRK54, 2)
+    stream = torch.cuda.current_stream()
+    ctx.ssprk_step(amrvac.SSPRK54, warmup, cfl=0.4, t=None)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.ssprk_step(amrvac.SSPRK54, nsteps, cfl=0.4, t=None)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ctx.sync()
+    el = e0.elapsed_time(e1) / 1e3
+    ctx.close()
+    return {"workload": "2D ideal MHD, smooth Orszag-Tang data, 512^2 periodic, 1024 x 16^2, SSPRK(5,4) + MP5",
+            "tile_shape": var, "steps": nsteps, "ms_per_step": 1e3 * el / nsteps,
+            "cell_updates_per_s": cells * nsteps / el, "cells": cells}
+
+
 def stage_roofline(key, cells, stage_s, bytes_per_cell_step):
     """FP64 VALU roofline of one fused stage launch: the oracle-counted
     operations per cell (median form) x cells / the launch time, against
@@ -380,6 +406,8 @@ def main():
                     help="skip the GLM-MHD leg on the same block list")
     ap.add_argument("--no-lim03", action="store_true",
                     help="skip the RK3 + LIM03 leg on the same block list")
+    ap.add_argument("--no-mhd2d", action="store_true",
+                    help="skip the 2D MHD 512^2 forward leg")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the leg that times one launch per stage over the whole list")
     ap.add_argument("--class-sweep", action="store_true",
@@ -549,6 +577,11 @@ def main():
                                 max(1, args.per_block_steps))
         adjoint_2d = adjoint_ratio_2d(args.adjoint_2d_steps)
 
+    mhd2d = None
+    if not args.no_mhd2d:
+        print("bench: 2D MHD 512^2 forward", file=sys.stderr, flush=True)
+        mhd2d = forward_mhd2d(args.steps, args.warmup)
+
     roofline = stage_roofline("mhd3d_uneven4096", cells, stage_s, BYTES_PER_CELL_STEP_MHD3D)
     roofline["traffic"] = measured_traffic(variant)
     roofline["kernel"] = f"k_stage<3,MHD> (fused SSPRK stage), {variant}"
@@ -563,6 +596,11 @@ def main():
         others["euler2d_256_forward"] = stage_roofline(
             "euler2d_256", 256 * 256, 256 * 256 / c4 / STAGES, BYTES_PER_CELL_STEP_EULER2D)
         others["euler2d_256_forward"]["kernel"] = f"k_stage<2,HD>, {adjoint_2d['forward_tile_shape']}"
+    if mhd2d:
+        others["mhd2d_512_forward"] = stage_roofline(
+            "mhd2d_512", mhd2d["cells"], mhd2d["cells"] / mhd2d["cell_updates_per_s"] / STAGES,
+            BYTES_PER_CELL_STEP_MHD3D)
+        others["mhd2d_512_forward"]["kernel"] = f"k_stage<2,MHD>, {mhd2d['tile_shape']}"
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -586,6 +624,7 @@ def main():
         "adjoint_forward_ratio": adjoint["ratio"] if adjoint else None,
         "adjoint": adjoint,
         "adjoint_2d_euler": adjoint_2d,
+        "mhd2d_512": mhd2d,
         "lim03": lim03,
         "glm": glm,
         "hall": hall,

@@ -19,8 +19,8 @@ stage combination.  The method's work per cell and stage is then
 direction), counted as arithmetic operations (+, -, *, /, sqrt; the oracle
 forms no fused multiply-add) and, separately, as comparisons and selections
 (min, max, minmod, median, |x|, branch tests).  The same counts are taken
-on 16 blocks of the 256^3 periodic 3D MHD list and on the 2D Euler 256^2
-list.  Writes profiles/oracle_op_count_mhd3d_uneven4096.json, read by
+on 16 blocks of the 256^3 periodic 3D MHD list, on the 2D Euler 256^2 list
+and on the 2D MHD 512^2 list.  Writes profiles/oracle_op_count_mhd3d_uneven4096.json, read by
 bench.py.
 """
 import json
@@ -88,6 +88,9 @@ def main():
     h2 = inputs.hydro_random_2d()
     out["euler2d_256"] = record(h2, "2D Euler, 256^2 periodic in 16^2 blocks, SSPRK(5,4) + MP5",
                                 f"the whole list ({h2.interior_cells()} cells), one step")
+    ot = inputs.orszag_tang_2d(512, 16)
+    out["mhd2d_512"] = record(ot, "2D ideal MHD, smooth Orszag-Tang data, 512^2 periodic in 16^2 blocks, "
+                                  "SSPRK(5,4) + MP5", f"the whole list ({ot.interior_cells()} cells), one step")
     with open(OUT, "w") as fh:
         json.dump(out, fh, indent=1)
     print("wrote", OUT)
