@@ -18,9 +18,11 @@
 // then the split adjoint (lamF = (lamF+ + lamF-)/2, c (lamF+ - lamF-)/2) and
 // the transpose of the flux Jacobian (hand-written reverse of the primitive
 // recovery and flux).
-// The c_max term sum_j U_j (lamF+_j - lamF-_j)/2 is summed per tile; a
-// second kernel adds its product with d(|v_d| + c_f,d)/dU at the maximising
-// cell (lowest block, then lowest cell index, on ties).
+// The c_max term sum_j U_j (lamF+_j - lamF-_j)/2 is summed per work-group
+// over its tiles; k_vjp_cmax adds the total's product with d(|v_d| +
+// c_f,d)/dU at the maximising cell (lowest block, then lowest cell index, on
+// ties).  On fixed faces, k_vjp_ghost forms the same split adjoint and flux
+// transpose for the caller's ghost cells, the adjoint of the boundary data.
 #include "device_math.h"
 
 namespace amrvac {

@@ -255,12 +255,6 @@ __device__ __forceinline__ double m4pair(double x, double y) {
   return minmod4(fma(4.0, x, -y), fma(4.0, y, -x), x, y);
 }
 
-// Index (1..4) of the first of (w, x, y, z) equal to the minmod result m,
-// 0 when m is zero: the argument minmod4 returned.
-__device__ __forceinline__ int minmod4_arg(double m, double w, double x, double y) {
-  return m == 0.0 ? 0 : w == m ? 1 : x == m ? 2 : y == m ? 3 : 4;
-}
-
 // Bounds and clamp of MP5 from the stencil centre c, its right neighbour
 // d, the fifth-order value fL, c - b and the two curvature limiters.
 struct Mp5Parts {
@@ -379,13 +373,6 @@ __device__ __forceinline__ double mp5(double a, double b, double c, double d, do
   return r;
 }
 
-__device__ __forceinline__ double mp5_coded(double a, double b, double c, double d, double e, int& code) {
-  const double f[5] = {a, b, c, d, e};
-  double r;
-  mp5_run<1, true>(f, &r, &code);
-  return r;
-}
-
 // ---------------------------------------------------------------------------
 // LIM03 (Cada & Torrilhon 2009): compact third-order reconstruction with the
 // asymptotic-region switch.
@@ -426,10 +413,6 @@ __device__ __forceinline__ double lim03_eval(double a, double b, double c, doubl
 __device__ __forceinline__ double lim03(double a, double b, double c, double kr) {
   int unused;
   return lim03_eval<false>(a, b, c, kr, unused);
-}
-
-__device__ __forceinline__ double lim03_coded(double a, double b, double c, double kr, int& code) {
-  return lim03_eval<true>(a, b, c, kr, code);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,6 +1,7 @@
 // Host runtime behind the C ABI of include/amrvac.h: argument validation,
 // block and tile tables, context-owned scratch, Shu-Osher stage recipes
-// (Sect. 2.3), per-block and batched (persistent, graph-replayed) execution.
+// (Sect. 2.3), per-block and batched (persistent, graph-replayed, one launch
+// per block-size class or one per stage) execution.
 #include "amrvac.h"
 #include "amrvac_internal.h"
 
@@ -141,7 +142,8 @@ static amrvac_status select_variant(amrvac_ctx* c, int i);
 // Build the tile list of the current variant: blocks ordered largest first,
 // then along a Morton curve of their origins; tiles of a block contiguous and
 // Morton-ordered.  The list is cut into launch groups of whole size classes
-// (blocks of equal cell count), one stage launch per group.
+// (blocks of equal cell count), one stage launch per group; the single-launch
+// form keeps every class in one group.
 static amrvac_status build_tiles(amrvac_ctx* c) {
   const StageVariant* V = c->var;
   const int T[3] = {V->tx, V->ty, V->tz};
