@@ -194,9 +194,15 @@ struct SweepShape {
   // pencils along D (the tile's cross-section), LDS row stride made odd
   static constexpr int NP(int D) { return TC / T(D); }
   static constexpr int PSTR(int D) { return NP(D) | 1; }
-  // a sweep item covers SEG consecutive cells of one pencil
-  static constexpr int SEG(int D) { return T(D) < 8 ? T(D) : 8; }
-  static constexpr int NSEG(int D) { return T(D) / SEG(D); }
+  // a sweep item covers SEG consecutive cells of one pencil: at most 8, and
+  // halved (while it divides the pencil and stays >= 2) until the items of
+  // NV variables fill NT threads, so that small-variable-count shapes keep
+  // every thread busy with shorter walks
+  static constexpr int SEG(int D, int NV, int NT) {
+    int seg = T(D) < 8 ? T(D) : 8;
+    while (seg > 2 && seg % 2 == 0 && NP(D) * NV * (T(D) / seg) < NT) seg /= 2;
+    return seg;
+  }
   // mu rows: cells o_D-3 .. o_D+T_D+2; code rows: lower faces of cells
   // o_D-2 .. o_D+T_D+2 (interfaces i+1/2, i = o_D-3 .. o_D+T_D+1)
   static constexpr int MROWS(int D) { return T(D) + 6; }
@@ -366,7 +372,7 @@ __global__ void __launch_bounds__(NT) k_vjp(VjpParams P) {
       constexpr int D = decltype(Dc)::value;
       constexpr int TD = S::T(D), NP = S::NP(D), PS = S::PSTR(D);
       constexpr int MR = S::MROWS(D), CR = S::CROWS(D);
-      constexpr int SEG = S::SEG(D), NSEG = S::NSEG(D);
+      constexpr int SEG = S::SEG(D, NV, NT), NSEG = TD / SEG;
       constexpr int C0 = D == 0 ? CR : TX, C1 = D == 1 ? CR : TY, C2 = D == 2 ? CR : TZ;
       const double c = cin[D];
       const double idx_d = B.inv_dx[D];
