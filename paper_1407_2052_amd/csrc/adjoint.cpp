@@ -27,8 +27,10 @@ namespace {
 struct Adj {
   amrvac_ctx* c;
   const VjpVariant* V;
-  std::vector<Tile> htiles;
+  std::vector<Tile> htiles;           // tiles of the recompute's shape
   Tile* d_tiles = nullptr;
+  std::vector<Tile> hvtiles;          // tiles of the VJP's shape
+  Tile* d_vtiles = nullptr;
   double* d_hist = nullptr;   // c_max of every stage state of a segment, 3 per state
   double* d_cpart = nullptr;
   double** d_ptrs = nullptr;
@@ -44,6 +46,7 @@ struct Adj {
 
   ~Adj() {
     if (d_tiles) (void)hipFree(d_tiles);
+    if (d_vtiles) (void)hipFree(d_vtiles);
     if (d_hist) (void)hipFree(d_hist);
     if (d_cpart) (void)hipFree(d_cpart);
     if (d_ptrs) (void)hipFree(d_ptrs);
@@ -53,6 +56,7 @@ struct Adj {
   }
 
   int ntiles() const { return (int)htiles.size(); }
+  int nvtiles() const { return (int)hvtiles.size(); }
 
   // dst = sum of coefficient * buffer over `terms` (launches of at most 6
   // sources; later launches carry the partial sum in dst).
@@ -63,8 +67,8 @@ struct Adj {
       CombineParams p{};
       p.dst = dst;
       p.st = state_table(c);
-      p.tiles = d_tiles;
-      p.ntiles = ntiles();
+      p.tiles = d_vtiles;
+      p.ntiles = nvtiles();
       p.tx = V->tx;
       p.ty = V->ty;
       p.tz = V->tz;
@@ -93,8 +97,8 @@ struct Adj {
     StateTable st = state_table(c);
     VjpParams p{};
     p.st = st;
-    p.tiles = d_tiles;
-    p.ntiles = ntiles();
+    p.tiles = d_vtiles;
+    p.ntiles = nvtiles();
     p.ctl = c->d_ctl;
     p.gamma = c->cfg.gamma;
     p.in = state;
@@ -192,10 +196,10 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
   adj.V = vjp_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD);
   const StageVariant* EV = emit_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD, c->cfg.recon);
   if (!adj.V || !EV) return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: no kernel for this ndim/physics");
-  if (EV->tx != adj.V->tx || EV->ty != adj.V->ty || EV->tz != adj.V->tz)
-    return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: recompute and adjoint tile shapes differ");
-  {
-    const int T[3] = {adj.V->tx, adj.V->ty, adj.V->tz};
+  // one tile list per shape: the recompute's and the VJP's
+  for (int which = 0; which < 2; ++which) {
+    const int T[3] = {which ? adj.V->tx : EV->tx, which ? adj.V->ty : EV->ty, which ? adj.V->tz : EV->tz};
+    std::vector<Tile>& out = which ? adj.hvtiles : adj.htiles;
     for (int b = 0; b < nb; ++b) {
       const amrvac_block& q = c->hb[b];
       int nt[3];
@@ -208,7 +212,7 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
             t.o[0] = x * T[0];
             t.o[1] = y * T[1];
             t.o[2] = z * T[2];
-            adj.htiles.push_back(t);
+            out.push_back(t);
           }
     }
   }
@@ -218,7 +222,9 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
     return ctx_fail(c, e == hipErrorOutOfMemory ? AMRVAC_ERR_NOMEM : AMRVAC_ERR_DEVICE, "%s: %s", what,
                     hipGetErrorString(e));
   };
+  const int nvt = adj.nvtiles();
   if ((st = hip_ok(hipMalloc(&adj.d_tiles, sizeof(Tile) * nt), "hipMalloc")) != AMRVAC_OK) return st;
+  if ((st = hip_ok(hipMalloc(&adj.d_vtiles, sizeof(Tile) * nvt), "hipMalloc")) != AMRVAC_OK) return st;
   if ((st = hip_ok(hipMalloc(&adj.d_hist, sizeof(double) * 3 * (size_t)s * (size_t)k), "hipMalloc")) != AMRVAC_OK)
     return st;
   // the maximiser keys start above every valid key (the VJPs lower them)
@@ -230,7 +236,7 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
       if (c->hb[b].nbr[f] < 0) hfaces.push_back(FixedFace{b, f});
   adj.nfaces = (int)hfaces.size();
   adj.grid_ghost = std::max(1, std::min(adj.nfaces, c->ncu * 4));
-  if ((st = hip_ok(hipMalloc(&adj.d_cpart, sizeof(double) * 3 * ((size_t)nt + adj.grid_ghost)), "hipMalloc")) !=
+  if ((st = hip_ok(hipMalloc(&adj.d_cpart, sizeof(double) * 3 * ((size_t)nvt + adj.grid_ghost)), "hipMalloc")) !=
       AMRVAC_OK)
     return st;
   if (adj.nfaces > 0) {
@@ -244,6 +250,9 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
   }
   if ((st = hip_ok(hipMalloc(&adj.d_ptrs, sizeof(double*) * nb), "hipMalloc")) != AMRVAC_OK) return st;
   if ((st = hip_ok(hipMemcpyAsync(adj.d_tiles, adj.htiles.data(), sizeof(Tile) * nt, hipMemcpyHostToDevice,
+                                  c->stream), "upload")) != AMRVAC_OK)
+    return st;
+  if ((st = hip_ok(hipMemcpyAsync(adj.d_vtiles, adj.hvtiles.data(), sizeof(Tile) * nvt, hipMemcpyHostToDevice,
                                   c->stream), "upload")) != AMRVAC_OK)
     return st;
   std::vector<double*> hptrs(lam, lam + nb);
@@ -263,13 +272,13 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
   if ((st = hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj.V->fn, adj.V->nt, 0), "occupancy")) !=
       AMRVAC_OK)
     return st;
-  adj.grid_vjp = std::max(1, std::min(std::max(per_cu, 1) * c->ncu, nt));
+  adj.grid_vjp = std::max(1, std::min(std::max(per_cu, 1) * c->ncu, nvt));
   per_cu = 0;
   if ((st = hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, EV->fn, EV->nt, 0), "occupancy")) !=
       AMRVAC_OK)
     return st;
   adj.grid_emit = std::max(1, std::min(std::max(per_cu, 1) * c->ncu, nt));
-  adj.grid_small = std::max(1, std::min(c->ncu * 8, nt));
+  adj.grid_small = std::max(1, std::min(c->ncu * 8, nvt));
 
   double alpha[6][6], beta[6][6];
   scheme_table(scheme, alpha, beta);
