@@ -26,6 +26,11 @@
 //      interfaces per pencil, into registers, then LDS,
 //   C) accumulates -(Fhat_{i+1/2} - Fhat_{i-1/2}) / dx_d into per-thread
 //      register accumulators of the cells it owns.
+// In the run forms the interface fluxes of B go beside the split fluxes of A
+// in LDS wherever both fit (the array is padded for that while it keeps the
+// resident work-groups per CU), which drops the barrier before they are
+// stored and, when the next direction's split fluxes also stay clear of
+// them, the barrier after C.
 // The stage update reads its sources once per cell and writes the result.
 // The owned-cell (CORE) forms load the tile's own cells once per tile into
 // registers; phase A of each direction then loads only the halo planes of the
@@ -52,6 +57,13 @@ namespace amrvac {
 // ---------------------------------------------------------------------------
 // Fused stage kernel.
 // ---------------------------------------------------------------------------
+// LDS doubles of direction D in a run form with the interface fluxes (and
+// code bytes) beside the split fluxes of the extended box.
+template <class S, int VPG, int XP, bool CODES>
+constexpr int side_by_side(int D) {
+  return 2 * VPG * (D == 0 ? XP * S::T(1) * S::T(2) : S::NEXT(D)) + (VPG + (CODES ? 1 : 0)) * S::NIFC(D);
+}
+
 template <int NDIM, bool MHD, int TX, int TY, int TZ, int NT, int NGRP, int WPE, bool EMIT = false,
           bool RUNS = false, bool LIM = false, bool GLM = false, bool HALL = false, bool CORE = false>
 __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
@@ -76,7 +88,24 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
   constexpr bool CODE_LDS = EMIT && RUNS && NGRP == 1;
   static_assert(!EMIT || CODE_LDS, "the code-emitting forms are run forms with one variable group");
   static_assert(!CODE_LDS || NV <= 8, "8 code bytes per interface");
-  constexpr int LDS_N = cmax_i<2 * VPG * EXT, VPG * IFC + (CODE_LDS ? IFC : 0)>::v;
+  constexpr int LDS_BASE = cmax_i<2 * VPG * EXT, VPG * IFC + (CODE_LDS ? IFC : 0)>::v;
+  // Run forms: the interface fluxes (and codes) of a direction go to the top
+  // of the array when they fit beside that direction's split fluxes; then the
+  // barrier between the reconstructions and their store is not needed, nor
+  // the one after phase C when the next split fluxes stay clear of them too.
+  // The array grows to fit every direction that can be placed so without
+  // fewer resident work-groups per CU (160 KB of LDS per CU) than the launch
+  // bounds aim at and the unpadded array allows.
+  constexpr int WG_BASE = 20480 / LDS_BASE;
+  constexpr int WG_AIM = cmax_i<WPE * 4 / (NT / 64), 1>::v;
+  constexpr int LDS_LIMIT = 20480 / (WG_BASE < WG_AIM ? WG_BASE : WG_AIM);
+  constexpr int SB0 = side_by_side<S, VPG, XP, CODE_LDS>(0);
+  constexpr int SB1 = NDIM >= 2 ? side_by_side<S, VPG, XP, CODE_LDS>(1) : 0;
+  constexpr int SB2 = NDIM >= 3 ? side_by_side<S, VPG, XP, CODE_LDS>(2) : 0;
+  constexpr int PAD = !(RUNS && NGRP == 1) ? 0
+                      : cmax_i<cmax_i<SB0 <= LDS_LIMIT ? SB0 : 0, SB1 <= LDS_LIMIT ? SB1 : 0>::v,
+                               SB2 <= LDS_LIMIT ? SB2 : 0>::v;
+  constexpr int LDS_N = cmax_i<LDS_BASE, PAD>::v;
   __shared__ double lds[LDS_N];
   // the closing c_max reduction reuses the start of lds: every wave has
   // passed the barrier that ends the last phase C before any writes it
@@ -162,6 +191,16 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
       constexpr int IPT = (NITEM + NT - 1) / NT;
       constexpr int I0 = S::I(D, 0), I1 = S::I(D, 1);
       constexpr int SD = (D == 0) ? 1 : (D == 1) ? E0P : E0P * E1;
+      // interface fluxes at lds[RB ..]: beside the split fluxes (DISJ) or over them
+      constexpr int RES_SPAN = VPG * NIFC_D + (CODE_LDS ? NIFC_D : 0);
+      constexpr bool DISJ = RUNS && NGRP == 1 && 2 * VPG * NEXTP + RES_SPAN <= LDS_N;
+      constexpr int RB = DISJ ? LDS_N - RES_SPAN : 0;
+      // what is written to LDS after phase C: the next direction's split
+      // fluxes, or the next tile's first ones and the closing reduction
+      constexpr int DN = D + 1 < NDIM ? D + 1 : 0;
+      constexpr int NEXT_SPAN = cmax_i<2 * VPG * (DN == 0 ? XP : S::E(DN, 0)) * S::E(DN, 1) * S::E(DN, 2),
+                                       3 * (NT / 64)>::v;
+      constexpr bool SKIP_C_BARRIER = DISJ && NEXT_SPAN <= RB;
       const double c = cin[D];
       const double idx_d = B.inv_dx[D];
       // LIM03's asymptotic-region scale 1 / (r dx_d)^2
@@ -357,7 +396,7 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
               for (int kk = 0; kk < RUN; ++kk) cbyte[r][kk] = (unsigned char)(cp[kk] | (cm[RUN - 1 - kk] << 4));
             }
           }
-          __syncthreads();
+          if constexpr (!DISJ) __syncthreads();
 #pragma unroll
           for (int r = 0; r < IPR; ++r) {
             const int w = tid + r * NT;
@@ -373,10 +412,10 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
             const int q0 = a[0] + I0 * (a[1] + I1 * a[2]);
             constexpr int SI = S::SI(D);
 #pragma unroll
-            for (int kk = 0; kk < RUN; ++kk) lds[vg * NIFC_D + q0 + kk * SI] = res[r][kk];
+            for (int kk = 0; kk < RUN; ++kk) lds[RB + vg * NIFC_D + q0 + kk * SI] = res[r][kk];
             if constexpr (CODE_LDS) {
               if ((G * VPG + vg) < NV) {
-                unsigned char* lc = reinterpret_cast<unsigned char*>(lds + VPG * NIFC_D);
+                unsigned char* lc = reinterpret_cast<unsigned char*>(lds + RB + VPG * NIFC_D);
 #pragma unroll
                 for (int kk = 0; kk < RUN; ++kk) lc[(q0 + kk * SI) * 8 + vg] = cbyte[r][kk];
               }
@@ -386,7 +425,7 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
           if constexpr (CODE_LDS) {
             // one 8-byte word per owned cell: the codes of the interface on
             // its lower face (unused bytes of a hydro word stay unspecified)
-            const unsigned long long* lc = reinterpret_cast<const unsigned long long*>(lds + VPG * NIFC_D);
+            const unsigned long long* lc = reinterpret_cast<const unsigned long long*>(lds + RB + VPG * NIFC_D);
 #pragma unroll
             for (int r = 0; r < CPT; ++r) {
               const int cidx = tid + r * NT;
@@ -470,14 +509,14 @@ __global__ void __launch_bounds__(NT, WPE) k_stage(StageParams P) {
               for (int vg = 0; vg < VPG; ++vg) {
                 const int v = G * VPG + vg;
                 if (v < NV) {
-                  const double diff = lds[vg * NIFC_D + il + SI] - lds[vg * NIFC_D + il];
+                  const double diff = lds[RB + vg * NIFC_D + il + SI] - lds[RB + vg * NIFC_D + il];
                   L[r][v] = fma(-diff, idx_d, L[r][v]);
                 }
               }
             }
           }
         }
-        __syncthreads();
+        if constexpr (!SKIP_C_BARRIER) __syncthreads();
       });
     });
 
