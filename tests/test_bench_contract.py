@@ -41,16 +41,16 @@ def test_traffic_is_reported_for_recorded_shapes_of_the_current_code():
     rec = record()
     if rec["kernel_source_hash"] != bench.kernel_source_hash():
         pytest.skip("the traffic record predates the current kernel code")
-    assert bench.measured_traffic(rec["variant"]) == rec["bytes_per_stage"]
-    for name, v in rec.get("variants", {}).items():
-        assert bench.measured_traffic(name) == v["bytes_per_stage"]
-    assert bench.measured_traffic("no-such-tile-shape") is None
+    assert bench.measured_traffic(rec["variant"], rec["form"]) == rec["bytes_per_stage"]
+    other = "single" if rec["form"] == "per_class" else "per_class"
+    assert bench.measured_traffic(rec["variant"], other) is None
+    assert bench.measured_traffic("no-such-tile-shape", rec["form"]) is None
 
 
 def test_traffic_is_withheld_when_the_code_changes(monkeypatch):
     rec = record()
     monkeypatch.setattr(bench, "kernel_source_hash", lambda read=None: "0" * 16)
-    assert bench.measured_traffic(rec["variant"]) is None
+    assert bench.measured_traffic(rec["variant"], rec["form"]) is None
 
 
 def test_record_is_calibrated_and_consistent():
@@ -58,11 +58,14 @@ def test_record_is_calibrated_and_consistent():
     kib = 1024.0
     assert rec["copy_probe"]["bytes"] / kib / rec["copy_probe"]["fetch_size_kib"] == pytest.approx(rec["read_factor"])
     assert rec["copy_probe"]["bytes"] / kib / rec["copy_probe"]["write_size_kib"] == pytest.approx(rec["write_factor"])
-    # a stage is launches_per_stage dispatches (one per block-size class)
+    # a stage is launches_per_stage dispatches: one per block-size class, or one
+    assert rec["launches_per_stage"] == {"per_class": 3, "single": 1}[rec["form"]]
     total = rec["launches_per_stage"] * (rec["fetch_size_kib_per_dispatch"] * kib * rec["read_factor"]
                                          + rec["write_size_kib_per_dispatch"] * kib * rec["write_factor"])
     assert total == pytest.approx(rec["bytes_per_stage"], rel=1e-6)
     # algorithmic bytes: 17 state passes x 8 variables x 8 bytes per cell and step, over 5 stages
     assert rec["algorithmic_bytes_per_stage"] == pytest.approx(
         bench.BYTES_PER_CELL_STEP_MHD3D / bench.STAGES * 25160192)
-    assert rec["variants"][rec["variant"]]["bytes_per_stage"] == pytest.approx(rec["bytes_per_stage"])
+    # every shape in the per-class autotuning pass of the same run
+    for v in rec["variants"].values():
+        assert v["bytes_per_stage"] > rec["algorithmic_bytes_per_stage"]
