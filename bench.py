@@ -417,8 +417,9 @@ def main():
                     help="also run one plain device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs (--gpus > 1) are not "
-              "supported (the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py: the library runs on one GPU; multi-GPU runs (--gpus > 1) are not supported "
+              "(blocks would be split into Morton ranges per GPU with face-halo exchange and a "
+              "max all-reduce of c_max per stage, which is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
