@@ -76,7 +76,9 @@ def measured_traffic(variant, form):
     """HBM bytes per stage (the stage's launches together) from committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs (calibrated against a plain copy),
     if they were taken on the current kernel source, on the tile shape and in
-    the launch form ("per_class" or "single") that is being timed."""
+    the launch form ("per_class" or "single") that is being timed.  The record
+    holds the timed pair of its run and, for the per-class form, every tile
+    shape (the autotuner runs each of them per class in the same program)."""
     path = os.path.join(ROOT, "profiles", "stage_kernel_mhd3d_uneven4096_traffic.json")
     if not os.path.exists(path):
         return None
@@ -86,6 +88,8 @@ def measured_traffic(variant, form):
         return None
     if rec.get("variant") == variant and rec.get("form") == form:
         return rec.get("bytes_per_stage")
+    if form == "per_class":   # every shape, from the autotuner's per-class pass of the same run
+        return rec.get("variants", {}).get(variant, {}).get("bytes_per_stage")
     return None
 
 

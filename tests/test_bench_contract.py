@@ -42,8 +42,11 @@ def test_traffic_is_reported_for_recorded_shapes_of_the_current_code():
     if rec["kernel_source_hash"] != bench.kernel_source_hash():
         pytest.skip("the traffic record predates the current kernel code")
     assert bench.measured_traffic(rec["variant"], rec["form"]) == rec["bytes_per_stage"]
-    other = "single" if rec["form"] == "per_class" else "per_class"
-    assert bench.measured_traffic(rec["variant"], other) is None
+    for name, v in rec["variants"].items():   # the per-class pass covers every shape
+        assert bench.measured_traffic(name, "per_class") == v["bytes_per_stage"]
+    if rec["form"] == "single":
+        others = [n for n in rec["variants"] if n != rec["variant"]]
+        assert all(bench.measured_traffic(n, "single") is None for n in others)
     assert bench.measured_traffic("no-such-tile-shape", rec["form"]) is None
 
 
