@@ -6,9 +6,10 @@ Workload: 3D ideal MHD, 4096 independent blocks of 32^3 : 16^3 : 8^3 cells
 
 A step is one full SSPRK(5,4) step over every block (5 fused stage launches
 plus the on-device dt computation), inputs resident in HBM.  The headline
-value is the batched form (one persistent launch per stage, replayed from a
-HIP graph); the plain per-block launch on the same block list is timed beside
-it.  One JSON line is printed.
+value is the faster batched form (persistent launches, one per stage or one
+per block-size class and stage, after autotuning both; steps replayed from HIP
+graphs); the plain per-block launch on the same block list is timed beside it.
+One JSON line is printed.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 2]
 """
@@ -639,9 +640,9 @@ def main():
         "config": {"workload": "3D ideal MHD, 4096 uneven blocks 32^3:16^3:8^3 (1:2:4), fixed ghosts "
                                "from a seeded 8-mode field, SSPRK(5,4)+MP5+global LF, CFL 0.4",
                    "blocks": bs.nb, "cells": cells,
-                   "exec": ("batched persistent, one launch per block-size class and stage, HIP graph per step"
+                   "exec": ("batched persistent, one launch per block-size class and stage, steps replayed from HIP graphs"
                             if form == "per_class" else
-                            "batched persistent, one launch per stage over the whole list, HIP graph per step")
+                            "batched persistent, one launch per stage over the whole list, steps replayed from HIP graphs")
                            + " (the faster autotuned batched form)",
                    "tile_shape": variant,
                    "parallelism": "single GPU"},

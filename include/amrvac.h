@@ -89,10 +89,11 @@ typedef enum { AMRVAC_RK3 = 0, AMRVAC_SSPRK43 = 1, AMRVAC_SSPRK54 = 2 } amrvac_s
  *  BATCHED:         persistent fused launches over the block list, one per
  *                   block-size class (blocks of equal cell count; a class
  *                   with fewer tiles than twice the resident work-groups
- *                   joins the next), the step replayed from a HIP graph;
+ *                   joins the next), steps replayed from HIP graphs (of 8
+ *                   steps, and of one step for the remainder of a call);
  *  BATCHED_SINGLE:  one persistent fused launch per stage over the whole
  *                   list (each XCD's share holds an eighth of every class),
- *                   the step replayed from a HIP graph.
+ *                   steps replayed from HIP graphs as for BATCHED.
  * Setting a batched form rebuilds the work list; the autotuner times tile
  * shapes in the form that is set. */
 typedef enum { AMRVAC_EXEC_PER_BLOCK = 0, AMRVAC_EXEC_BATCHED = 1, AMRVAC_EXEC_BATCHED_SINGLE = 2 } amrvac_exec;

@@ -178,6 +178,30 @@ def test_execution_forms_are_bitwise_identical(case):
         assert np.array_equal(x, y) and np.array_equal(x, z)
 
 
+@pytest.mark.parametrize("case", ["ot2d", "uneven3d"])
+def test_multi_step_graph_replays_equal_eager_launches(case):
+    """Calls long enough to replay the multi-step graph (8 steps per graph,
+    the remainder on the one-step graph), several in a row with eager work
+    and synchronisations between them, against the per-block form (kernels
+    launched one by one, no graph) on the same call pattern: bitwise equal
+    after every call."""
+    import torch
+    say(f"[graphs] {case}: calls of 21, 8, 3 and 16 steps")
+    bs = CASES[case]()
+    ctxs = [A.context_for(bs, e) for e in (A.EXEC_BATCHED, A.EXEC_PER_BLOCK)]
+    try:
+        for n in (21, 8, 3, 16):
+            ts = [ctx.ssprk_step(oracle.SSPRK54, n, cfl=0.4, t=0.0) for ctx, _, _ in ctxs]
+            scratch = torch.ones(1 << 16, dtype=torch.float64, device="cuda").cumsum(0)   # eager work between
+            torch.cuda.synchronize()
+            del scratch
+            assert ts[0] == ts[1]
+            assert torch.equal(ctxs[0][1], ctxs[1][1])
+    finally:
+        for ctx, _, _ in ctxs:
+            ctx.close()
+
+
 def test_runs_are_bitwise_deterministic():
     bs = CASES["mhd3d"]()
     say("[determinism] mhd3d")
