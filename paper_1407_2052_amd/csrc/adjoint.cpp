@@ -43,8 +43,12 @@ struct Adj {
   int grid_vjp = 0;
   int grid_emit = 0;
   int grid_small = 0;
+  // overlapped recompute: the context's second stream and its events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fwd = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
 
   ~Adj() {
+    if (side) (void)hipStreamSynchronize(side);
     if (d_tiles) (void)hipFree(d_tiles);
     if (d_vtiles) (void)hipFree(d_vtiles);
     if (d_hist) (void)hipFree(d_hist);
@@ -161,14 +165,49 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
   const int N = nsteps;
   const int k = std::max(1, std::min(ckpt_every, std::max(N, 1)));
   const int M = (N + k - 1) / k;   // segments
+  const VjpVariant* VV = vjp_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD);
+  const StageVariant* EV = emit_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD, c->cfg.recon);
+  if (!VV || !EV) return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: no kernel for this ndim/physics");
+  // Lists whose recompute and VJP launches hold at most two work-groups per
+  // CU leave most of the GPU idle in each launch: there the next segment is
+  // recomputed on a second stream (into a second set of stage states and
+  // codes) while this one is reversed.  AMRVAC_ADJOINT_OVERLAP=0/1 overrides.
+  bool overlap = false;
+  {
+    long long tv = 0, te = 0;
+    for (int b = 0; b < nb; ++b) {
+      long long a = 1, e = 1;
+      const int TV[3] = {VV->tx, VV->ty, VV->tz}, TE[3] = {EV->tx, EV->ty, EV->tz};
+      for (int d = 0; d < 3; ++d) {
+        a *= (c->hb[b].n[d] + TV[d] - 1) / TV[d];
+        e *= (c->hb[b].n[d] + TE[d] - 1) / TE[d];
+      }
+      tv += a;
+      te += e;
+    }
+    overlap = M > 1 && tv <= 2LL * c->ncu && te <= 2LL * c->ncu;
+    const char* env = std::getenv("AMRVAC_ADJOINT_OVERLAP");
+    if (env && *env) overlap = M > 1 && env[0] == '1';
+  }
+  const int sets = overlap ? 2 : 1;
   // buffer ids (scratch slot = id - 1)
-  const int A = 1, Bf = 2, S = 3, W0 = 4, W1 = 5;
+  const int A = 1, Bf = 2, W1 = 5;
+  int Sset[2] = {3, 0}, W0set[2] = {4, 0};
   int next = 6;
   std::vector<int> ck(std::max(M, 1), 0);   // ck[0] = caller's U0 (id 0)
   for (int m = 1; m < M; ++m) ck[m] = next++;
-  std::vector<std::vector<int>> X(k, std::vector<int>(s, 0));
-  for (int j = 0; j < k; ++j)
-    for (int i = 0; i < s; ++i) X[j][i] = next++;
+  // stage states of a segment, per set: X[set][j][i] (X[set][j][0] of j = 0
+  // is the segment's checkpoint)
+  std::vector<std::vector<std::vector<int>>> X(sets, std::vector<std::vector<int>>(k, std::vector<int>(s, 0)));
+  for (int set = 0; set < sets; ++set) {
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i < s; ++i) X[set][j][i] = next++;
+    if (set > 0) {
+      Sset[set] = next++;
+      W0set[set] = next++;
+    }
+  }
+  const int S = Sset[0], W0 = W0set[0];
   std::vector<int> Lm(s + 1);
   for (int i = 0; i <= s; ++i) Lm[i] = next++;
   // memory: state slots (the context keeps them for later calls) and the
@@ -180,7 +219,7 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
     for (int d = 0; d < 3; ++d) fw = std::max(fw, c->face_words[d]);
     const double slot_bytes = 8.0 * (double)c->slot_stride;
     const double grow = next - 1 > c->nslots ? slot_bytes * (double)(next - 1 - c->nslots) : 0.0;
-    const double codes = 8.0 * (double)(c->total_cells + fw) * c->cfg.ndim * s * (double)k;
+    const double codes = 8.0 * (double)(c->total_cells + fw) * c->cfg.ndim * s * (double)k * sets;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && grow + codes > 0.97 * (double)free_b)
       return ctx_fail(c, AMRVAC_ERR_NOMEM,
@@ -193,9 +232,7 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
 
   Adj adj;
   adj.c = c;
-  adj.V = vjp_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD);
-  const StageVariant* EV = emit_variant(c->cfg.ndim, c->cfg.physics == AMRVAC_MHD, c->cfg.recon);
-  if (!adj.V || !EV) return ctx_fail(c, AMRVAC_ERR_UNSUPPORTED, "ssprk_adjoint: no kernel for this ndim/physics");
+  adj.V = VV;
   // one tile list per shape: the recompute's and the VJP's
   for (int which = 0; which < 2; ++which) {
     const int T[3] = {which ? adj.V->tx : EV->tx, which ? adj.V->ty : EV->ty, which ? adj.V->tz : EV->tz};
@@ -225,7 +262,8 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
   const int nvt = adj.nvtiles();
   if ((st = hip_ok(hipMalloc(&adj.d_tiles, sizeof(Tile) * nt), "hipMalloc")) != AMRVAC_OK) return st;
   if ((st = hip_ok(hipMalloc(&adj.d_vtiles, sizeof(Tile) * nvt), "hipMalloc")) != AMRVAC_OK) return st;
-  if ((st = hip_ok(hipMalloc(&adj.d_hist, sizeof(double) * 3 * (size_t)s * (size_t)k), "hipMalloc")) != AMRVAC_OK)
+  if ((st = hip_ok(hipMalloc(&adj.d_hist, sizeof(double) * 3 * (size_t)s * (size_t)k * sets), "hipMalloc")) !=
+      AMRVAC_OK)
     return st;
   // the maximiser keys start above every valid key (the VJPs lower them)
   if ((st = hip_ok(hipMemsetAsync(c->d_ctl->arg, 0x7f, sizeof(c->d_ctl->arg), c->stream), "memset")) != AMRVAC_OK)
@@ -263,11 +301,25 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
   long long fw = 0;
   for (int d = 0; d < 3; ++d) fw = std::max(fw, c->face_words[d]);
   adj.code_plane = (c->total_cells + fw) * 8;
-  const size_t code_bytes = (size_t)adj.code_plane * (size_t)c->cfg.ndim * (size_t)s * (size_t)k;
+  const size_t code_bytes = (size_t)adj.code_plane * (size_t)c->cfg.ndim * (size_t)s * (size_t)k * sets;
   if ((st = hip_ok(hipMalloc(&adj.d_codes, code_bytes), "hipMalloc (MP5 piece codes)")) != AMRVAC_OK) return st;
-  auto codes_of = [&](int j, int kst) {
-    return adj.d_codes + ((size_t)j * s + kst) * (size_t)c->cfg.ndim * (size_t)adj.code_plane;
+  auto codes_of = [&](int set, int j, int kst) {
+    return adj.d_codes + (((size_t)set * k + j) * s + kst) * (size_t)c->cfg.ndim * (size_t)adj.code_plane;
   };
+  auto hist_of = [&](int set, int j, int kst) { return adj.d_hist + 3 * (((size_t)set * k + j) * s + kst); };
+  if (overlap) {
+    if (!c->adj_side &&
+        (st = hip_ok(hipStreamCreateWithFlags(&c->adj_side, hipStreamNonBlocking), "stream")) != AMRVAC_OK)
+      return st;
+    for (hipEvent_t& e : c->adj_ev)
+      if (!e && (st = hip_ok(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event")) != AMRVAC_OK) return st;
+    adj.side = c->adj_side;
+    adj.ev_fwd = c->adj_ev[0];
+    adj.ev_rec[0] = c->adj_ev[1];
+    adj.ev_rec[1] = c->adj_ev[2];
+    adj.ev_rev[0] = c->adj_ev[3];
+    adj.ev_rev[1] = c->adj_ev[4];
+  }
   int per_cu = 0;
   if ((st = hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj.V->fn, adj.V->nt, 0), "occupancy")) !=
       AMRVAC_OK)
@@ -306,29 +358,32 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
   int R = Lm[s];   // running adjoint of the current output state
   launch_lam_import(state_table(c), adj.d_ptrs, c->nvar, R, nb, c->stream);
   std::vector<int> lslots(Lm.begin(), Lm.end());
-  for (int m = M - 1; m >= 0; --m) {
-    const int n0 = m * k;
-    const int kk = std::min(k, N - n0);
-    // recompute the segment, storing every stage state
-    X[0][0] = ck[m];
-    launch_cmax_of(c, X[0][0], 0, c->stream);
+  // recompute segment m into stage-state set `set`, storing every stage state
+  auto recompute = [&](int m, int set, hipStream_t strm) {
+    const int kk = std::min(k, N - m * k);
+    std::vector<std::vector<int>>& XX = X[set];
+    XX[0][0] = ck[m];
+    launch_cmax_of(c, XX[0][0], 0, strm);
     for (int j = 0; j < kk; ++j) {
       int outs[6];
-      for (int i = 1; i < s; ++i) outs[i] = X[j][i];
-      outs[s] = (j + 1 < kk) ? X[j + 1][0] : W0;   // the segment's last output is not needed
+      for (int i = 1; i < s; ++i) outs[i] = XX[j][i];
+      outs[s] = (j + 1 < kk) ? XX[j + 1][0] : W0set[set];   // the segment's last output is not needed
       EmitPlan plan{};
       plan.var = EV;
       plan.tiles = adj.d_tiles;
       plan.ntiles = nt;
       plan.grid = adj.grid_emit;
       for (int i = 0; i < s; ++i) {
-        plan.codes[i] = codes_of(j, i);
-        plan.cm_hist[i] = adj.d_hist + 3 * ((size_t)j * s + i);
+        plan.codes[i] = codes_of(set, j, i);
+        plan.cm_hist[i] = hist_of(set, j, i);
       }
       plan.code_plane = adj.code_plane;
-      enqueue_step_outs(c, scheme, exec, c->stream, X[j][0], outs, S, &plan);
+      enqueue_step_outs(c, scheme, exec, strm, XX[j][0], outs, Sset[set], &plan);
     }
-    // reverse the segment's steps
+  };
+  // reverse segment m's steps from stage-state set `set` (context stream)
+  auto reverse = [&](int m, int set) {
+    const int kk = std::min(k, N - m * k);
     for (int j = kk - 1; j >= 0; --j) {
       // lam(s) = R; lam(i) for i < s are the other slots
       std::vector<int> L(s + 1);
@@ -348,10 +403,40 @@ extern "C" amrvac_status amrvac_ssprk_adjoint(amrvac_ctx* c, int scheme, double 
         if (mu_t.empty())
           adj.combine(L[kst], lam_t);
         else
-          adj.vjp(X[j][kst], codes_of(j, kst), adj.d_hist + 3 * ((size_t)j * s + kst), mu_t, lam_t, L[kst], dt);
+          adj.vjp(X[set][j][kst], codes_of(set, j, kst), hist_of(set, j, kst), mu_t, lam_t, L[kst], dt);
       }
       R = L[0];
     }
+  };
+  if (!overlap) {
+    for (int m = M - 1; m >= 0; --m) {
+      recompute(m, 0, c->stream);
+      reverse(m, 0);
+    }
+  } else {
+    // the second stream starts after the forward pass; segment m uses set
+    // m % 2, whose previous user (segment m + 2) must be reversed first
+    hipError_t err = hipSuccess;
+    auto ok = [&](hipError_t e) {
+      if (e != hipSuccess && err == hipSuccess) err = e;
+      return err == hipSuccess;
+    };
+    if (ok(hipEventRecord(adj.ev_fwd, c->stream)) && ok(hipStreamWaitEvent(adj.side, adj.ev_fwd, 0))) {
+      recompute(M - 1, (M - 1) % 2, adj.side);
+      ok(hipEventRecord(adj.ev_rec[(M - 1) % 2], adj.side));
+    }
+    for (int m = M - 1; m >= 0 && err == hipSuccess; --m) {
+      const int set = m % 2;
+      if (!ok(hipStreamWaitEvent(c->stream, adj.ev_rec[set], 0))) break;
+      if (m >= 1) {
+        if (m + 1 <= M - 1 && !ok(hipStreamWaitEvent(adj.side, adj.ev_rev[1 - set], 0))) break;
+        recompute(m - 1, 1 - set, adj.side);
+        if (!ok(hipEventRecord(adj.ev_rec[1 - set], adj.side))) break;
+      }
+      reverse(m, set);
+      ok(hipEventRecord(adj.ev_rev[set], c->stream));
+    }
+    if (err != hipSuccess) return hip_ok(err, "adjoint streams");
   }
   launch_lam_export(state_table(c), adj.d_ptrs, c->nvar, R, nb, adj.d_gadj, c->ghost_cells, c->stream);
   hipError_t e = hipGetLastError();

@@ -1191,6 +1191,12 @@ void amrvac_destroy(amrvac_ctx* c) {
   free_tables(c);
   if (c->d_ctl) (void)hipFree(c->d_ctl);
   if (c->cap) (void)hipStreamDestroy(c->cap);
+  if (c->adj_side) {
+    (void)hipStreamSynchronize(c->adj_side);
+    (void)hipStreamDestroy(c->adj_side);
+  }
+  for (hipEvent_t e : c->adj_ev)
+    if (e) (void)hipEventDestroy(e);
   delete c;
 }
 

@@ -50,6 +50,10 @@ struct amrvac_ctx {
   int exec = AMRVAC_EXEC_BATCHED;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
+  // the adjoint's second stream (recompute beside the reverse sweep) and its
+  // events, created on first use
+  hipStream_t adj_side = nullptr;
+  hipEvent_t adj_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int device = 0;
   int ncu = 0;
   std::string err;

@@ -131,6 +131,28 @@ def test_checkpoint_interval_changes_nothing_bitwise():
             assert np.array_equal(x, y), k
 
 
+@pytest.mark.parametrize("case", ["mhd2d", "hydro3d", "sod_fixed"])
+def test_overlapped_recompute_equals_the_sequential_one(case, monkeypatch):
+    """The next segment recomputed on a second stream while this one is
+    reversed (forced on) against one stream (forced off): bitwise equal,
+    over several segments, fixed faces included."""
+    say(f"[adjoint overlap] {case}")
+    if case == "mhd2d":
+        bs, scheme, nsteps, ckpt = periodic_state(2, True, 32, 16, seed=3), oracle.SSPRK54, 7, 2
+    elif case == "hydro3d":
+        bs, scheme, nsteps, ckpt = periodic_state(3, False, 16, 8, seed=4), oracle.RK3, 5, 1
+    else:
+        bs, scheme, nsteps, ckpt = sod_like(), oracle.SSPRK54, 6, 2
+    dt = fixed_dt(bs)
+    lam_n = random_cotangent(bs, 7)
+    out = {}
+    for flag in ("0", "1"):
+        monkeypatch.setenv("AMRVAC_ADJOINT_OVERLAP", flag)
+        out[flag] = gpu_adjoint(bs, scheme, dt, nsteps, ckpt, lam_n)
+    for x, y in zip(out["0"], out["1"]):
+        assert np.array_equal(x, y)
+
+
 def test_zero_steps_is_identity():
     """lam_0 = lam_N on the interiors, ghost entries set to 0 (non-zero on
     entry here), for Euler and MHD."""
