@@ -278,8 +278,13 @@ amrvac_status amrvac_ssprk_step_noalloc(amrvac_ctx *ctx, int scheme, double cfl,
  * maximising cell, lowest block then lowest cell index on ties); MP5,
  * LIM03, minmod and median are differentiated along the branch taken by the
  * forward pass.  Checkpoints of U are kept every ckpt_every steps and the
- * steps in between are recomputed.  Requires n[d] >= 5 for every block and
- * every face neighbour.  Synchronises the stream and reports device errors.
+ * steps in between are recomputed, segment by segment; on lists of at most
+ * 2 x 256 tiles the next segment is recomputed on a second stream of the
+ * context while the current one is reversed (twice the segment's stage
+ * states and codes; environment variable AMRVAC_ADJOINT_OVERLAP=0/1 forces
+ * it off or on; the result is the same bit for bit).  The context keeps the
+ * state slots for later calls.  Requires n[d] >= 5 for every block and every
+ * face neighbour.  Synchronises the stream and reports device errors.
  * Errors: INVALID (no blocks, null lam or entry, nsteps < 0, ckpt_every < 1,
  * dt not > 0 and finite, scheme unknown), UNSUPPORTED (n[d] < 5, GLM, Hall
  * MHD, passive blocks), NONPHYSICAL, NOMEM, DEVICE. */
