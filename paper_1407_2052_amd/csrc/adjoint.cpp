@@ -12,7 +12,9 @@
 // Memory: checkpoints of U every ckpt_every steps; a segment is recomputed
 // from its checkpoint with every stage state stored, together with the MP5
 // linear-piece codes of L at each of them (8 bytes per cell and direction),
-// then reversed.
+// then reversed.  On small lists (launches of at most two work-groups per
+// CU) the next segment is recomputed on a second stream, into a second set
+// of stage states and codes, while the current one is reversed.
 #include "runtime_internal.h"
 
 #include <algorithm>
