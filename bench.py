@@ -94,6 +94,21 @@ def measured_traffic(variant, form):
     return None
 
 
+def measured_traffic_other(leg, variant):
+    """HBM bytes per stage of another workload's forward (`leg`: a key of
+    FORWARD_LEGS) on tile shape `variant`, from the same committed record:
+    every shape of that list's autotuning pass, profiled in a run of its own
+    (`bench.py --forward-leg LEG`), if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "stage_kernel_mhd3d_uneven4096_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("others", {}).get(leg, {}).get("variants", {}).get(variant, {}).get("bytes_per_stage")
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -331,6 +346,39 @@ def forward_mhd2d(nsteps, warmup):
             "cell_updates_per_s": cells * nsteps / el, "cells": cells}
 
 
+FORWARD_LEGS = {
+    "mhd3d_periodic256": "3D ideal MHD 256^3 periodic, 4096 x 16^3",
+    "euler2d_256": "2D Euler 256^2 periodic, 256 x 16^2",
+    "mhd2d_512": "2D ideal MHD, smooth Orszag-Tang data, 512^2 periodic, 1024 x 16^2",
+}
+
+
+def forward_leg(leg, nsteps, warmup):
+    """Only the SSPRK(5,4) + MP5 forward of one of the other lists (autotuned,
+    batched), for profiling that list's stage kernel in a run of its own."""
+    import torch
+    from paper_1407_2052_amd import amrvac, inputs
+    bs = {"mhd3d_periodic256": inputs.mhd_turbulence_3d, "euler2d_256": inputs.hydro_random_2d,
+          "mhd2d_512": lambda: inputs.orszag_tang_2d(512, 16)}[leg]()
+    cells = bs.interior_cells()
+    ctx, flat, views = amrvac.context_for(bs, amrvac.EXEC_BATCHED)
+    var, _ = ctx.autotune(amrvac.SSPRK54, 2)
+    stream = torch.cuda.current_stream()
+    ctx.ssprk_step(amrvac.SSPRK54, warmup, cfl=0.4, t=None)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.ssprk_step(amrvac.SSPRK54, nsteps, cfl=0.4, t=None)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ctx.sync()
+    el = e0.elapsed_time(e1) / 1e3
+    ctx.close()
+    return {"leg": leg, "workload": FORWARD_LEGS[leg], "tile_shape": var, "steps": nsteps,
+            "ms_per_step": 1e3 * el / nsteps, "cell_updates_per_s": cells * nsteps / el, "cells": cells}
+
+
 def stage_roofline(key, cells, stage_s, bytes_per_cell_step):
     """FP64 VALU roofline of one fused stage launch: the oracle-counted
     operations per cell (median form) x cells / the launch time, against
@@ -418,6 +466,9 @@ def main():
     ap.add_argument("--class-sweep", action="store_true",
                     help="also run the autotuner on each block-size class of the uneven list on its own "
                          "(per-class tile-shape times on stderr)")
+    ap.add_argument("--forward-leg", choices=sorted(FORWARD_LEGS),
+                    help="run only the forward of this other list (autotune, warm-up, timed steps), for "
+                         "profiling its stage kernel in a run of its own; prints one JSON line")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run one plain device-to-device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -429,6 +480,19 @@ def main():
 
     import torch
     from paper_1407_2052_amd import amrvac, inputs
+
+    if args.forward_leg:
+        torch.cuda.set_device(0)
+        out = forward_leg(args.forward_leg, args.steps, args.warmup)
+        if args.copy_probe > 0:
+            a = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
+            b = torch.empty_like(a)
+            torch.cuda.synchronize()
+            b.copy_(a)
+            torch.cuda.synchronize()
+            del a, b
+        print(json.dumps(out), flush=True)
+        return
 
     print("bench: generating 3D MHD uneven block list (4096 blocks)", file=sys.stderr, flush=True)
     bs = inputs.uneven_3d()
@@ -616,16 +680,20 @@ def main():
         others["mhd3d_periodic256_forward"] = stage_roofline(
             "mhd3d_periodic256", 16 ** 3 * 4096, 16 ** 3 * 4096 / c5 / STAGES, BYTES_PER_CELL_STEP_MHD3D)
         others["mhd3d_periodic256_forward"]["kernel"] = f"k_stage<3,MHD>, {adjoint['forward_tile_shape']}"
+        others["mhd3d_periodic256_forward"]["traffic"] = measured_traffic_other(
+            "mhd3d_periodic256", adjoint["forward_tile_shape"])
     if adjoint_2d:
         c4 = adjoint_2d["forward_cell_updates_per_s"]
         others["euler2d_256_forward"] = stage_roofline(
             "euler2d_256", 256 * 256, 256 * 256 / c4 / STAGES, BYTES_PER_CELL_STEP_EULER2D)
         others["euler2d_256_forward"]["kernel"] = f"k_stage<2,HD>, {adjoint_2d['forward_tile_shape']}"
+        others["euler2d_256_forward"]["traffic"] = measured_traffic_other("euler2d_256", adjoint_2d["forward_tile_shape"])
     if mhd2d:
         others["mhd2d_512_forward"] = stage_roofline(
             "mhd2d_512", mhd2d["cells"], mhd2d["cells"] / mhd2d["cell_updates_per_s"] / STAGES,
             BYTES_PER_CELL_STEP_MHD3D)
         others["mhd2d_512_forward"]["kernel"] = f"k_stage<2,MHD>, {mhd2d['tile_shape']}"
+        others["mhd2d_512_forward"]["traffic"] = measured_traffic_other("mhd2d_512", mhd2d["tile_shape"])
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -72,3 +72,22 @@ def test_record_is_calibrated_and_consistent():
     # every shape in the per-class autotuning pass of the same run
     for v in rec["variants"].values():
         assert v["bytes_per_stage"] > rec["algorithmic_bytes_per_stage"]
+
+
+def test_other_lists_traffic_is_reported_per_shape():
+    rec = record()
+    if rec["kernel_source_hash"] != bench.kernel_source_hash():
+        pytest.skip("the traffic record predates the current kernel code")
+    assert set(rec["others"]) == set(bench.FORWARD_LEGS)
+    for leg, o in rec["others"].items():
+        kib = 1024.0
+        assert o["copy_probe"]["bytes"] / kib / o["copy_probe"]["fetch_size_kib"] == pytest.approx(o["read_factor"])
+        assert o["copy_probe"]["bytes"] / kib / o["copy_probe"]["write_size_kib"] == pytest.approx(o["write_factor"])
+        for name, v in o["variants"].items():
+            assert bench.measured_traffic_other(leg, name) == v["bytes_per_stage"]
+            # one launch per stage: bytes = calibrated FETCH + WRITE of one dispatch
+            total = v["fetch_size_kib_per_dispatch"] * kib * o["read_factor"] + \
+                v["write_size_kib_per_dispatch"] * kib * o["write_factor"]
+            assert total == pytest.approx(v["bytes_per_stage"], rel=1e-6)
+            assert v["bytes_per_stage"] > 0.9 * v["algorithmic_bytes_per_stage"]
+        assert bench.measured_traffic_other(leg, "no-such-tile-shape") is None
